@@ -1,0 +1,370 @@
+/*
+ * tcol_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded FP64 reference of one iteration of the
+ * population-based gradient-descent colouring method (TensCol) of Goudet,
+ * Duval and Hao, "Population-based Gradient Descent Weight Learning for Graph
+ * Coloring Problems".  It exists so the GPU library can be checked against
+ * something written straight from the paper; only the tests, the smoke check
+ * and the benchmark's CPU-baseline leg may load it.  It shares no code, header
+ * or table with the GPU library.
+ *
+ * Every sum over "j with c_d(j) = l" below is the plain definition of the
+ * product X * S_d for a one-hot S_d, so no dense n x n x k product is formed.
+ *
+ * Conventions (readings of the paper where it is silent or inconsistent):
+ *  - arrays are row-major; W is [D][n][k], A is [n][n] uint8 0/1;
+ *  - argmax ties go to the lowest colour index;
+ *  - c1 = floor(n/k), c2 = ceil(n/k)  (= floor(n/k)+1 unless k divides n);
+ *  - kappa and varpi sum over ordered pairs (i, j), both triangles;
+ *  - the bonus matrix J - A includes the diagonal when bonus_diag = 1;
+ *  - 0^p = 0 for p > 0;
+ *  - the loss and its gradient use the iteration counter t that starts at 0;
+ *  - smoothing W /= rho follows the update of iteration t when
+ *    (t+1) mod nb_iter == 0;
+ *  - an iteration whose population holds a legal member stops before its
+ *    update, and the lowest such member is returned.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t problem;   /* 0 = k-COL (GCP), 1 = equitable colouring (ECP) */
+    int32_t n, k, D;
+    double eta, rho;
+    int32_t nb_iter;
+    double alpha, lambda, beta, mu, nu;
+    int32_t bonus_diag;
+    int32_t stop_on_legal;
+} orc_params;
+
+/* Step 1 (vertex to colour assignment): c_d(i) = argmax_l W[d,i,l].
+ * Returns 0, or -5 if some row holds a non-finite weight. */
+int orc_colors(int D, int n, int k, const double *W, int16_t *c)
+{
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < n; ++i) {
+            const double *w = W + ((size_t)d * n + i) * k;
+            int best = 0;
+            for (int l = 0; l < k; ++l) {
+                if (!isfinite(w[l]))
+                    return -5;
+                if (w[l] > w[best])
+                    best = l;
+            }
+            c[(size_t)d * n + i] = (int16_t)best;
+        }
+    return 0;
+}
+
+/* #V_{d,l}: number of vertices of member d that receive colour l. */
+void orc_class_sizes(int D, int n, int k, const int16_t *c, int32_t *V)
+{
+    memset(V, 0, sizeof(int32_t) * (size_t)D * k);
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < n; ++i)
+            V[(size_t)d * k + c[(size_t)d * n + i]] += 1;
+}
+
+/* Step 2, individual fitness: f_color(S_d) = 1/2 sum_ij a_ij m_dij, i.e. the
+ * number of edges {i, j} whose two ends share a colour in member d. */
+void orc_fcolor(int D, int n, const uint8_t *A, const int16_t *c, int64_t *fcol)
+{
+    for (int d = 0; d < D; ++d) {
+        const int16_t *cd = c + (size_t)d * n;
+        int64_t f = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (A[(size_t)i * n + j] && cd[i] == cd[j])
+                    f += 1;
+        fcol[d] = f;
+    }
+}
+
+/* Bounds of the equity constraint: c1 = floor(n/k); c2 = floor(n/k)+1, equal
+ * to c1 when k divides n. */
+void orc_equity_bounds(int n, int k, int32_t *c1, int32_t *c2)
+{
+    *c1 = n / k;
+    *c2 = (n % k == 0) ? n / k : n / k + 1;
+}
+
+/* Equity fitness: f_eq(S_d) = sum_l min(|#V_dl - c1|, |#V_dl - c2|). */
+void orc_feq(int D, int n, int k, const int32_t *V, int64_t *feq)
+{
+    int32_t c1, c2;
+    orc_equity_bounds(n, k, &c1, &c2);
+    for (int d = 0; d < D; ++d) {
+        int64_t f = 0;
+        for (int l = 0; l < k; ++l) {
+            int64_t v = V[(size_t)d * k + l];
+            int64_t a = llabs(v - c1), b = llabs(v - c2);
+            f += a < b ? a : b;
+        }
+        feq[d] = f;
+    }
+}
+
+/* Group concentration matrix: mt_ij = sum_d m_dij = #{d : c_d(i) = c_d(j)}. */
+void orc_mtilde(int D, int n, const int16_t *c, int32_t *Mt)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            int32_t m = 0;
+            for (int d = 0; d < D; ++d)
+                if (c[(size_t)d * n + i] == c[(size_t)d * n + j])
+                    m += 1;
+            Mt[(size_t)i * n + j] = m;
+        }
+}
+
+/* x^p with the convention 0^p = 0 (p > 0). */
+static double pow0(double x, double p)
+{
+    return x == 0.0 ? 0.0 : pow(x, p);
+}
+
+/* Derivative of the equity fitness with respect to s_{d,i,l}: +1 if the class
+ * is above c2, -1 if below c1, 0 otherwise. */
+static double dfeq(int32_t v, int32_t c1, int32_t c2)
+{
+    if (v > c2)
+        return 1.0;
+    if (v < c1)
+        return -1.0;
+    return 0.0;
+}
+
+/* Gradient of the global loss with respect to the one-hot tensor S:
+ *   gS = A.S + nu t grad f_eq + 2 alpha lambda t (A o Mt^(alpha-1)).S
+ *        - 2 beta mu t ((J - A) o Mt^(beta-1)).S
+ * evaluated at the hard assignment of step 1.  The two element-wise powered
+ * n x n matrices are formed once, then each product with S_d is the sum over
+ * the vertices j that member d colours l.  gS is [D][n][k]. */
+void orc_grad_s(const orc_params *p, int64_t t, const uint8_t *A, const int16_t *c,
+                const int32_t *Mt, const int32_t *V, double *gS)
+{
+    const int n = p->n, k = p->k, D = p->D;
+    const double tt = (double)t;
+    const double cpen = 2.0 * p->alpha * p->lambda * tt;
+    const double cbon = 2.0 * p->beta * p->mu * tt;
+    const double ceq = p->nu * tt;
+    int32_t c1, c2;
+    orc_equity_bounds(n, k, &c1, &c2);
+    /* P = A o Mt^(alpha-1), Q = (J - A) o Mt^(beta-1) */
+    double *P = (double *)calloc((size_t)n * n, sizeof(double));
+    double *Q = (double *)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const size_t e = (size_t)i * n + j;
+            const double m = (double)Mt[e];
+            if (A[e])
+                P[e] = pow0(m, p->alpha - 1.0);
+            else if (j != i || p->bonus_diag)
+                Q[e] = pow0(m, p->beta - 1.0);
+        }
+    memset(gS, 0, sizeof(double) * (size_t)D * n * k);
+    for (int d = 0; d < D; ++d) {
+        const int16_t *cd = c + (size_t)d * n;
+        for (int i = 0; i < n; ++i) {
+            double *g = gS + ((size_t)d * n + i) * k;
+            const uint8_t *Ai = A + (size_t)i * n;
+            const double *Pi = P + (size_t)i * n;
+            const double *Qi = Q + (size_t)i * n;
+            for (int j = 0; j < n; ++j) {
+                const int l = cd[j];
+                g[l] += (double)Ai[j];          /* gamma matrix term */
+                g[l] += cpen * Pi[j];           /* shared-conflict penalisation */
+                g[l] -= cbon * Qi[j];           /* shared-assignment bonus */
+            }
+            if (p->problem == 1)
+                for (int l = 0; l < k; ++l)
+                    g[l] += ceq * dfeq(V[(size_t)d * k + l], c1, c2);
+        }
+    }
+    free(P);
+    free(Q);
+}
+
+/* Straight-through softmax gradient:
+ *   s_hat = softmax(w) along the colour axis (max subtracted),
+ *   gW_j = s_hat_j gS_j - s_hat_j sum_l s_hat_l gS_l. */
+void orc_grad_w(int D, int n, int k, const double *W, const double *gS, double *gW)
+{
+    double *sh = (double *)malloc(sizeof(double) * (size_t)k);
+    for (size_t r = 0; r < (size_t)D * n; ++r) {
+        const double *w = W + r * k;
+        const double *g = gS + r * k;
+        double *o = gW + r * k;
+        double mx = w[0];
+        for (int l = 1; l < k; ++l)
+            if (w[l] > mx)
+                mx = w[l];
+        double z = 0.0;
+        for (int l = 0; l < k; ++l) {
+            sh[l] = exp(w[l] - mx);
+            z += sh[l];
+        }
+        double rs = 0.0;
+        for (int l = 0; l < k; ++l) {
+            sh[l] /= z;
+            rs += sh[l] * g[l];
+        }
+        for (int l = 0; l < k; ++l)
+            o[l] = sh[l] * g[l] - sh[l] * rs;
+    }
+    free(sh);
+}
+
+/* Step 4 iii-iv: W <- W - eta gW, then W <- W / rho after the update of
+ * iteration t when (t+1) mod nb_iter == 0. */
+void orc_update(const orc_params *p, int64_t t, double *W, const double *gW)
+{
+    const size_t cnt = (size_t)p->D * p->n * p->k;
+    const int smooth = p->nb_iter > 0 && ((t + 1) % p->nb_iter) == 0;
+    for (size_t e = 0; e < cnt; ++e) {
+        double w = W[e] - p->eta * gW[e];
+        if (smooth)
+            w = w / p->rho;
+        W[e] = w;
+    }
+}
+
+/* Global loss L(t) = f_color + nu t f_eq + lambda t kappa - mu t varpi with
+ * kappa = sum_ij a_ij mt_ij^alpha and varpi = sum_ij (1 - a_ij) mt_ij^beta.
+ * out = {L, sum f_color, sum f_eq, kappa, varpi}. */
+void orc_loss(const orc_params *p, int64_t t, const uint8_t *A, const int32_t *Mt,
+              const int64_t *fcol, const int64_t *feq, double *out)
+{
+    const int n = p->n, D = p->D;
+    double sf = 0.0, se = 0.0, kappa = 0.0, varpi = 0.0;
+    for (int d = 0; d < D; ++d) {
+        sf += (double)fcol[d];
+        se += (double)feq[d];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const double m = (double)Mt[(size_t)i * n + j];
+            if (A[(size_t)i * n + j])
+                kappa += pow0(m, p->alpha);
+            else if (j != i || p->bonus_diag)
+                varpi += pow0(m, p->beta);
+        }
+    const double tt = (double)t;
+    const double eq = p->problem == 1 ? se : 0.0;
+    out[0] = sf + p->nu * tt * eq + p->lambda * tt * kappa - p->mu * tt * varpi;
+    out[1] = sf;
+    out[2] = eq;
+    out[3] = kappa;
+    out[4] = varpi;
+}
+
+/* Work arrays for one iteration. */
+typedef struct {
+    int16_t *c;
+    int32_t *V, *Mt;
+    int64_t *fcol, *feq;
+    double *gS, *gW;
+} orc_work;
+
+static int work_alloc(const orc_params *p, orc_work *w)
+{
+    const size_t D = p->D, n = p->n, k = p->k;
+    w->c = (int16_t *)malloc(sizeof(int16_t) * D * n);
+    w->V = (int32_t *)malloc(sizeof(int32_t) * D * k);
+    w->Mt = (int32_t *)malloc(sizeof(int32_t) * n * n);
+    w->fcol = (int64_t *)malloc(sizeof(int64_t) * D);
+    w->feq = (int64_t *)malloc(sizeof(int64_t) * D);
+    w->gS = (double *)malloc(sizeof(double) * D * n * k);
+    w->gW = (double *)malloc(sizeof(double) * D * n * k);
+    return (w->c && w->V && w->Mt && w->fcol && w->feq && w->gS && w->gW) ? 0 : -6;
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->c); free(w->V); free(w->Mt); free(w->fcol); free(w->feq);
+    free(w->gS); free(w->gW);
+}
+
+/* One iteration of the algorithm on member weights W (updated in place).
+ * Outputs (any may be NULL): colours c [D*n], fitness f = f_color + f_eq [D],
+ * f_color [D], f_eq [D], the gradients gS and gW [D*n*k] of this iteration.
+ * Returns 1 if the population held a legal member (no update; *legal_d set to
+ * the lowest such member when stop_on_legal), 0 after an update, or a
+ * negative error (-5 non-finite weight, -6 out of memory). */
+int orc_iteration(const orc_params *p, int64_t *t, const uint8_t *A, double *W,
+                  int16_t *c_out, int64_t *f_out, int64_t *fcol_out, int64_t *feq_out,
+                  double *gS_out, double *gW_out, int32_t *legal_d)
+{
+    const int n = p->n, k = p->k, D = p->D;
+    orc_work w;
+    if (work_alloc(p, &w)) {
+        work_free(&w);
+        return -6;
+    }
+    int rc = orc_colors(D, n, k, W, w.c);
+    if (rc) {
+        work_free(&w);
+        return rc;
+    }
+    orc_class_sizes(D, n, k, w.c, w.V);
+    orc_fcolor(D, n, A, w.c, w.fcol);
+    if (p->problem == 1)
+        orc_feq(D, n, k, w.V, w.feq);
+    else
+        memset(w.feq, 0, sizeof(int64_t) * D);
+    int best = -1;
+    for (int d = 0; d < D; ++d) {
+        const int64_t f = w.fcol[d] + w.feq[d];
+        if (f_out) f_out[d] = f;
+        if (f == 0 && best < 0) best = d;
+    }
+    if (c_out) memcpy(c_out, w.c, sizeof(int16_t) * (size_t)D * n);
+    if (fcol_out) memcpy(fcol_out, w.fcol, sizeof(int64_t) * D);
+    if (feq_out) memcpy(feq_out, w.feq, sizeof(int64_t) * D);
+    if (legal_d) *legal_d = best;
+    if (best >= 0 && p->stop_on_legal) {
+        work_free(&w);
+        return 1;
+    }
+    orc_mtilde(D, n, w.c, w.Mt);
+    orc_grad_s(p, *t, A, w.c, w.Mt, w.V, w.gS);
+    orc_grad_w(D, n, k, W, w.gS, w.gW);
+    if (gS_out) memcpy(gS_out, w.gS, sizeof(double) * (size_t)D * n * k);
+    if (gW_out) memcpy(gW_out, w.gW, sizeof(double) * (size_t)D * n * k);
+    orc_update(p, *t, W, w.gW);
+    *t += 1;
+    work_free(&w);
+    return 0;
+}
+
+/* Algorithm loop: up to max_steps iterations.  Returns the number of updates
+ * performed; *legal_d is the returned member (or -1) and colors_out [n] its
+ * colouring when one was found. */
+int orc_run(const orc_params *p, int64_t *t, const uint8_t *A, double *W, int max_steps,
+            int32_t *legal_d, int16_t *colors_out)
+{
+    const int n = p->n, D = p->D;
+    int16_t *c = (int16_t *)malloc(sizeof(int16_t) * (size_t)D * n);
+    int done = 0;
+    *legal_d = -1;
+    for (int s = 0; s < max_steps; ++s) {
+        int32_t ld = -1;
+        int rc = orc_iteration(p, t, A, W, c, NULL, NULL, NULL, NULL, NULL, &ld);
+        if (rc < 0) {
+            free(c);
+            return rc;
+        }
+        if (rc == 1) {
+            *legal_d = ld;
+            if (colors_out)
+                memcpy(colors_out, c + (size_t)ld * n, sizeof(int16_t) * n);
+            break;
+        }
+        done += 1;
+    }
+    free(c);
+    return done;
+}

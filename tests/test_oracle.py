@@ -1,0 +1,431 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each test checks it against a
+value the paper prints, a closed form, a second formulation (the literal
+tensor transcription, brute force over edges or colourings), an invariance
+the paper states, or finite differences.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import literal
+import tcolgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def onehot(c, k):
+    c = np.asarray(c)
+    D, n = c.shape
+    S = np.zeros((D, n, k))
+    for d in range(D):
+        S[d, np.arange(n), c[d]] = 1.0
+    return S
+
+
+def adj_from_edges(n, edges):
+    A = np.zeros((n, n), np.uint8)
+    for i, j in edges:
+        A[i, j] = A[j, i] = 1
+    return A
+
+
+def rand_params(problem, n, k, D, **kw):
+    d = dict(problem=problem, n=n, k=k, D=D, eta=1e-3, rho=10.0, nb_iter=5, alpha=2.5,
+             lam=1e-2, beta=1.2, mu=3e-3, nu=0.05, bonus_diag=1, stop_on_legal=1)
+    d.update(kw)
+    return oracle.Params(**d)
+
+
+def colour_weights(c, k, rng, scale=1.0):
+    """Weights whose argmax is the colouring c (other entries strictly smaller)."""
+    c = np.asarray(c)
+    D, n = c.shape
+    W = rng.uniform(-1.0, 0.0, size=(D, n, k))
+    for d in range(D):
+        W[d, np.arange(n), c[d]] = 1.0 + rng.uniform(0, 1, size=n)
+    return W * scale
+
+
+# ---------------------------------------------------------------- step 1 -----
+
+def test_argmax_ties_lowest_and_nonfinite():
+    W = np.zeros((2, 3, 4))
+    W[0, 0] = [1, 3, 3, 2]      # tie between colours 1 and 2 -> 1
+    W[0, 1] = [5, 5, 5, 5]      # all equal -> 0
+    W[0, 2] = [-1, -2, -1, 0.5]
+    W[1, 0] = [0, 0, 0, 1e-30]
+    W[1, 1] = [-0.0, 0.0, -1, -1]  # -0 == +0 -> 0
+    W[1, 2] = [2, 1, 2, 1]
+    c = oracle.colors(W)
+    assert c.tolist() == [[1, 0, 3], [3, 0, 0]]
+    W[1, 2, 3] = np.nan
+    with pytest.raises(FloatingPointError):
+        oracle.colors(W)
+    W[1, 2, 3] = np.inf
+    with pytest.raises(FloatingPointError):
+        oracle.colors(W)
+
+
+def test_argmax_matches_literal_one_hot():
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((3, 17, 6))
+    c = oracle.colors(W)
+    S = literal.one_hot_argmax(W)
+    assert np.array_equal(onehot(c, 6), S)
+
+
+# ---------------------------------------------------------------- step 2 -----
+
+@pytest.mark.parametrize("n,k,seed", [(4, 3, 0), (5, 3, 1), (6, 2, 2), (6, 3, 3)])
+def test_fcolor_exhaustive_all_colourings(n, k, seed):
+    """Every one of the k^n colourings: the oracle's edge count equals the paper's
+    1/2 sum(A o S S') (literal) and a brute force written here over the edge list."""
+    A = tcolgen.gnp(n, 0.6, seed)
+    cols = np.array(list(itertools.product(range(k), repeat=n)), dtype=np.int16)
+    f = oracle.fcolor(A, cols)
+    f_lit = literal.fitness_color(A.astype(float), onehot(cols, k))
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if A[i, j]]
+    f_bf = np.array([sum(1 for i, j in edges if c[i] == c[j]) for c in cols])
+    assert np.array_equal(f, f_bf)
+    assert np.array_equal(f, f_lit.astype(np.int64))
+    # a legal colouring exists iff min f == 0; chromatic number by exhaustion
+    assert (f.min() == 0) == any(all(c[i] != c[j] for i, j in edges) for c in cols)
+
+
+def test_fcolor_complete_graph_one_colour():
+    for n in (1, 2, 7, 12):
+        A = np.ones((n, n), np.uint8) - np.eye(n, dtype=np.uint8)
+        c = np.zeros((1, n), np.int16)
+        assert oracle.fcolor(A, c)[0] == n * (n - 1) // 2
+
+
+def test_fitness_zero_on_planted_colouring():
+    P = tcolgen.planted(200, 9, seed=11)
+    c = P.classes[None, :]
+    assert oracle.fcolor(P.A, c)[0] == 0
+    V = oracle.class_sizes(c, 9)
+    assert oracle.feq(V, 200)[0] == 0
+    # and a perturbed colouring has conflicts
+    c2 = c.copy()
+    i = int(np.nonzero(P.A[0])[0][0])
+    c2[0, i] = c2[0, 0]
+    assert oracle.fcolor(P.A, c2)[0] >= 1
+
+
+def test_feq_closed_forms():
+    # n=10, k=3, all vertices in one class: c1=3, c2=4 -> (10-4) + 2*3 = 12
+    assert oracle.equity_bounds(10, 3) == (3, 4)
+    V = np.array([[10, 0, 0]], np.int32)
+    assert oracle.feq(V, 10)[0] == 12
+    # k divides n: c1 = c2 = n/k
+    assert oracle.equity_bounds(12, 3) == (4, 4)
+    assert oracle.feq(np.array([[12, 0, 0]], np.int32), 12)[0] == 8 + 4 + 4
+    assert oracle.feq(np.array([[4, 4, 4]], np.int32), 12)[0] == 0
+    # general: equals sum_l max(0, c1 - V) + max(0, V - c2) for integer V
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        n = int(rng.integers(1, 60)); k = int(rng.integers(1, 12))
+        c = rng.integers(0, k, size=(4, n)).astype(np.int16)
+        V = oracle.class_sizes(c, k)
+        c1, c2 = n // k, -(-n // k)
+        want = (np.maximum(0, c1 - V) + np.maximum(0, V - c2)).sum(axis=1)
+        assert np.array_equal(oracle.feq(V, n), want)
+        assert np.array_equal(oracle.feq(V, n), literal.equity_fitness(onehot(c, k)).astype(np.int64))
+        # zero iff class sizes differ by at most one
+        eqt = (V.max(axis=1) - V.min(axis=1)) <= 1
+        assert np.array_equal(oracle.feq(V, n) == 0, eqt)
+
+
+# ---------------------------------------------------------------- step 3 -----
+
+def test_kappa_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "kappa_worked_example.json")))
+    A = adj_from_edges(g["n"], g["edges"])
+    for case in g["cases"]:
+        c = np.array(case["colors"], np.int16)
+        assert oracle.fcolor(A, c).tolist() == case["conflicts_per_member"]
+        Mt = oracle.mtilde(c)
+        p = oracle.Params(problem=0, n=g["n"], k=g["k"], D=c.shape[0], alpha=g["alpha"], lam=1.0,
+                          beta=1.5, mu=0.0)
+        out = oracle.loss(p, 1, A, Mt, oracle.fcolor(A, c), np.zeros(c.shape[0], np.int64))
+        assert out[3] == case["kappa"]
+        assert literal.kappa(A.astype(float), onehot(c, g["k"]), g["alpha"]) == case["kappa"]
+
+
+def test_mtilde_properties():
+    rng = np.random.default_rng(7)
+    D, n, k = 6, 40, 5
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    Mt = oracle.mtilde(c)
+    assert np.array_equal(Mt, Mt.T)
+    assert np.all(np.diag(Mt) == D)
+    V = oracle.class_sizes(c, k)
+    assert Mt.sum() == int((V.astype(np.int64) ** 2).sum())
+    assert np.array_equal(Mt, literal.group_concentration(onehot(c, k)).astype(np.int32))
+    # D = 1: Mt is the association matrix of the single member
+    M1 = oracle.mtilde(c[:1])
+    assert np.array_equal(M1, (c[0][:, None] == c[0][None, :]).astype(np.int32))
+
+
+def test_kappa_varpi_single_member_identities():
+    """D=1: kappa = 2 f_color; varpi = sum_l V_l^2 - 2 f_color (diagonal included), n less without."""
+    rng = np.random.default_rng(1)
+    for trial in range(10):
+        n, k = int(rng.integers(5, 40)), int(rng.integers(2, 7))
+        A = tcolgen.gnp(n, 0.4, 100 + trial)
+        c = rng.integers(0, k, size=(1, n)).astype(np.int16)
+        f = oracle.fcolor(A, c)
+        V = oracle.class_sizes(c, k)
+        Mt = oracle.mtilde(c)
+        for diag in (1, 0):
+            p = oracle.Params(problem=0, n=n, k=k, D=1, alpha=2.5, beta=1.2, lam=1, mu=1,
+                              bonus_diag=diag)
+            out = oracle.loss(p, 0, A, Mt, f, np.zeros(1, np.int64))
+            assert out[3] == pytest.approx(2 * f[0], abs=1e-12)
+            want = float((V.astype(float) ** 2).sum() - 2 * f[0] - (0 if diag else n))
+            assert out[4] == pytest.approx(want, abs=1e-12)
+
+
+def test_identical_copies_scale():
+    """D identical members: Mt = D M, kappa = D^alpha 2f, varpi = D^beta (sum V^2 - 2f)."""
+    rng = np.random.default_rng(2)
+    n, k, D = 30, 4, 5
+    A = tcolgen.gnp(n, 0.5, 9)
+    c1 = rng.integers(0, k, size=(1, n)).astype(np.int16)
+    c = np.repeat(c1, D, axis=0)
+    Mt = oracle.mtilde(c)
+    assert np.array_equal(Mt, D * oracle.mtilde(c1))
+    f = oracle.fcolor(A, c)
+    V = oracle.class_sizes(c1, k)
+    p = oracle.Params(problem=0, n=n, k=k, D=D, alpha=2.5, beta=1.2)
+    out = oracle.loss(p, 0, A, Mt, f, np.zeros(D, np.int64))
+    assert out[3] == pytest.approx(D ** 2.5 * 2 * f[0], rel=1e-13)
+    assert out[4] == pytest.approx(D ** 1.2 * ((V.astype(float) ** 2).sum() - 2 * f[0]), rel=1e-13)
+
+
+def test_gamma_matrix_term():
+    """At t = 0 the gradient is A.S: entry (d,i,l) counts the neighbours of i coloured l
+    (the TabuCol gamma matrix); sum_i gS[d,i,c_d(i)] = 2 f_color(S_d)."""
+    rng = np.random.default_rng(4)
+    D, n, k = 3, 35, 6
+    A = tcolgen.gnp(n, 0.3, 21)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    V = oracle.class_sizes(c, k)
+    p = rand_params(1, n, k, D)
+    gS = oracle.grad_s(p, 0, A, c, oracle.mtilde(c), V)
+    gamma = np.zeros((D, n, k))
+    for d in range(D):
+        for i in range(n):
+            for j in np.nonzero(A[i])[0]:
+                gamma[d, i, c[d, j]] += 1
+    assert np.array_equal(gS, gamma)
+    f = oracle.fcolor(A, c)
+    for d in range(D):
+        assert gS[d, np.arange(n), c[d]].sum() == 2 * f[d]
+
+
+@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0), (1, 0)])
+def test_grad_s_matches_literal(problem, diag):
+    rng = np.random.default_rng(10 + problem + 2 * diag)
+    D, n, k = 4, 23, 5
+    A = tcolgen.gnp(n, 0.5, 31)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    p = rand_params(problem, n, k, D, bonus_diag=diag)
+    t = 7
+    gS = oracle.grad_s(p, t, A, c, oracle.mtilde(c), oracle.class_sizes(c, k))
+    lit = literal.grad_s(A.astype(float), onehot(c, k), t, p.alpha, p.lam, p.beta, p.mu, p.nu,
+                         problem, diag)
+    np.testing.assert_allclose(gS, lit, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0)])
+def test_grad_s_finite_differences(problem, diag):
+    """Central differences (h = 1e-3) of the paper's loss, as a polynomial in S, at the hard S."""
+    rng = np.random.default_rng(20 + problem)
+    D, n, k = 3, 14, 4
+    A = tcolgen.gnp(n, 0.5, 41)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    p = rand_params(problem, n, k, D, bonus_diag=diag)
+    t = 5
+    gS = oracle.grad_s(p, t, A, c, oracle.mtilde(c), oracle.class_sizes(c, k))
+    S = onehot(c, k)
+    Af = A.astype(float)
+    h = 1e-3
+
+    def L(Sx):
+        return literal.global_loss(Af, Sx, t, p.alpha, p.lam, p.beta, p.mu, p.nu, problem, diag)
+
+    for (d, i, l) in tcolgen.fd_entries(32, D, n, k, seed=3):
+        Sp = S.copy(); Sp[d, i, l] += h
+        Sm = S.copy(); Sm[d, i, l] -= h
+        fd = (L(Sp) - L(Sm)) / (2 * h)
+        assert fd == pytest.approx(gS[d, i, l], rel=1e-4, abs=1e-6), (d, i, l)
+
+
+# ---------------------------------------------------------------- step 4 -----
+
+def test_grad_w_finite_differences_of_surrogate():
+    """The straight-through gradient is the exact gradient of Phi(w) = sum_l G_l softmax(w)_l
+    with G frozen; check by central differences, plus zero row sums and the constant-G case."""
+    rng = np.random.default_rng(8)
+    D, n, k = 2, 5, 7
+    W = rng.standard_normal((D, n, k)) * 0.7
+    G = rng.standard_normal((D, n, k)) * 3
+    gW = oracle.grad_w(W, G)
+    np.testing.assert_allclose(gW, literal.grad_w(W, G), rtol=1e-12, atol=1e-14)
+    assert np.abs(gW.sum(axis=2)).max() < 1e-13
+    h = 1e-3
+    for d in range(D):
+        for i in range(n):
+            for j in range(k):
+                def phi(w):
+                    e = np.exp(w - w.max())
+                    return float((G[d, i] * e / e.sum()).sum())
+                wp = W[d, i].copy(); wp[j] += h
+                wm = W[d, i].copy(); wm[j] -= h
+                fd = (phi(wp) - phi(wm)) / (2 * h)
+                assert fd == pytest.approx(gW[d, i, j], rel=1e-4, abs=1e-7)
+    Gc = np.broadcast_to(rng.standard_normal((D, n, 1)), (D, n, k)).copy()
+    assert np.abs(oracle.grad_w(W, Gc)).max() < 1e-14
+
+
+def test_grad_w_large_weights_stable():
+    W = np.array([[[1000.0, 999.0, -1000.0]]])
+    G = np.array([[[1.0, 2.0, 3.0]]])
+    gW = oracle.grad_w(W, G)
+    assert np.all(np.isfinite(gW))
+    np.testing.assert_allclose(gW, literal.grad_w(W, G), rtol=1e-12, atol=1e-300)
+
+
+def test_update_and_smoothing_schedule():
+    p = oracle.Params(problem=0, n=2, k=3, D=1, eta=0.1, rho=4.0, nb_iter=5)
+    W = np.arange(6, dtype=float).reshape(1, 2, 3)
+    gW = np.ones_like(W)
+    assert np.allclose(oracle.update(p, 0, W, gW), W - 0.1)
+    assert np.allclose(oracle.update(p, 3, W, gW), W - 0.1)
+    assert np.allclose(oracle.update(p, 4, W, gW), (W - 0.1) / 4.0)   # (t+1) mod 5 == 0
+    assert np.allclose(oracle.update(p, 9, W, gW), (W - 0.1) / 4.0)
+
+
+def test_loss_matches_literal():
+    rng = np.random.default_rng(12)
+    for problem in (0, 1):
+        D, n, k = 4, 20, 4
+        A = tcolgen.gnp(n, 0.5, 51)
+        c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+        p = rand_params(problem, n, k, D)
+        Mt = oracle.mtilde(c)
+        fc = oracle.fcolor(A, c)
+        fe = oracle.feq(oracle.class_sizes(c, k), n)
+        out = oracle.loss(p, 6, A, Mt, fc, fe)
+        lit = literal.global_loss(A.astype(float), onehot(c, k), 6, p.alpha, p.lam, p.beta, p.mu,
+                                  p.nu, problem)
+        assert out[0] == pytest.approx(lit, rel=1e-12)
+
+
+# ---------------------------------------------------------------- invariances --
+
+def test_invariances():
+    """Colour permutation within a member, population order and vertex relabelling
+    leave fitness and the group concentration matrix unchanged (permuted accordingly)."""
+    rng = np.random.default_rng(13)
+    D, n, k = 4, 25, 5
+    A = tcolgen.gnp(n, 0.5, 61)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    p = rand_params(1, n, k, D)
+    t = 3
+    f = oracle.fcolor(A, c)
+    Mt = oracle.mtilde(c)
+    gS = oracle.grad_s(p, t, A, c, Mt, oracle.class_sizes(c, k))
+    # colours of member 1 permuted
+    perm = rng.permutation(k)
+    c2 = c.copy(); c2[1] = perm[c[1]]
+    assert np.array_equal(oracle.fcolor(A, c2), f)
+    assert np.array_equal(oracle.mtilde(c2), Mt)
+    gS2 = oracle.grad_s(p, t, A, c2, oracle.mtilde(c2), oracle.class_sizes(c2, k))
+    np.testing.assert_allclose(gS2[1][:, perm], gS[1], rtol=1e-13, atol=1e-13)
+    # population order
+    q = rng.permutation(D)
+    assert np.array_equal(oracle.fcolor(A, c[q]), f[q])
+    assert np.array_equal(oracle.mtilde(c[q]), Mt)
+    # vertex relabelling P A P^T
+    v = rng.permutation(n)
+    Ap = A[np.ix_(v, v)]
+    cp = c[:, v]
+    assert np.array_equal(oracle.fcolor(Ap, cp), f)
+    assert np.array_equal(oracle.mtilde(cp), Mt[np.ix_(v, v)])
+    gSp = oracle.grad_s(p, t, Ap, cp, oracle.mtilde(cp), oracle.class_sizes(cp, k))
+    np.testing.assert_allclose(gSp, gS[:, v, :], rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- iteration ----
+
+def test_iteration_composes_steps_and_matches_literal():
+    rng = np.random.default_rng(14)
+    for problem in (0, 1):
+        D, n, k = 3, 18, 4
+        A = tcolgen.gnp(n, 0.5, 71)
+        W = rng.standard_normal((D, n, k)) * 0.01
+        p = rand_params(problem, n, k, D)
+        for t in (0, 4):      # t=4: (t+1) mod 5 == 0, smoothing applies
+            r = oracle.iteration(p, t, A, W)
+            assert r.status == 0 and r.t == t + 1
+            S = literal.one_hot_argmax(W)
+            gS = literal.grad_s(A.astype(float), S, t, p.alpha, p.lam, p.beta, p.mu, p.nu, problem)
+            gW = literal.grad_w(W, gS)
+            W1 = W - p.eta * gW
+            if (t + 1) % p.nb_iter == 0:
+                W1 = W1 / p.rho
+            np.testing.assert_allclose(r.gS, gS, rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(r.gW, gW, rtol=1e-10, atol=1e-15)
+            np.testing.assert_allclose(r.W, W1, rtol=1e-13, atol=1e-17)
+
+
+def test_planted_population_stops_before_update():
+    P = tcolgen.planted(120, 6, seed=5)
+    rng = np.random.default_rng(15)
+    D, n, k = 4, 120, 6
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    c[2] = P.classes       # member 2 holds the hidden legal colouring
+    c[3] = P.classes
+    W = colour_weights(c, k, rng, scale=0.01)
+    p = rand_params(1, n, k, D)
+    r = oracle.iteration(p, 3, P.A, W)
+    assert r.status == 1 and r.legal_d == 2 and r.t == 3
+    np.testing.assert_array_equal(r.W, W)
+    Wf, t, done, ld, col = oracle.run(p, 3, P.A, W, 10)
+    assert done == 0 and ld == 2 and np.array_equal(col, P.classes)
+
+
+def test_run_matches_repeated_iterations():
+    rng = np.random.default_rng(16)
+    D, n, k = 3, 20, 5
+    A = tcolgen.gnp(n, 0.5, 81)
+    W = rng.standard_normal((D, n, k)) * 0.01
+    p = rand_params(0, n, k, D, stop_on_legal=0)
+    Wr, t, done, ld, _ = oracle.run(p, 0, A, W, 12)
+    Wi, ti = W, 0
+    for _ in range(12):
+        r = oracle.iteration(p, ti, A, Wi, want_grads=False)
+        Wi, ti = r.W, r.t
+    assert done == 12 and t == 12 and ti == 12
+    np.testing.assert_array_equal(Wr, Wi)
+
+
+def test_mycielski_toy_reaches_legal():
+    """The paper's toy setting (D=1, lambda=mu=0, eta=1e-3, nb_iter=5, rho=200, seed 0) on a
+    synthetic Mycielski graph with chi=5 finds a legal 5-colouring."""
+    A = tcolgen.mycielski(5)
+    n = A.shape[0]
+    W = tcolgen.weights0(1, n, 5, seed=0)
+    p = oracle.Params(problem=0, n=n, k=5, D=1, eta=1e-3, rho=200.0, nb_iter=5, lam=0.0, mu=0.0)
+    Wf, t, done, ld, col = oracle.run(p, 0, A, W, 20000)
+    assert ld == 0
+    assert oracle.fcolor(A, col[None, :])[0] == 0
