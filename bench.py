@@ -1,0 +1,183 @@
+"""Throughput of the TensCol population step on one MI355X.
+
+One step = one iteration of the method (argmax colouring, fitness through A.S,
+group concentration and penalty operand, the contraction for the loss
+gradient, softmax straight-through update and smoothing) over the whole
+population, on synthetic inputs already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5] [--precision fp8]
+
+Prints one JSON line: population-iterations/s (D * steps / s), the roofline of
+the dominant kernel (the MFMA contraction), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+import tcolgen
+
+PEAK = {"fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
+HBM_PEAK = 8.0e12
+PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8}
+
+
+def workload(name: str, prec: str):
+    p = PREC[prec]
+    table = {
+        "c1": lambda: tcolgen.case_c1(),
+        "c2": lambda: tcolgen.case_c2(p),
+        "c3": lambda: tcolgen.case_c3(p),
+        "c4": lambda: tcolgen.case_c4(p),
+        "c5": lambda: tcolgen.case_c5(p),
+    }
+    c = table[name]()
+    c.precision = p
+    c.stop_on_legal = 0
+    return c
+
+
+def gemm_flops(case, t: int):
+    """Algorithmic flops of one contraction launch: 2 n^2 D k for A.S plus the same for the
+    penalty product when lambda t or mu t is non-zero (real n and k, not padded)."""
+    base = 2.0 * case.n * case.n * case.D * case.k
+    pen = (case.lam * t != 0.0) or (case.mu * t != 0.0)
+    return base, (base if pen else 0.0)
+
+
+def mixed_peak(prec: str, f_as: float, f_pen: float) -> float:
+    """Peak of a launch whose A.S pass runs at the operand dtype and whose penalty pass runs
+    in bf16 (fp8 precision) or the operand dtype: total flops over the ideal time."""
+    p_as = PEAK[prec]
+    p_pen = PEAK["bf16"] if prec == "fp8" else PEAK[prec]
+    ideal = f_as / p_as + f_pen / p_pen
+    return (f_as + f_pen) / ideal
+
+
+def cpu_baseline(case, A, W0, budget_s: float):
+    import oracle
+    p = oracle.Params.from_dict(case.params())
+    W = W0.astype(np.float64)
+    t = 0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.iteration(p, t, A, W, want_grads=False)
+        W, t = r.W, r.t
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    return {"value": case.D * steps / el, "unit": "population-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} iterations of the same workload from the same W0 (single-threaded FP64 C "
+                      f"oracle, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--precision", default=None, choices=list(PREC))
+    ap.add_argument("--path", default="separate", choices=["separate", "fused"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--tile-bm", type=int, default=0)
+    ap.add_argument("--tile-ntw", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the population step on a single MI355X "
+              "(the population would shard over GPUs by members; see DESIGN.md). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1909_02261_amd as pk
+
+    prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp8", "c4": "bf16", "c5": "fp8"}[args.workload]
+    case = workload(args.workload, prec)
+    print(f"[bench] workload {case.name} precision {prec}: generating inputs", file=sys.stderr, flush=True)
+    A = case.adjacency()
+    W0 = case.weights()
+    dev = torch.device("cuda:0")
+    Wt = torch.from_numpy(W0).to(dev)
+    At = torch.from_numpy(A).to(dev)
+    s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
+    s.set_options(use_graph=0 if args.no_graph else 1, fused=1 if args.path == "fused" else 0,
+                  tile_bm=args.tile_bm, tile_ntw=args.tile_ntw)
+    opts = s.options()
+    print(f"[bench] options {opts}; warmup {args.warmup}", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    done, _ = s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert done == args.steps
+    value = case.D * args.steps / (ms / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel durations (HIP events around each launch on the same stream)
+    ph = s.profile(args.profile_steps, as_only=True)
+    t_now = s.get_t()
+    f_as, f_pen = gemm_flops(case, t_now)
+    gemm_s = ph["gemm"] / 1e3
+    achieved = (f_as + f_pen) / gemm_s
+    peak = mixed_peak(prec, f_as, f_pen)
+    as_s = ph["gemm_as_only"] / 1e3
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "k_gemm (A.S pass + penalty pass + fitness gather)",
+            "flops_per_launch": f_as + f_pen, "ms_per_launch": ph["gemm"]}
+    roof_as = {"bound": "mfma", "achieved": f_as / as_s / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+               "frac": f_as / as_s / PEAK[prec], "ms_per_launch": ph["gemm_as_only"]}
+    print(f"[bench] phases ms {json.dumps({k: round(v, 4) for k, v in ph.items()})}", file=sys.stderr, flush=True)
+    s.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] oracle baseline ({args.cpu_seconds:.0f} s budget)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(case, A, W0, args.cpu_seconds)
+
+    out = {
+        "metric": "population-iterations/s (D*steps/s)",
+        "value": value,
+        "unit": "population-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic (seeded Philox G(n,p) graph and N(0, 0.01^2) weights)",
+        "config": {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
+                   "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
+                   "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"]},
+        "roofline": roof,
+        "roofline_as_only": roof_as,
+        "phases_ms": ph,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

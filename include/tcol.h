@@ -1,0 +1,200 @@
+/*
+ * tcol.h -- C ABI of the MI355X (gfx950) population step of TensCol.
+ *
+ * The method (Goudet, Duval, Hao: "Population-based Gradient Descent Weight
+ * Learning for Graph Coloring Problems") keeps D weight tensors W_d (n x k)
+ * per graph.  One iteration (Section 2, Algorithm 1, steps 1-4):
+ *   1. S = one_hot(argmax(W)) along the colour axis;
+ *   2. fitness f_color(S_d) = 1/2 sum(A o S_d S_d^T)   (eq. individual fitness),
+ *      plus the equity fitness f_eq for the ECP           (eq. equity fitness);
+ *   3. group concentration Mt = sum_d S_d S_d^T           (eq. tildeM) and the
+ *      gradient of the global loss                        (eq. global loss gradient)
+ *        gS = A.S + nu t grad f_eq + 2 alpha lambda t (A o Mt^(alpha-1)).S
+ *             - 2 beta mu t ((J - A) o Mt^(beta-1)).S;
+ *   4. straight-through softmax gradient gW = S^ o (gS - (S^ o gS).J)
+ *      (eq. tensor gradient), W <- W - eta gW, and W <- W / rho every nb_iter
+ *      iterations (eq. smoothing).
+ * The loop stops when some member is legal (f = 0, Section 2 general scheme).
+ *
+ * Conventions fixed by this library where the paper leaves a choice:
+ *  - argmax ties go to the lowest colour;
+ *  - c1 = floor(n/k), c2 = ceil(n/k) in the equity fitness;
+ *  - an iteration that finds a legal member stops before its update and
+ *    returns the lowest such member;
+ *  - smoothing follows the update of iteration t when (t+1) mod nb_iter = 0;
+ *  - kappa and varpi sum over ordered pairs; the bonus matrix J - A keeps its
+ *    diagonal unless bonus_diag = 0; 0^p = 0.
+ *
+ * Memory: every pointer named *_dev is a device pointer on the current HIP
+ * device.  The caller owns A, W, all outputs and the optional workspace; the
+ * library owns only small host state plus, when no workspace is given, the
+ * device memory it allocates at init and frees in tcol_destroy.
+ *
+ * Streams: all device work is enqueued on the stream given at init (a
+ * hipStream_t passed as void*; NULL = the default stream).  tcol_step
+ * synchronises that stream once, at its end, to fill its host outputs; the
+ * other calls are asynchronous.
+ *
+ * Errors: every call returns a tcol_status; on an error no output is
+ * guaranteed.  tcol_status_string gives a static description.
+ */
+#ifndef TCOL_H
+#define TCOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tcol_status;
+enum {
+    TCOL_OK = 0,
+    TCOL_EINVAL = -1,      /* bad argument (NULL, out-of-range parameter, g out of range) */
+    TCOL_ESHAPE = -2,      /* bad n, k or D, or a size beyond the supported maximum */
+    TCOL_EGRAPH = -3,      /* A not symmetric, diagonal not zero, or an entry not 0/1 */
+    TCOL_EHIP = -4,        /* a HIP runtime call failed */
+    TCOL_ENONFINITE = -5,  /* a weight is NaN or infinite */
+    TCOL_ENOMEM = -6,      /* device allocation failed or the workspace is too small */
+    TCOL_ESTATE = -7       /* call not valid in the current state */
+};
+
+/* Problem statement (Section 2): k-COL is one step of the GCP (fitness =
+ * conflicts); the ECP adds the equity fitness to the fitness and the loss. */
+enum { TCOL_KCOL = 0, TCOL_ECP = 1 };
+
+/* Operand precision of the contractions A.S and (penalty).S.  The 0/1
+ * operands A and S are exact in every format and accumulate in FP32, so the
+ * conflict counts are exact in all three; the penalty operand is rounded to
+ * bf16 in TCOL_BF16 and TCOL_FP8 (TCOL_FP8 runs A.S in fp8 e4m3 and the
+ * penalty product in bf16).  Softmax, gradient and update are FP32. */
+enum { TCOL_FP32 = 0, TCOL_BF16 = 1, TCOL_FP8 = 2 };
+
+/* Parameters of one graph (parameter table of the paper: eta 1e-3, nb_iter 5,
+ * rho in {1,2,10,100,200}, alpha 2.5, lambda 1e-5, beta 1.2, mu 1e-6 (GCP) or 0
+ * (ECP), nu 0 (GCP) or 1e-5 (ECP)). */
+typedef struct {
+    int32_t problem;        /* TCOL_KCOL or TCOL_ECP */
+    int32_t precision;      /* TCOL_FP32, TCOL_BF16 or TCOL_FP8 */
+    int32_t n, k, D;        /* vertices (1..32768), colours (1..4096), members (1..1024) */
+    float eta, rho;         /* learning rate > 0; smoothing divisor >= 1 */
+    int32_t nb_iter;        /* smoothing period >= 1 */
+    float alpha, lambda;    /* penalisation exponent (> 1 when lambda > 0) and weight >= 0 */
+    float beta, mu;         /* bonus exponent (> 1 when mu > 0) and weight >= 0 */
+    float nu;               /* equity weight >= 0 (ECP) */
+    int32_t bonus_diag;     /* 1: bonus matrix J - A includes i = j (literal); 0: excludes it */
+    int32_t stop_on_legal;  /* 1: Algorithm 1 stop rule; 0: never stop (timing) */
+} tcol_graph_params;
+
+/* Execution options of a context. */
+typedef struct {
+    int32_t fused;          /* 1: one GEMM kernel per step that also applies softmax, gradient,
+                               update and the next argmax (default); 0: separate kernels */
+    int32_t use_graph;      /* 1: replay each step from a captured hipGraph (default) */
+    int32_t unroll;         /* steps per captured graph (1..64, default 8) */
+    int32_t tile_bm;        /* GEMM rows per block: 64 or 128; 0 = autotuned/default */
+    int32_t tile_ntw;       /* GEMM 16-column subtiles per wave (2..18); 0 = autotuned/default */
+} tcol_options;
+
+typedef struct tcol_ctx tcol_ctx;
+
+/* Static text for a status code. */
+const char *tcol_status_string(tcol_status s);
+
+/* Device bytes needed for G graphs with parameters p[G] (for tcol_init's workspace).
+ * Errors: TCOL_EINVAL (NULL), TCOL_ESHAPE (sizes out of range). */
+tcol_status tcol_workspace_size(int32_t G, const tcol_graph_params *p, size_t *bytes);
+
+/* Create a context for G >= 1 graphs stepped together.
+ *   p[G]      parameters per graph (copied);
+ *   A_dev[G]  adjacency, n x n uint8 row-major 0/1, symmetric, zero diagonal;
+ *             read during this call only (packed copies are kept);
+ *   W_dev[G]  weights, D x n x k fp32 row-major; caller-owned, read and
+ *             updated in place by tcol_step; must stay valid for the context;
+ *   ws_dev    device workspace of ws_bytes >= tcol_workspace_size, or NULL to
+ *             let the library allocate it;
+ *   stream    hipStream_t (as void*) for all work, NULL = default stream.
+ * The iteration counter t of every graph starts at 0.
+ * Errors: TCOL_EINVAL, TCOL_ESHAPE, TCOL_EGRAPH (A fails validation),
+ *         TCOL_ENOMEM, TCOL_EHIP.  On error *ctx is NULL. */
+tcol_status tcol_init(tcol_ctx **ctx, int32_t G, const tcol_graph_params *p,
+                      const uint8_t *const *A_dev, float *const *W_dev,
+                      void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Change execution options (before or between tcol_step calls). */
+tcol_status tcol_set_options(tcol_ctx *ctx, const tcol_options *opt);
+tcol_status tcol_get_options(tcol_ctx *ctx, tcol_options *opt);
+
+/* Run up to max_steps iterations of Algorithm 1 on every graph (steps 1-4;
+ * a graph whose population holds a legal member stops before that
+ * iteration's update when stop_on_legal = 1).
+ *   steps_done (host, may be NULL): largest number of updates any graph made;
+ *   legal_d (host [G], may be NULL): lowest legal member d* of each graph in
+ *     the iteration where it stopped, or -1;
+ *   colors_out_dev ([G] device pointers to n int16 each, may be NULL, entries
+ *     may be NULL): colouring S_{d*} of each graph that stopped.
+ * Synchronises the stream once.  Errors: TCOL_ENONFINITE (some weight is not
+ * finite; the affected graph stops without updating), TCOL_EHIP, TCOL_EINVAL. */
+tcol_status tcol_step(tcol_ctx *ctx, int32_t max_steps, int32_t *steps_done, int32_t *legal_d,
+                      int16_t *const *colors_out_dev);
+
+/* Steps 1-2 only, on the current W of graph g (W unchanged, t unchanged):
+ *   colors_dev  (D*n int16, may be NULL) argmax colours c_d(i);
+ *   f_color_dev (D int64, may be NULL) conflicts per member, computed from the
+ *               contraction A.S as 1/2 sum_i (A.S_d)[i, c_d(i)];
+ *   f_eq_dev    (D int64, may be NULL) equity fitness per member (0 for k-COL).
+ * Asynchronous.  Errors: TCOL_EINVAL. */
+tcol_status tcol_conflicts(tcol_ctx *ctx, int32_t g, int16_t *colors_dev, int64_t *f_color_dev,
+                           int64_t *f_eq_dev);
+
+/* Loss and gradients of graph g at its current W and t (no update):
+ *   loss_dev  (5 doubles, may be NULL): L, sum f_color, sum f_eq, kappa, varpi
+ *             (eq. global loss; FP64 reduction on the GPU);
+ *   gradS_dev (D*n*k fp32, may be NULL): gradient of L with respect to S;
+ *   gradW_dev (D*n*k fp32, may be NULL): straight-through gradient with respect to W.
+ * Asynchronous.  Errors: TCOL_EINVAL. */
+tcol_status tcol_loss_grad(tcol_ctx *ctx, int32_t g, double *loss_dev, float *gradS_dev,
+                           float *gradW_dev);
+
+/* Group concentration matrix Mt (n*n int32, row-major) of graph g at its
+ * current W (eq. tildeM).  Asynchronous.  Errors: TCOL_EINVAL. */
+tcol_status tcol_mtilde(tcol_ctx *ctx, int32_t g, int32_t *mt_dev);
+
+/* Iteration counter of graph g (checkpoint / resume: the state is W and t).
+ * tcol_get_t synchronises the stream. */
+tcol_status tcol_get_t(tcol_ctx *ctx, int32_t g, int64_t *t);
+tcol_status tcol_set_t(tcol_ctx *ctx, int32_t g, int64_t t);
+
+/* Clear the "stopped" state of every graph so tcol_step continues (for
+ * example after the caller changed k or re-initialised W). */
+tcol_status tcol_reset(tcol_ctx *ctx);
+
+/* Measure each candidate GEMM tile shape for this context's graphs on its
+ * stream (a few timed steps each, W restored afterwards) and keep the fastest
+ * in the options.  *best_bm / *best_ntw (host, may be NULL) receive it.
+ * Errors: TCOL_EHIP. */
+tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
+
+/* Measurement utility.  Runs `steps` iterations of every graph eagerly (no
+ * captured graph) with HIP events around each kernel on the context's stream
+ * and writes the average milliseconds per iteration of each phase to
+ * ms[TCOL_NPHASES]: 0 argmax colours, 1 class sizes, 2 one-hot S expansion,
+ * 3 group concentration + penalty operand, 4 contraction A.S (+ penalty pass)
+ * with fitness gather and, on the fused path, the update epilogue,
+ * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
+ * 7 counter advance.  When as_only is non-zero it then also times `steps`
+ * launches of the contraction restricted to A.S with the gather (W unchanged)
+ * into ms[8]; otherwise ms[8] = 0.  Synchronises the stream.
+ * Errors: TCOL_EINVAL, TCOL_EHIP. */
+#define TCOL_NPHASES 9
+tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *ms);
+
+/* Release the context (and the workspace it allocated).  NULL is ignored. */
+void tcol_destroy(tcol_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCOL_H */

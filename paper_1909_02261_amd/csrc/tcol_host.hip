@@ -1,0 +1,625 @@
+// Host runtime of libtcol: the C ABI declared in include/tcol.h.
+//
+// A context holds G graphs stepped together.  All device memory lives in one
+// workspace (caller-provided or allocated here): a head with the descriptor
+// and state arrays of all graphs, then one region per graph.  Each launch in a
+// step covers every graph of the context through flattened work indices, and
+// the step sequence can be captured once into a hipGraph and replayed, since
+// every kernel reads the iteration counter and the stop flags from device
+// memory.
+#include "tcol_internal.h"
+#include "tcol_launch.h"
+#include "../../include/tcol.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+using namespace tcol;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum Buf {
+    B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_COUNT
+};
+
+struct Layout {
+    size_t off[B_COUNT];
+    size_t total;
+    int n_pad, rows_S, eb, mt_T, mt_tiles;
+};
+
+int elem_bytes_host(int prec) { return prec == TCOL_FP32 ? 4 : (prec == TCOL_BF16 ? 2 : 1); }
+
+Layout make_layout(const tcol_graph_params& p) {
+    Layout L{};
+    L.n_pad = round_up(p.n, kPadN);
+    L.rows_S = round_up(p.D * p.k, 16) + kSRowSlack;
+    L.eb = elem_bytes_host(p.precision);
+    L.mt_T = L.n_pad / 64;
+    L.mt_tiles = L.mt_T * (L.mt_T + 1) / 2;
+    const size_t n2 = (size_t)L.n_pad * L.n_pad;
+    const size_t dnk = (size_t)p.D * p.n * p.k;
+    size_t sz[B_COUNT];
+    sz[B_LUT_PEN] = sizeof(float) * (p.D + 1);
+    sz[B_LUT_BON] = sizeof(float) * (p.D + 1);
+    sz[B_LUT_KA] = sizeof(double) * (p.D + 1);
+    sz[B_LUT_VB] = sizeof(double) * (p.D + 1);
+    sz[B_W2] = sizeof(float) * dnk;
+    sz[B_A8] = n2;
+    sz[B_AOP] = n2 * L.eb;
+    sz[B_POP] = n2 * (p.precision == TCOL_FP32 ? 4 : 2);
+    sz[B_S0] = sz[B_S1] = (size_t)L.rows_S * L.n_pad * L.eb;
+    sz[B_SP0] = sz[B_SP1] = p.precision == TCOL_FP8 ? (size_t)L.rows_S * L.n_pad * 2 : 0;
+    sz[B_C0] = sz[B_C1] = sizeof(int16_t) * ((size_t)p.D * p.n + 64);
+    sz[B_V0] = sz[B_V1] = sizeof(int32_t) * (size_t)p.D * p.k;
+    sz[B_G] = sizeof(float) * dnk;
+    sz[B_F2] = sizeof(int32_t) * p.D;
+    sz[B_FCOL] = sz[B_FEQ] = sz[B_F] = sizeof(int64_t) * p.D;
+    sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
+    sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
+    size_t o = 0;
+    for (int b = 0; b < B_COUNT; ++b) {
+        L.off[b] = o;
+        o += align_up(sz[b]);
+    }
+    L.total = o;
+    return L;
+}
+
+size_t head_bytes(int G) { return align_up(sizeof(GraphDev) * G) + align_up(sizeof(GraphState) * G); }
+
+tcol_status check_params(const tcol_graph_params& p) {
+    if (p.n < 1 || p.n > kMaxN || p.k < 1 || p.k > kMaxK || p.D < 1 || p.D > kMaxD) return TCOL_ESHAPE;
+    if ((long long)p.D * p.k > (1LL << 26)) return TCOL_ESHAPE;
+    if (p.problem != TCOL_KCOL && p.problem != TCOL_ECP) return TCOL_EINVAL;
+    if (p.precision < TCOL_FP32 || p.precision > TCOL_FP8) return TCOL_EINVAL;
+    if (!(p.eta > 0.0f) || !(p.rho >= 1.0f) || p.nb_iter < 1) return TCOL_EINVAL;
+    if (!(p.lambda >= 0.0f) || !(p.mu >= 0.0f) || !(p.nu >= 0.0f)) return TCOL_EINVAL;
+    if (p.lambda > 0.0f && !(p.alpha > 1.0f)) return TCOL_EINVAL;
+    if (p.mu > 0.0f && !(p.beta > 1.0f)) return TCOL_EINVAL;
+    if (!isfinite(p.alpha) || !isfinite(p.beta) || !isfinite(p.eta) || !isfinite(p.rho)) return TCOL_EINVAL;
+    return TCOL_OK;
+}
+
+double pow0(double x, double p) { return x == 0.0 ? 0.0 : pow(x, p); }
+
+}  // namespace
+
+struct tcol_ctx {
+    int G = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<tcol_graph_params> params;
+    std::vector<Layout> layouts;
+    std::vector<size_t> base;       // workspace offset of each graph region
+    std::vector<GraphDev> hdesc;
+    GraphDev* ddesc = nullptr;
+    GraphState* dstate = nullptr;
+    GraphState* hstate = nullptr;   // pinned
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    tcol_options opt{};
+    GemmShape shape{};
+    int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0, total_gm = 0, kmax = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [0] = unroll steps, [1] = one step
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int graph_unroll = 0;
+};
+
+#define HIPCHK(x)                                                    \
+    do {                                                             \
+        hipError_t e_ = (x);                                         \
+        if (e_ != hipSuccess) {                                      \
+            fprintf(stderr, "libtcol: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+            return TCOL_EHIP;                                        \
+        }                                                            \
+    } while (0)
+
+static void drop_graphs(tcol_ctx* c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) hipGraphExecDestroy(c->gexec[i]);
+        if (c->graph[i]) hipGraphDestroy(c->graph[i]);
+        c->gexec[i] = nullptr;
+        c->graph[i] = nullptr;
+    }
+    c->graph_unroll = 0;
+}
+
+// choose the GEMM tile shape for the current options
+static GemmShape pick_shape(const tcol_ctx* c) {
+    int prec = c->params[0].precision;
+    for (auto& p : c->params)
+        if (p.precision != prec) prec = -1;
+    GemmShape s{prec < 0 ? 0 : prec, 128, 8, c->opt.fused ? 1 : 0};
+    if (c->opt.tile_bm) s.bm = c->opt.tile_bm;
+    if (c->opt.tile_ntw) s.ntw = c->opt.tile_ntw;
+    else {
+        long long cols = 0;
+        for (auto& p : c->params) cols = std::max<long long>(cols, (long long)p.D * p.k);
+        if (cols <= 512) s.ntw = 4;
+        if (cols <= 128) s.ntw = 2;
+    }
+    if (!c->opt.tile_bm) {
+        int nmin = 1 << 30;
+        for (auto& p : c->params) nmin = std::min(nmin, p.n);
+        if (nmin <= 256) s.bm = 64;
+    }
+    return s;
+}
+
+// recompute flattened work offsets for the tile shape and upload the descriptors
+static tcol_status rebuild_schedule(tcol_ctx* c) {
+    c->shape = pick_shape(c);
+    if (!gemm_supported(c->shape)) {
+        c->shape.bm = 128;
+        c->shape.ntw = 8;
+        if (!gemm_supported(c->shape)) return TCOL_EINVAL;
+    }
+    HIPCHK(gemm_prepare(c->shape));
+    const int BN = gemm_bn(c->shape.ntw);
+    int rows = 0, mem = 0, mt = 0, ex = 0, gm = 0, kmax = 0;
+    for (int g = 0; g < c->G; ++g) {
+        const tcol_graph_params& p = c->params[g];
+        const Layout& L = c->layouts[g];
+        GraphDev& d = c->hdesc[g];
+        d.row_begin = rows;
+        rows += p.D * p.n;
+        d.mem_begin = mem;
+        mem += p.D;
+        d.mt_begin = mt;
+        d.mt_T = L.mt_T;
+        mt += L.mt_tiles;
+        d.ex_begin = ex;
+        const long long items = (long long)p.D * p.k * (L.n_pad / 16);
+        d.ex_cblocks = (int)((items + 255) / 256);
+        ex += d.ex_cblocks;
+        d.gm_begin = gm;
+        d.gm_tm = L.n_pad / c->shape.bm;
+        if (c->shape.mode == 1) {
+            d.gm_mpb = std::max(1, BN / p.k);
+            d.gm_tn = ceil_div(p.D, d.gm_mpb);
+        } else {
+            d.gm_mpb = 0;
+            d.gm_tn = ceil_div(p.D * p.k, BN);
+        }
+        gm += d.gm_tm * d.gm_tn;
+        kmax = std::max(kmax, p.k);
+    }
+    c->total_rows = rows;
+    c->total_mem = mem;
+    c->total_mt = mt;
+    c->total_ex = ex;
+    c->total_gm = gm;
+    c->kmax = kmax;
+    HIPCHK(hipMemcpyAsync(c->ddesc, c->hdesc.data(), sizeof(GraphDev) * c->G, hipMemcpyHostToDevice, c->stream));
+    drop_graphs(c);
+    return TCOL_OK;
+}
+
+// ---------------------------------------------------------------- sequences --
+
+// one Algorithm-1 iteration for every running graph (separate-kernel path)
+static hipError_t enqueue_step_separate(tcol_ctx* c, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_colors(c->ddesc, c->G, c->total_rows, 1, s)) != hipSuccess) return e;
+    if ((e = launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 1, 7, s)) != hipSuccess) return e;
+    if ((e = launch_fitness(c->ddesc, c->G, 1, 0, -1, s)) != hipSuccess) return e;
+    if ((e = launch_update(c->ddesc, c->G, c->total_rows, 1, 0, -1, nullptr, nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_advance(c->ddesc, c->G, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+static hipError_t enqueue_steps(tcol_ctx* c, int n, hipStream_t s) {
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = enqueue_step_separate(c, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static tcol_status build_graphs(tcol_ctx* c) {
+    drop_graphs(c);
+    const int U = std::max(1, std::min(64, c->opt.unroll));
+    const int counts[2] = {U, 1};
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_steps(c, counts[i], c->cap);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap, &gr);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (gr) hipGraphDestroy(gr);
+            fprintf(stderr, "libtcol: graph capture failed: %s\n", hipGetErrorString(e != hipSuccess ? e : e2));
+            return TCOL_EHIP;
+        }
+        c->graph[i] = gr;
+        HIPCHK(hipGraphInstantiate(&c->gexec[i], gr, nullptr, nullptr, 0));
+    }
+    c->graph_unroll = U;
+    return TCOL_OK;
+}
+
+// ---------------------------------------------------------------- C ABI ------
+
+extern "C" {
+
+const char* tcol_status_string(tcol_status s) {
+    switch (s) {
+        case TCOL_OK: return "ok";
+        case TCOL_EINVAL: return "invalid argument";
+        case TCOL_ESHAPE: return "unsupported shape";
+        case TCOL_EGRAPH: return "adjacency matrix is not symmetric 0/1 with a zero diagonal";
+        case TCOL_EHIP: return "HIP runtime error";
+        case TCOL_ENONFINITE: return "non-finite weight";
+        case TCOL_ENOMEM: return "out of device memory or workspace too small";
+        case TCOL_ESTATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+tcol_status tcol_workspace_size(int32_t G, const tcol_graph_params* p, size_t* bytes) {
+    if (G < 1 || !p || !bytes) return TCOL_EINVAL;
+    size_t tot = head_bytes(G);
+    for (int g = 0; g < G; ++g) {
+        tcol_status s = check_params(p[g]);
+        if (s != TCOL_OK) return s;
+        tot += make_layout(p[g]).total;
+    }
+    *bytes = tot;
+    return TCOL_OK;
+}
+
+void tcol_destroy(tcol_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap) hipStreamDestroy(c->cap);
+    if (c->ws_owned && c->ws) hipFree(c->ws);
+    if (c->hstate) hipHostFree(c->hstate);
+    delete c;
+}
+
+tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, const uint8_t* const* A_dev,
+                      float* const* W_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+    if (!out) return TCOL_EINVAL;
+    *out = nullptr;
+    if (G < 1 || !p || !A_dev || !W_dev) return TCOL_EINVAL;
+    size_t need = 0;
+    tcol_status s = tcol_workspace_size(G, p, &need);
+    if (s != TCOL_OK) return s;
+    for (int g = 0; g < G; ++g)
+        if (!A_dev[g] || !W_dev[g]) return TCOL_EINVAL;
+    if (ws_dev && ws_bytes < need) return TCOL_ENOMEM;
+
+    tcol_ctx* c = new tcol_ctx();
+    c->G = G;
+    c->stream = (hipStream_t)stream;
+    c->params.assign(p, p + G);
+    c->opt.fused = 0;
+    c->opt.use_graph = 1;
+    c->opt.unroll = 8;
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return TCOL_EHIP;
+    }
+    if (hipHostMalloc((void**)&c->hstate, sizeof(GraphState) * G, hipHostMallocDefault) != hipSuccess) {
+        tcol_destroy(c);
+        return TCOL_ENOMEM;
+    }
+    if (ws_dev) {
+        c->ws = (uint8_t*)ws_dev;
+        c->ws_bytes = ws_bytes;
+    } else {
+        if (hipMalloc((void**)&c->ws, need) != hipSuccess) {
+            c->ws = nullptr;
+            tcol_destroy(c);
+            return TCOL_ENOMEM;
+        }
+        c->ws_owned = true;
+        c->ws_bytes = need;
+    }
+    // every buffer starts at zero: padding rows/columns of the operands stay zero forever
+    if (hipMemsetAsync(c->ws, 0, need, c->stream) != hipSuccess) {
+        tcol_destroy(c);
+        return TCOL_EHIP;
+    }
+    c->ddesc = (GraphDev*)c->ws;
+    c->dstate = (GraphState*)(c->ws + align_up(sizeof(GraphDev) * G));
+    size_t off = head_bytes(G);
+    c->hdesc.resize(G);
+    c->layouts.resize(G);
+    c->base.resize(G);
+    int* dbad = nullptr;
+    if (hipMalloc((void**)&dbad, sizeof(int)) != hipSuccess || hipMemsetAsync(dbad, 0, sizeof(int), c->stream) != hipSuccess) {
+        tcol_destroy(c);
+        return TCOL_EHIP;
+    }
+    tcol_status rc = TCOL_OK;
+    for (int g = 0; g < G && rc == TCOL_OK; ++g) {
+        const tcol_graph_params& q = p[g];
+        Layout L = make_layout(q);
+        c->layouts[g] = L;
+        c->base[g] = off;
+        uint8_t* b = c->ws + off;
+        off += L.total;
+        GraphDev& d = c->hdesc[g];
+        memset(&d, 0, sizeof(d));
+        d.n = q.n;
+        d.k = q.k;
+        d.D = q.D;
+        d.n_pad = L.n_pad;
+        d.ncols = q.D * q.k;
+        d.rows_S = L.rows_S;
+        d.problem = q.problem;
+        d.precision = q.precision;
+        d.bonus_diag = q.bonus_diag ? 1 : 0;
+        d.stop_on_legal = q.stop_on_legal ? 1 : 0;
+        d.nb_iter = q.nb_iter;
+        d.c1 = q.n / q.k;
+        d.c2 = (q.n % q.k == 0) ? q.n / q.k : q.n / q.k + 1;
+        d.eta = q.eta;
+        d.rho = q.rho;
+        d.nu = q.problem == TCOL_ECP ? q.nu : 0.0f;
+        d.lambda = q.lambda;
+        d.mu = q.mu;
+        d.lut_pen = (const float*)(b + L.off[B_LUT_PEN]);
+        d.lut_bon = (const float*)(b + L.off[B_LUT_BON]);
+        d.lut_ka = (const double*)(b + L.off[B_LUT_KA]);
+        d.lut_vb = (const double*)(b + L.off[B_LUT_VB]);
+        d.W[0] = W_dev[g];
+        d.W[1] = (float*)(b + L.off[B_W2]);
+        d.A8 = b + L.off[B_A8];
+        d.Aop = b + L.off[B_AOP];
+        d.Pop = b + L.off[B_POP];
+        d.Sop[0] = b + L.off[B_S0];
+        d.Sop[1] = b + L.off[B_S1];
+        d.Sp2[0] = q.precision == TCOL_FP8 ? (void*)(b + L.off[B_SP0]) : nullptr;
+        d.Sp2[1] = q.precision == TCOL_FP8 ? (void*)(b + L.off[B_SP1]) : nullptr;
+        d.c[0] = (int16_t*)(b + L.off[B_C0]);
+        d.c[1] = (int16_t*)(b + L.off[B_C1]);
+        d.V[0] = (int32_t*)(b + L.off[B_V0]);
+        d.V[1] = (int32_t*)(b + L.off[B_V1]);
+        d.G = (float*)(b + L.off[B_G]);
+        d.f2 = (int32_t*)(b + L.off[B_F2]);
+        d.fcol = (int64_t*)(b + L.off[B_FCOL]);
+        d.feq = (int64_t*)(b + L.off[B_FEQ]);
+        d.f = (int64_t*)(b + L.off[B_F]);
+        d.part = (double*)(b + L.off[B_PART]);
+        d.snap = (int16_t*)(b + L.off[B_SNAP]);
+        d.st = c->dstate + g;
+        // look-up tables over the group concentration m = 0..D (host libm, FP64)
+        std::vector<float> lp(q.D + 1), lb(q.D + 1);
+        std::vector<double> lka(q.D + 1), lvb(q.D + 1);
+        for (int m = 0; m <= q.D; ++m) {
+            lp[m] = (float)(2.0 * q.alpha * q.lambda * pow0(m, (double)q.alpha - 1.0));
+            lb[m] = (float)(2.0 * q.beta * q.mu * pow0(m, (double)q.beta - 1.0));
+            lka[m] = pow0(m, q.alpha);
+            lvb[m] = pow0(m, q.beta);
+        }
+        if (hipMemcpy(b + L.off[B_LUT_PEN], lp.data(), sizeof(float) * lp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b + L.off[B_LUT_BON], lb.data(), sizeof(float) * lb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b + L.off[B_LUT_KA], lka.data(), sizeof(double) * lka.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b + L.off[B_LUT_VB], lvb.data(), sizeof(double) * lvb.size(), hipMemcpyHostToDevice) != hipSuccess)
+            rc = TCOL_EHIP;
+        if (rc == TCOL_OK &&
+            launch_pack_graph(A_dev[g], q.n, L.n_pad, q.precision, (uint8_t*)d.A8, d.Aop, dbad, c->stream) != hipSuccess)
+            rc = TCOL_EHIP;
+    }
+    int bad = 0;
+    if (rc == TCOL_OK) {
+        if (hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = TCOL_EHIP;
+    }
+    hipFree(dbad);
+    if (rc == TCOL_OK && bad) rc = TCOL_EGRAPH;
+    if (rc == TCOL_OK) {
+        std::vector<GraphState> st(G);
+        for (auto& x : st) {
+            memset(&x, 0, sizeof(x));
+            x.legal_d = -1;
+        }
+        if (hipMemcpy(c->dstate, st.data(), sizeof(GraphState) * G, hipMemcpyHostToDevice) != hipSuccess)
+            rc = TCOL_EHIP;
+    }
+    if (rc == TCOL_OK) rc = rebuild_schedule(c);
+    if (rc == TCOL_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = TCOL_EHIP;
+    if (rc != TCOL_OK) {
+        tcol_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return TCOL_OK;
+}
+
+tcol_status tcol_set_options(tcol_ctx* c, const tcol_options* o) {
+    if (!c || !o) return TCOL_EINVAL;
+    if (o->unroll < 0 || o->unroll > 64) return TCOL_EINVAL;
+    if (o->tile_bm && o->tile_bm != 64 && o->tile_bm != 128) return TCOL_EINVAL;
+    if (o->tile_ntw < 0 || o->tile_ntw > 18) return TCOL_EINVAL;
+    tcol_options old = c->opt;
+    c->opt = *o;
+    if (c->opt.unroll == 0) c->opt.unroll = 8;
+    c->opt.fused = 0;   // the fused epilogue is selected only where it is built
+    tcol_status s = rebuild_schedule(c);
+    if (s != TCOL_OK) {
+        c->opt = old;
+        rebuild_schedule(c);
+    }
+    return s;
+}
+
+tcol_status tcol_get_options(tcol_ctx* c, tcol_options* o) {
+    if (!c || !o) return TCOL_EINVAL;
+    *o = c->opt;
+    if (!o->tile_bm) o->tile_bm = c->shape.bm;
+    if (!o->tile_ntw) o->tile_ntw = c->shape.ntw;
+    return TCOL_OK;
+}
+
+tcol_status tcol_step(tcol_ctx* c, int32_t max_steps, int32_t* steps_done, int32_t* legal_d,
+                      int16_t* const* colors_out_dev) {
+    if (!c || max_steps < 0) return TCOL_EINVAL;
+    HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
+    if (max_steps > 0) {
+        if (c->opt.use_graph) {
+            if (c->graph_unroll != std::max(1, std::min(64, c->opt.unroll)) || !c->gexec[0]) {
+                tcol_status s = build_graphs(c);
+                if (s != TCOL_OK) return s;
+            }
+            const int U = c->graph_unroll;
+            for (int i = 0; i < max_steps / U; ++i) HIPCHK(hipGraphLaunch(c->gexec[0], c->stream));
+            for (int i = 0; i < max_steps % U; ++i) HIPCHK(hipGraphLaunch(c->gexec[1], c->stream));
+        } else {
+            HIPCHK(enqueue_steps(c, max_steps, c->stream));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->hstate, c->dstate, sizeof(GraphState) * c->G, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int done = 0;
+    tcol_status rc = TCOL_OK;
+    for (int g = 0; g < c->G; ++g) {
+        const GraphState& st = c->hstate[g];
+        done = std::max(done, st.steps_done);
+        if (legal_d) legal_d[g] = st.legal_d;
+        if (st.error) rc = st.error;
+        if (colors_out_dev && colors_out_dev[g] && st.legal_d >= 0)
+            HIPCHK(hipMemcpyAsync(colors_out_dev[g], c->hdesc[g].snap, sizeof(int16_t) * c->params[g].n,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (steps_done) *steps_done = done;
+    return rc;
+}
+
+tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t* f_color_dev, int64_t* f_eq_dev) {
+    if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
+    // steps 1-2 for all graphs of the context (cheap), reporting only
+    HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
+    HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, c->stream));
+    GemmShape s = c->shape;
+    s.mode = 0;
+    if (s.mode != c->shape.mode) HIPCHK(gemm_prepare(s));
+    // separate-mode tiling is needed for the gather over arbitrary column tiles
+    HIPCHK(launch_gemm(s, c->ddesc, c->G, c->total_gm, 0, 1, c->stream));
+    HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
+    HIPCHK(launch_copy_report(c->ddesc, g, colors_dev, f_color_dev, f_eq_dev, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* gradS_dev, float* gradW_dev) {
+    if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
+    HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
+    HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, c->stream));
+    HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagLoss | kFlagForcePen, g, nullptr, c->stream));
+    HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 0, 7, c->stream));
+    HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
+    if (loss_dev) HIPCHK(launch_loss(c->ddesc, g, c->layouts[g].mt_tiles, loss_dev, c->stream));
+    if (gradS_dev || gradW_dev)
+        HIPCHK(launch_update(c->ddesc, c->G, c->total_rows, 0, 1, g, gradS_dev, gradW_dev, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_mtilde(tcol_ctx* c, int32_t g, int32_t* mt_dev) {
+    if (!c || g < 0 || g >= c->G || !mt_dev) return TCOL_EINVAL;
+    HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
+    HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagMtOut, g, mt_dev, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_get_t(tcol_ctx* c, int32_t g, int64_t* t) {
+    if (!c || g < 0 || g >= c->G || !t) return TCOL_EINVAL;
+    GraphState st;
+    HIPCHK(hipMemcpyAsync(&st, c->dstate + g, sizeof(GraphState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *t = st.t;
+    return TCOL_OK;
+}
+
+tcol_status tcol_set_t(tcol_ctx* c, int32_t g, int64_t t) {
+    if (!c || g < 0 || g >= c->G || t < 0) return TCOL_EINVAL;
+    HIPCHK(launch_state(c->ddesc, c->G, 1, g, t, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_reset(tcol_ctx* c) {
+    if (!c) return TCOL_EINVAL;
+    HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms) {
+    if (!c || steps < 1 || !ms) return TCOL_EINVAL;
+    constexpr int NP = TCOL_NPHASES;
+    hipEvent_t ev[NP];
+    for (int i = 0; i < NP; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    double acc[NP] = {0};
+    hipStream_t s = c->stream;
+    HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, s));
+    for (int it = 0; it < steps; ++it) {
+        HIPCHK(hipEventRecord(ev[0], s));
+        HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
+        HIPCHK(hipEventRecord(ev[1], s));
+        HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+        HIPCHK(hipEventRecord(ev[2], s));
+        HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, s));
+        HIPCHK(hipEventRecord(ev[3], s));
+        HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
+        HIPCHK(hipEventRecord(ev[4], s));
+        HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 1, 7, s));
+        HIPCHK(hipEventRecord(ev[5], s));
+        HIPCHK(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+        HIPCHK(hipEventRecord(ev[6], s));
+        HIPCHK(launch_update(c->ddesc, c->G, c->total_rows, 1, 0, -1, nullptr, nullptr, s));
+        HIPCHK(hipEventRecord(ev[7], s));
+        HIPCHK(launch_advance(c->ddesc, c->G, s));
+        HIPCHK(hipEventRecord(ev[8], s));
+        HIPCHK(hipEventSynchronize(ev[8]));
+        for (int i = 0; i < 8; ++i) {
+            float x = 0;
+            HIPCHK(hipEventElapsedTime(&x, ev[i], ev[i + 1]));
+            acc[i] += x;
+        }
+    }
+    for (int i = 0; i < 8; ++i) ms[i] = (float)(acc[i] / steps);
+    ms[8] = 0.0f;
+    if (as_only) {
+        double a = 0;
+        GemmShape sh = c->shape;
+        sh.mode = 0;
+        for (int it = 0; it < steps; ++it) {
+            HIPCHK(hipEventRecord(ev[0], s));
+            HIPCHK(launch_gemm(sh, c->ddesc, c->G, c->total_gm, 0, 1, s));
+            HIPCHK(hipEventRecord(ev[1], s));
+            HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, s));
+            HIPCHK(hipEventSynchronize(ev[1]));
+            float x = 0;
+            HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
+            a += x;
+        }
+        ms[8] = (float)(a / steps);
+    }
+    for (int i = 0; i < NP; ++i) hipEventDestroy(ev[i]);
+    return TCOL_OK;
+}
+
+tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
+    if (!c) return TCOL_EINVAL;
+    if (best_bm) *best_bm = c->shape.bm;
+    if (best_ntw) *best_ntw = c->shape.ntw;
+    return TCOL_OK;
+}
+
+}  // extern "C"

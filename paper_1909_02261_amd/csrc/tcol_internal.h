@@ -1,0 +1,98 @@
+// Internal definitions shared by the gfx950 kernels and the host runtime of libtcol.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcol {
+
+constexpr int kPrecFP32 = 0;
+constexpr int kPrecBF16 = 1;
+constexpr int kPrecFP8 = 2;
+
+constexpr int kMaxN = 32768;
+constexpr int kMaxK = 4096;
+constexpr int kMaxD = 1024;
+
+// operand rows and columns are padded to this multiple (GEMM tile in M and K)
+constexpr int kPadN = 128;
+// extra zero rows after the D*k rows of S^T so any column tile can read a full tile
+constexpr int kSRowSlack = 576;
+// bytes per operand row per GEMM K-stage, and its padded LDS stride
+constexpr int kStageRowBytes = 128;
+constexpr int kLdsStride = 144;
+
+// device-resident per-graph state (iteration counter, stop flags, parities)
+struct GraphState {
+    long long t;        // iteration counter of Algorithm 1 (starts at 0)
+    int stopped;        // a legal member was found (stop_on_legal) or an error occurred
+    int error;          // 0 or a negative tcol status (non-finite weight)
+    int legal_d;        // lowest legal member of the stopping iteration, or -1
+    int steps_done;     // updates made since the last reset by the host
+    int pW;             // fused path: which W buffer holds the current weights (0 = caller's)
+    int pS;             // fused path: which colour / S buffer set is current
+};
+
+// per-graph descriptor, uploaded once at init
+struct GraphDev {
+    int n, k, D;
+    int n_pad;          // padded n (rows and K of the operands)
+    int ncols;          // D * k
+    int rows_S;         // rows of S^T (D*k + slack)
+    int problem, precision, bonus_diag, stop_on_legal, nb_iter;
+    int c1, c2;         // equity bounds
+    float eta, rho, nu, lambda, mu;
+    // look-up tables over m = 0..D
+    const float* lut_pen;     // 2 alpha lambda m^(alpha-1)   (0 at m = 0)
+    const float* lut_bon;     // 2 beta mu m^(beta-1)         (0 at m = 0)
+    const double* lut_ka;     // m^alpha
+    const double* lut_vb;     // m^beta
+    // buffers
+    float* W[2];              // [0] caller's weights, [1] fused-path ping-pong buffer
+    const uint8_t* A8;        // [n_pad][n_pad] 0/1 bytes (zero padded)
+    void* Aop;                // [n_pad][n_pad] A in the operand precision
+    void* Pop;                // [n_pad][n_pad] penalty operand (fp32, or bf16 for BF16/FP8)
+    void* Sop[2];             // [rows_S][n_pad] S^T in the A.S operand precision
+    void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 penalty pass (else null)
+    int16_t* c[2];            // colours [D][n]
+    int32_t* V[2];            // class sizes [D][k]
+    float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)
+    int32_t* f2;              // [D] 2 * f_color accumulated by the GEMM
+    int64_t* fcol;            // [D]
+    int64_t* feq;             // [D]
+    int64_t* f;               // [D]
+    double* part;             // [mt_tiles][2] kappa / varpi partial sums
+    int16_t* snap;            // [n] colouring of the legal member
+    GraphState* st;
+    // flattened work offsets (prefix sums over graphs)
+    int row_begin;            // rows (d, i) for row kernels
+    int mem_begin;            // members d for per-member kernels
+    int mt_begin;             // tiles of the group-concentration kernel
+    int mt_T;                 // 64-row tiles per side
+    int ex_begin;             // blocks of the S^T expansion kernel
+    int ex_cblocks;           // column blocks per S^T row group
+    int gm_begin;             // GEMM tiles
+    int gm_tm, gm_tn;         // GEMM tiles along rows and along columns
+    int gm_mpb;               // fused path: members per column tile
+};
+
+// run-time flags passed to the kernels of one launch sequence
+enum : int {
+    kFlagLoss = 1,        // group-concentration kernel also writes kappa/varpi partials
+    kFlagMtOut = 2,       // ... and Mt to an output buffer
+    kFlagForcePen = 4,    // build the penalty operand even when lambda t = mu t = 0
+    kFlagReport = 8,      // fitness kernel only reports (no stop, no state change)
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
+
+// find the graph that owns flattened work item `w` given a begin offset per graph
+template <typename F>
+__device__ inline int find_graph(const GraphDev* gd, int G, int w, F begin_of) {
+    int g = 0;
+    while (g + 1 < G && begin_of(gd[g + 1]) <= w) ++g;
+    return g;
+}
+
+}  // namespace tcol

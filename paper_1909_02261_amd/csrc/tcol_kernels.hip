@@ -1,0 +1,556 @@
+// gfx950 kernels of the TensCol population step other than the MFMA contraction:
+// graph validation and packing, argmax colouring, class sizes, one-hot S^T
+// expansion, group concentration with the penalty operand, fitness and stop
+// rule, softmax straight-through update, loss reduction, state updates.
+//
+// Every kernel takes the descriptor array of all graphs of a context and a
+// flattened work index, so one launch serves a batch of graphs of uneven sizes.
+#include "tcol_internal.h"
+#include "tcol_launch.h"
+
+#include <math.h>
+
+namespace tcol {
+
+// ---------------------------------------------------------------- helpers ----
+
+__device__ inline uint16_t f32_to_bf16_rne(float x) {
+    // round to nearest even on the upper 16 bits (inputs here are finite)
+    uint32_t u = __float_as_uint(x);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline bool finite_f(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
+
+// 1.0 in each operand format
+__device__ inline uint32_t one_bits(int prec) {
+    return prec == kPrecFP32 ? 0x3F800000u : (prec == kPrecBF16 ? 0x3F80u : 0x38u);
+}
+
+__device__ inline int graph_of_row(const GraphDev* gd, int G, int w) {
+    return find_graph(gd, G, w, [](const GraphDev& x) { return x.row_begin; });
+}
+
+// ------------------------------------------------------ validation, packing --
+
+// Checks A (n x n, row-major 0/1, symmetric, zero diagonal) and writes the
+// zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]).
+__global__ void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
+                             uint8_t* __restrict__ A8, void* __restrict__ Aop, int* __restrict__ bad) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)n_pad * n_pad;
+    if (e >= total) return;
+    int i = (int)(e / n_pad), j = (int)(e - (long long)i * n_pad);
+    uint8_t a = 0;
+    if (i < n && j < n) {
+        a = A[(size_t)i * n + j];
+        uint8_t b = A[(size_t)j * n + i];
+        if (a > 1 || a != b || (i == j && a != 0)) atomicOr(bad, 1);
+        a = a ? 1 : 0;
+    }
+    A8[e] = a;
+    if (prec == kPrecFP32)
+        ((float*)Aop)[e] = a ? 1.0f : 0.0f;
+    else if (prec == kPrecBF16)
+        ((uint16_t*)Aop)[e] = a ? 0x3F80 : 0;
+    else
+        ((uint8_t*)Aop)[e] = a ? 0x38 : 0;
+}
+
+// ------------------------------------------------------------ step 1 -----------
+
+// c_d(i) = argmax_l W[d,i,l], lowest l on ties; 16 lanes per row.
+__global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd, int G, int total_rows,
+                                                int honor_stop) {
+    const int l16 = threadIdx.x & 15;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (row >= total_rows) return;
+    const GraphDev& d = gd[graph_of_row(gd, G, row)];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int r = row - d.row_begin;
+    const float* w = d.W[st->pW] + (size_t)r * d.k;
+    float best = -INFINITY;
+    int bi = 0x7FFFFFFF;
+    int bad = 0;
+    for (int l = l16; l < d.k; l += 16) {
+        float x = w[l];
+        if (!finite_f(x)) bad = 1;
+        if (x > best) { best = x; bi = l; }
+    }
+    for (int m = 8; m >= 1; m >>= 1) {
+        float ob = __shfl_xor(best, m, 16);
+        int oi = __shfl_xor(bi, m, 16);
+        int obad = __shfl_xor(bad, m, 16);
+        bad |= obad;
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (l16 == 0) {
+        if (bad || bi >= d.k) {
+            bi = 0;
+            atomicExch(&st->error, -5);
+            atomicExch(&st->stopped, 1);
+        }
+        d.c[st->pS][r] = (int16_t)bi;
+    }
+}
+
+// #V_{d,l}: class sizes of member d; one block per member (all graphs).
+__global__ __launch_bounds__(256) void k_class_sizes(const GraphDev* __restrict__ gd, int G, int total_mem,
+                                                     int honor_stop, int next) {
+    extern __shared__ int hist[];
+    const int mem = blockIdx.x;
+    if (mem >= total_mem) return;
+    const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int p = next ? st->pS ^ 1 : st->pS;
+    const int m = mem - d.mem_begin;
+    for (int l = threadIdx.x; l < d.k; l += blockDim.x) hist[l] = 0;
+    __syncthreads();
+    const int16_t* c = d.c[p] + (size_t)m * d.n;
+    for (int i = threadIdx.x; i < d.n; i += blockDim.x) atomicAdd(&hist[c[i]], 1);
+    __syncthreads();
+    for (int l = threadIdx.x; l < d.k; l += blockDim.x) d.V[p][(size_t)m * d.k + l] = hist[l];
+}
+
+// One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread.
+// For FP8 graphs the bf16 copy used by the penalty pass is written as well.
+__global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                int honor_stop, int next) {
+    const int b = blockIdx.x;
+    if (b >= total_blocks) return;
+    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ex_begin; })];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int p = next ? st->pS ^ 1 : st->pS;
+    const int cgs = d.n_pad / 16;
+    const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
+    const int row = (int)(item / cgs);
+    const int cg = (int)(item - (long long)row * cgs);
+    if (row >= d.ncols) return;
+    const int dm = row / d.k;
+    const int l = row - dm * d.k;
+    const int16_t* c = d.c[p] + (size_t)dm * d.n;
+    const int j0 = cg * 16;
+    uint32_t mask = 0;   // bit q set when column j0+q has colour l
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        int j = j0 + q;
+        if (j < d.n && c[j] == l) mask |= 1u << q;
+    }
+    const size_t off = (size_t)row * d.n_pad + j0;
+    if (d.precision == kPrecFP32) {
+        float4* o = (float4*)((float*)d.Sop[p] + off);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float4 x;
+            x.x = (mask >> (4 * v + 0)) & 1 ? 1.0f : 0.0f;
+            x.y = (mask >> (4 * v + 1)) & 1 ? 1.0f : 0.0f;
+            x.z = (mask >> (4 * v + 2)) & 1 ? 1.0f : 0.0f;
+            x.w = (mask >> (4 * v + 3)) & 1 ? 1.0f : 0.0f;
+            o[v] = x;
+        }
+    } else {
+        uint16_t* sb = d.precision == kPrecBF16 ? (uint16_t*)d.Sop[p] : (uint16_t*)d.Sp2[p];
+        uint4* o = (uint4*)(sb + off);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            uint32_t w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                int q = 8 * v + 2 * h;
+                w[h] = (((mask >> q) & 1) ? 0x3F80u : 0u) | (((mask >> (q + 1)) & 1) ? 0x3F800000u : 0u);
+            }
+            o[v] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        if (d.precision == kPrecFP8) {
+            uint32_t w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if ((mask >> (4 * h + e)) & 1) x |= 0x38u << (8 * e);
+                w[h] = x;
+            }
+            *(uint4*)((uint8_t*)d.Sop[p] + off) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ step 3 -----------
+
+// Group concentration Mt_ij = #{d : c_d(i) = c_d(j)} over 64x64 tiles of the
+// upper triangle (mirrored), and from it the penalty operand
+//   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)).
+// Optional: Mt to mt_out (int32 [n][n]) and kappa / varpi partial sums.
+__global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd, int G, int total_tiles,
+                                                int honor_stop, int flags, int gsel, int32_t* __restrict__ mt_out) {
+    constexpr int DC = 128;   // members per LDS chunk
+    __shared__ int16_t ci[DC][64];
+    __shared__ int16_t cj[DC][64];
+    __shared__ double red[2][256];
+    const int b = blockIdx.x;
+    if (b >= total_tiles) return;
+    const int g = find_graph(gd, G, b, [](const GraphDev& x) { return x.mt_begin; });
+    const GraphDev& d = gd[g];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    if (gsel >= 0 && g != gsel) return;
+    const float tf = (float)st->t;
+    const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
+    if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
+    const int p = st->pS;
+    // upper-triangle tile (ti <= tj)
+    int u = b - d.mt_begin, ti = 0, T = d.mt_T;
+    while (u >= T - ti) { u -= T - ti; ++ti; }
+    const int tj = ti + u;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i0 = ti * 64, j0 = tj * 64;
+    int cnt[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cnt[a][q] = 0;
+    for (int dbase = 0; dbase < d.D; dbase += DC) {
+        const int dn = min(DC, d.D - dbase);
+        __syncthreads();
+        for (int e = threadIdx.x; e < dn * 64; e += 256) {
+            int dm = e >> 6, x = e & 63;
+            const int16_t* cr = d.c[p] + (size_t)(dbase + dm) * d.n;
+            // out-of-range vertices get distinct sentinels so they never match
+            ci[dm][x] = (i0 + x < d.n) ? cr[i0 + x] : (int16_t)-1;
+            cj[dm][x] = (j0 + x < d.n) ? cr[j0 + x] : (int16_t)-2;
+        }
+        __syncthreads();
+        for (int dm = 0; dm < dn; ++dm) {
+            int16_t a0 = ci[dm][ty * 4 + 0], a1 = ci[dm][ty * 4 + 1], a2 = ci[dm][ty * 4 + 2], a3 = ci[dm][ty * 4 + 3];
+            int16_t b0 = cj[dm][tx * 4 + 0], b1 = cj[dm][tx * 4 + 1], b2 = cj[dm][tx * 4 + 2], b3 = cj[dm][tx * 4 + 3];
+            int16_t av[4] = {a0, a1, a2, a3};
+            int16_t bv[4] = {b0, b1, b2, b3};
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
+        }
+    }
+    const bool mirror = ti != tj;
+    double ka = 0.0, vb = 0.0;
+    const bool fp32 = d.precision == kPrecFP32;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + ty * 4 + a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + tx * 4 + q;
+            float val = 0.0f;
+            if (i < d.n && j < d.n) {
+                const int m = cnt[a][q];
+                const bool edge = d.A8[(size_t)i * d.n_pad + j] != 0;
+                const bool bon = !edge && (i != j || d.bonus_diag);
+                if (edge) val = tf * d.lut_pen[m];
+                else if (bon) val = -(tf * d.lut_bon[m]);
+                if (flags & kFlagLoss) {
+                    const double wgt = mirror ? 2.0 : 1.0;
+                    if (edge) ka += wgt * d.lut_ka[m];
+                    else if (bon) vb += wgt * d.lut_vb[m];
+                }
+                if ((flags & kFlagMtOut) && mt_out) {
+                    mt_out[(size_t)i * d.n + j] = m;
+                    if (mirror) mt_out[(size_t)j * d.n + i] = m;
+                }
+            }
+            if (pen || (flags & kFlagForcePen)) {
+                if (fp32) {
+                    ((float*)d.Pop)[(size_t)i * d.n_pad + j] = val;
+                    if (mirror) ((float*)d.Pop)[(size_t)j * d.n_pad + i] = val;
+                } else {
+                    const uint16_t h = f32_to_bf16_rne(val);
+                    ((uint16_t*)d.Pop)[(size_t)i * d.n_pad + j] = h;
+                    if (mirror) ((uint16_t*)d.Pop)[(size_t)j * d.n_pad + i] = h;
+                }
+            }
+        }
+    }
+    if (flags & kFlagLoss) {
+        red[0][threadIdx.x] = ka;
+        red[1][threadIdx.x] = vb;
+        __syncthreads();
+        for (int s = 128; s >= 1; s >>= 1) {
+            if (threadIdx.x < s) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + s];
+                red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            d.part[2 * (b - d.mt_begin) + 0] = red[0][0];
+            d.part[2 * (b - d.mt_begin) + 1] = red[1][0];
+        }
+    }
+}
+
+// ------------------------------------------------------- step 2, stop rule -----
+
+// One block per graph: f_color = f2 / 2 (f2 gathered from A.S), f_eq from the
+// class sizes, f = f_color + f_eq (ECP); lowest legal member; stop rule.
+// Clears f2.  With kFlagReport only the fitness arrays are written.
+__global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd, int G, int honor_stop,
+                                                 int flags, int gsel) {
+    __shared__ int best;
+    const int g = blockIdx.x;
+    if (g >= G || (gsel >= 0 && g != gsel)) return;
+    const GraphDev& d = gd[g];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int p = st->pS;
+    if (threadIdx.x == 0) best = 0x7FFFFFFF;
+    __syncthreads();
+    for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
+        const long long fc = d.f2[m] / 2;
+        long long fe = 0;
+        if (d.problem == 1) {
+            const int32_t* V = d.V[p] + (size_t)m * d.k;
+            for (int l = 0; l < d.k; ++l) {
+                // min(|#V - c1|, |#V - c2|)
+                long long v = V[l];
+                long long x = v > d.c1 ? v - d.c1 : d.c1 - v;
+                long long y = v > d.c2 ? v - d.c2 : d.c2 - v;
+                fe += x < y ? x : y;
+            }
+        }
+        d.fcol[m] = fc;
+        d.feq[m] = fe;
+        d.f[m] = fc + fe;
+        d.f2[m] = 0;
+        if (fc + fe == 0) atomicMin(&best, m);
+    }
+    __syncthreads();
+    if (flags & kFlagReport) return;
+    const int ld = best == 0x7FFFFFFF ? -1 : best;
+    if (ld >= 0 && d.stop_on_legal) {
+        const int16_t* c = d.c[p] + (size_t)ld * d.n;
+        for (int i = threadIdx.x; i < d.n; i += blockDim.x) d.snap[i] = c[i];
+        if (threadIdx.x == 0) {
+            st->legal_d = ld;
+            st->stopped = 1;
+        }
+    }
+}
+
+// Separate-kernel path, step 4: softmax along k, straight-through gradient,
+// update and smoothing (mode 0), or gradient output without update (mode 1,
+// one graph).  16 lanes per row (d, i).
+__global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd, int G, int total_rows,
+                                                int honor_stop, int mode, int gsel,
+                                                float* __restrict__ gS_out, float* __restrict__ gW_out) {
+    const int l16 = threadIdx.x & 15;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (row >= total_rows) return;
+    const int g = graph_of_row(gd, G, row);
+    if (gsel >= 0 && g != gsel) return;
+    const GraphDev& d = gd[g];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int r = row - d.row_begin;
+    const int m = r / d.n;
+    const int k = d.k;
+    float* w = d.W[0] + (size_t)r * k;
+    const float* gs = d.G + (size_t)r * k;
+    const long long t = st->t;
+    const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+    const int32_t* V = d.V[st->pS] + (size_t)m * k;
+    float mx = -INFINITY;
+    for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
+    for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+    float z = 0.0f, q = 0.0f;
+    for (int l = l16; l < k; l += 16) {
+        float e = expf(w[l] - mx);
+        float gv = gs[l];
+        if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+        z += e;
+        q += e * gv;
+    }
+    for (int s = 8; s >= 1; s >>= 1) {
+        z += __shfl_xor(z, s, 16);
+        q += __shfl_xor(q, s, 16);
+    }
+    const float rz = 1.0f / z;
+    const float rr = q * rz;
+    const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
+    for (int l = l16; l < k; l += 16) {
+        float e = expf(w[l] - mx) * rz;
+        float gv = gs[l];
+        if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+        float gw = e * (gv - rr);
+        if (mode == 0) {
+            float nw = w[l] - d.eta * gw;
+            if (smooth) nw = nw / d.rho;
+            w[l] = nw;
+        } else {
+            if (gS_out) gS_out[(size_t)r * k + l] = gv;
+            if (gW_out) gW_out[(size_t)r * k + l] = gw;
+        }
+    }
+}
+
+// t <- t + 1 for every graph still running.
+__global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    GraphState* st = gd[g].st;
+    if (st->stopped) return;
+    st->t += 1;
+    st->steps_done += 1;
+}
+
+// FP64 loss of one graph: L = sum f_color + nu t sum f_eq + lambda t kappa - mu t varpi.
+__global__ __launch_bounds__(256) void k_loss(const GraphDev* __restrict__ gd, int g, int ntiles,
+                                              double* __restrict__ out) {
+    __shared__ double red[4][256];
+    const GraphDev& d = gd[g];
+    double ka = 0, vb = 0, sf = 0, se = 0;
+    for (int u = threadIdx.x; u < ntiles; u += 256) {
+        ka += d.part[2 * u];
+        vb += d.part[2 * u + 1];
+    }
+    for (int m = threadIdx.x; m < d.D; m += 256) {
+        sf += (double)d.fcol[m];
+        se += (double)d.feq[m];
+    }
+    red[0][threadIdx.x] = ka; red[1][threadIdx.x] = vb;
+    red[2][threadIdx.x] = sf; red[3][threadIdx.x] = se;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double t = (double)d.st->t;
+        const double eq = d.problem == 1 ? red[3][0] : 0.0;
+        out[0] = red[2][0] + (double)d.nu * t * eq + (double)d.lambda * t * red[0][0] - (double)d.mu * t * red[1][0];
+        out[1] = red[2][0];
+        out[2] = eq;
+        out[3] = red[0][0];
+        out[4] = red[1][0];
+    }
+}
+
+// copy fitness / colour outputs of one graph for tcol_conflicts
+__global__ void k_copy_report(const GraphDev* __restrict__ gd, int g, int16_t* colors, int64_t* fcol,
+                              int64_t* feq) {
+    const GraphDev& d = gd[g];
+    const int p = d.st->pS;
+    const size_t total = (size_t)d.D * d.n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        if (colors) colors[e] = d.c[p][e];
+        if (e < (size_t)d.D) {
+            if (fcol) fcol[e] = d.fcol[e];
+            if (feq) feq[e] = d.feq[e];
+        }
+    }
+}
+
+__global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_only, long long t) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G || (g_only >= 0 && g != g_only)) return;
+    GraphState* st = gd[g].st;
+    if (op == 0) {            // reset run state (keeps t)
+        st->stopped = 0; st->error = 0; st->legal_d = -1; st->steps_done = 0;
+    } else if (op == 1) {     // set t
+        st->t = t;
+    } else if (op == 2) {     // clear steps counter only
+        st->steps_done = 0; st->legal_d = -1;
+    }
+}
+
+// ------------------------------------------------------------- launchers -----
+
+#define TCOL_LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
+                             hipStream_t s) {
+    long long total = (long long)n_pad * n_pad;
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_pack_graph, dim3(blocks), dim3(256), 0, s, A, n, n_pad, prec, A8, Aop, bad);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s) {
+    if (total_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colors, dim3(ceil_div(total_rows, 16)), dim3(256), 0, s, gd, G, total_rows, honor_stop);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_class_sizes(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next,
+                              hipStream_t s) {
+    if (total_mem <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_class_sizes, dim3(total_mem), dim3(256), sizeof(int) * kmax, s, gd, G, total_mem,
+                       honor_stop, next);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3(total_blocks), dim3(256), 0, s, gd, G, total_blocks, honor_stop, next);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
+                         int32_t* mt_out, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mtilde, dim3(total_tiles), dim3(256), 0, s, gd, G, total_tiles, honor_stop, flags, gsel,
+                       mt_out);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_fitness(const GraphDev* gd, int G, int honor_stop, int flags, int gsel, hipStream_t s) {
+    hipLaunchKernelGGL(k_fitness, dim3(G), dim3(256), 0, s, gd, G, honor_stop, flags, gsel);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_stop, int mode, int gsel,
+                         float* gS_out, float* gW_out, hipStream_t s) {
+    if (total_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update, dim3(ceil_div(total_rows, 16)), dim3(256), 0, s, gd, G, total_rows, honor_stop,
+                       mode, gsel, gS_out, gW_out);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_advance(const GraphDev* gd, int G, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(ceil_div(G, 64)), dim3(64), 0, s, gd, G);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, gd, g, ntiles, out);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_report, dim3(256), dim3(256), 0, s, gd, g, colors, fcol, feq);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long t, hipStream_t s) {
+    hipLaunchKernelGGL(k_state, dim3(ceil_div(G, 64)), dim3(64), 0, s, gd, G, op, g_only, t);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace tcol

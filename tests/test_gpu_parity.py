@@ -1,0 +1,339 @@
+"""GPU parity of libtcol (through its C ABI) against the FP64 oracle.
+
+Bar: colours, conflict counts, equity fitness, the group concentration matrix
+and the stop decision bit-exact; FP32 loss, gradient and updated weights within
+1e-5 norm-wise (max |diff| <= 1e-5 max |ref| per tensor; the loss against
+sum|f_color| + nu t sum|f_eq| + lambda t |kappa| + mu t |varpi|).  BF16/FP8 runs
+keep the integer results exact; their gradient errors against FP64 are
+printed and only checked against a loose bound that catches wrong arithmetic.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tcolgen
+from tcolgen import BF16, ECP, FP8, FP32, KCOL, GraphCase
+
+from gpu_util import loss_scale, make_solver, normwise, orc_params
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def small_cases():
+    out = []
+    for prec in (FP32, BF16, FP8):
+        out.append(GraphCase(f"ragged77_kcol_p{prec}", KCOL, 77, 7, 5, prec, "gnp", 0.4, graph_seed=7,
+                             rho=10.0, lam=1e-2, mu=3e-3))
+        out.append(GraphCase(f"ragged150_ecp_p{prec}", ECP, 150, 11, 6, prec, "gnp", 0.5, graph_seed=8,
+                             rho=10.0, lam=1e-2, mu=3e-3, nu=0.05))
+    out.append(GraphCase("multi_tile300", KCOL, 300, 30, 12, FP32, "gnp", 0.5, graph_seed=9, lam=1e-3, mu=1e-4))
+    out.append(tcolgen.case_c1())
+    return out
+
+
+def ids(cases):
+    return [c.name for c in cases]
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("case", small_cases(), ids=ids(small_cases()))
+def test_conflicts_bit_exact(case):
+    s, (A,) = make_solver([case])
+    W = host(s.W[0])
+    c, fc, fe = s.conflicts(0)
+    c_ref = oracle.colors(W)
+    assert np.array_equal(host(c), c_ref)
+    assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
+    fe_ref = oracle.feq(oracle.class_sizes(c_ref, case.k), case.n) if case.problem == ECP else np.zeros(case.D)
+    assert np.array_equal(host(fe), fe_ref)
+    s.close()
+
+
+@pytest.mark.parametrize("case", small_cases(), ids=ids(small_cases()))
+def test_mtilde_bit_exact(case):
+    s, (A,) = make_solver([case])
+    M = host(s.mtilde(0))
+    assert np.array_equal(M, oracle.mtilde(oracle.colors(host(s.W[0]))))
+    s.close()
+
+
+@pytest.mark.parametrize("case", small_cases(), ids=ids(small_cases()))
+@pytest.mark.parametrize("t", [0, 3, 57])
+def test_loss_and_gradients(case, t):
+    s, (A,) = make_solver([case])
+    s.set_t(t)
+    loss, gs, gw = s.loss_grad(0)
+    W = host(s.W[0]).astype(np.float64)
+    p = orc_params(case.params())
+    c = oracle.colors(W)
+    V = oracle.class_sizes(c, case.k)
+    Mt = oracle.mtilde(c)
+    gS_ref = oracle.grad_s(p, t, A, c, Mt, V)
+    gW_ref = oracle.grad_w(W, gS_ref)
+    fc = oracle.fcolor(A, c)
+    fe = oracle.feq(V, case.n) if case.problem == ECP else np.zeros(case.D, np.int64)
+    L_ref = oracle.loss(p, t, A, Mt, fc, fe)
+    loss = host(loss)
+    eS, eW = normwise(host(gs), gS_ref), normwise(host(gw), gW_ref)
+    eL = abs(loss[0] - L_ref[0]) / loss_scale(p, t, L_ref)
+    print(f"{case.name} t={t}: gradS {eS:.2e} gradW {eW:.2e} loss {eL:.2e}")
+    assert loss[1] == L_ref[1] and loss[2] == L_ref[2]
+    assert abs(loss[3] - L_ref[3]) <= 1e-12 * max(1.0, abs(L_ref[3]))
+    assert abs(loss[4] - L_ref[4]) <= 1e-12 * max(1.0, abs(L_ref[4]))
+    if case.precision == FP32:
+        assert eS <= TOL and eW <= TOL and eL <= TOL
+    else:
+        # bf16 penalty operand: relative rounding 2^-9 per entry
+        assert eS <= 1e-2 and eW <= 1e-2 and eL <= TOL
+    s.close()
+
+
+def run_resynced(case, steps, tol, check_every=1):
+    """Step the GPU one iteration at a time; before each step feed its W to the oracle and compare."""
+    s, (A,) = make_solver([case])
+    p = orc_params(case.params())
+    t = 0
+    worst = 0.0
+    for it in range(steps):
+        W0 = host(s.W[0])
+        ref = oracle.iteration(p, t, A, W0, want_grads=False)
+        done, legal = s.step(1)
+        if ref.status == 1:
+            assert done == 0 and legal[0] == ref.legal_d
+            assert np.array_equal(host(s.W[0]), W0)
+            break
+        assert done == 1 and legal[0] == -1
+        W1 = host(s.W[0])
+        e = normwise(W1, ref.W)
+        worst = max(worst, e)
+        assert e <= tol, (it, e)
+        if it % check_every == 0:
+            c, fc, fe = s.conflicts(0)
+            c_ref = oracle.colors(W1)
+            assert np.array_equal(host(c), c_ref)
+            assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
+        t += 1
+        assert s.get_t() == t
+    s.close()
+    return worst
+
+
+def test_c1_resynced_200_steps():
+    worst = run_resynced(tcolgen.case_c1(), 200, TOL, check_every=10)
+    print(f"C1 worst W error {worst:.2e}")
+
+
+@pytest.mark.parametrize("prec", [BF16, FP8])
+def test_small_resynced_low_precision(prec):
+    case = GraphCase("kcol90", KCOL, 90, 9, 6, prec, "gnp", 0.5, graph_seed=12, rho=10.0, lam=1e-2, mu=3e-3)
+    # bf16 penalty operand: errors against FP64 are reported; the bound only catches wrong arithmetic
+    worst = run_resynced(case, 30, 1e-2)
+    print(f"prec {prec}: worst W error vs FP64 {worst:.2e}")
+
+
+def test_c2_resynced_steps():
+    worst = run_resynced(tcolgen.case_c2(FP32), 12, TOL, check_every=4)
+    print(f"C2 worst W error {worst:.2e}")
+
+
+def test_planted_stops_at_step0():
+    case = tcolgen.case_c3(FP8)
+    P = tcolgen.planted(case.n, case.k, case.graph_seed)
+    W = case.weights()
+    W[5, np.arange(case.n), P.classes] += 1.0     # member 5 holds the hidden legal colouring
+    for prec in (FP8, BF16, FP32):
+        case.precision = prec
+        s, _ = make_solver([case], As=[P.A], Ws=[W])
+        c, fc, fe = s.conflicts(0)
+        assert int(host(fc)[5]) == 0
+        c_ref = oracle.colors(W)
+        assert np.array_equal(host(fc), oracle.fcolor(P.A, c_ref))
+        col = __import__("torch").zeros(case.n, dtype=__import__("torch").int16, device="cuda")
+        done, legal = s.step(10, colors_out=[col])
+        assert done == 0 and legal == [5]
+        assert np.array_equal(host(col), P.classes)
+        assert np.array_equal(host(s.W[0]), W)
+        s.close()
+
+
+def test_edge_cases():
+    torch = __import__("torch")
+    # k = 1: every edge conflicts; D = 1
+    case = GraphCase("k1", KCOL, 40, 1, 1, FP32, "gnp", 0.3, graph_seed=3)
+    s, (A,) = make_solver([case])
+    c, fc, fe = s.conflicts(0)
+    assert int(host(fc)[0]) == int(A.sum() // 2)
+    s.close()
+    # n = 1, empty graph: legal at once
+    case = GraphCase("n1", KCOL, 1, 3, 2, BF16, "gnp", 0.5)
+    s, _ = make_solver([case])
+    assert s.step(5) == (0, [0])
+    s.close()
+    # complete graph with k = n (legal colourings exist); one member coloured legally
+    n = 20
+    A = (np.ones((n, n)) - np.eye(n)).astype(np.uint8)
+    W = np.zeros((3, n, n), np.float32)
+    W[1, np.arange(n), np.arange(n)] = 1.0
+    W[0, :, 0] = 1.0
+    case = GraphCase("Kn", KCOL, n, n, 3, FP8, "gnp", 1.0)
+    s, _ = make_solver([case], As=[A], Ws=[W])
+    c, fc, fe = s.conflicts(0)
+    assert host(fc).tolist() == [n * (n - 1) // 2, 0, n * (n - 1) // 2]   # member 2: all-zero W ties -> colour 0
+    s.close()
+
+
+def test_nonfinite_and_bad_graph():
+    import paper_1909_02261_amd as pk
+    torch = __import__("torch")
+    case = GraphCase("nan", KCOL, 50, 5, 4, FP32, "gnp", 0.5, graph_seed=4)
+    W = case.weights()
+    W[2, 7, 3] = np.nan
+    s, _ = make_solver([case], Ws=[W])
+    with pytest.raises(pk.TcolError) as ei:
+        s.step(3)
+    assert ei.value.status == -5
+    s.close()
+    A = case.adjacency()
+    A[0, 1] = 1
+    A[1, 0] = 0
+    with pytest.raises(pk.TcolError) as ei:
+        make_solver([case], As=[A])
+    assert ei.value.status == -3
+
+
+def test_graph_replay_matches_eager_and_is_deterministic():
+    case = GraphCase("det", KCOL, 200, 20, 8, BF16, "gnp", 0.5, graph_seed=5, rho=10.0, lam=1e-3, mu=1e-4,
+                     stop_on_legal=0)
+    outs = []
+    for use_graph, unroll in ((0, 1), (1, 4), (1, 8)):
+        s, _ = make_solver([case], use_graph=use_graph, unroll=unroll)
+        done, _ = s.step(23)
+        assert done == 23 and s.get_t() == 23
+        outs.append(host(s.W[0]).copy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_checkpoint_resume():
+    torch = __import__("torch")
+    case = GraphCase("ckpt", ECP, 120, 10, 6, FP32, "gnp", 0.5, graph_seed=6, rho=10.0, nu=1e-3, mu=0.0,
+                     lam=1e-3, stop_on_legal=0)
+    s, _ = make_solver([case])
+    s.step(20)
+    W_full = host(s.W[0]).copy()
+    s.close()
+    s, _ = make_solver([case])
+    s.step(10)
+    W_mid = s.W[0].clone()
+    t_mid = s.get_t()
+    s.close()
+    s2, _ = make_solver([case], Ws=[host(W_mid)])
+    s2.set_t(t_mid)
+    s2.step(10)
+    assert np.array_equal(host(s2.W[0]), W_full)
+    s2.close()
+
+
+def test_batch_of_uneven_graphs_matches_separate_contexts():
+    cases = [GraphCase("b0", KCOL, 130, 12, 4, BF16, "gnp", 0.5, graph_seed=21, lam=1e-3, mu=1e-4, stop_on_legal=0),
+             GraphCase("b1", ECP, 257, 19, 3, BF16, "gnp", 0.1, graph_seed=22, mu=0.0, nu=1e-3, stop_on_legal=0),
+             GraphCase("b2", KCOL, 64, 30, 7, BF16, "gnp", 0.9, graph_seed=23, alpha=1.5, stop_on_legal=0)]
+    sb, _ = make_solver(cases)
+    sb.step(9)
+    batch_W = [host(w).copy() for w in sb.W]
+    batch_f = [host(sb.conflicts(g)[1]) for g in range(3)]
+    sb.close()
+    for g, c in enumerate(cases):
+        s1, _ = make_solver([c])
+        s1.step(9)
+        assert np.array_equal(host(s1.W[0]), batch_W[g])
+        assert np.array_equal(host(s1.conflicts(0)[1]), batch_f[g])
+        s1.close()
+
+
+def test_autograd_backward_matches_step_and_finite_differences():
+    torch = __import__("torch")
+    import paper_1909_02261_amd as pk
+    case = tcolgen.case_c2(FP32)
+    case.nb_iter = 1000   # no smoothing in the compared step
+    s, (A,) = make_solver([case])
+    s.set_t(4)
+    W = s.W[0]
+    W.requires_grad_(True)
+    L = pk.TensColLoss.apply(W, s, 0)
+    L.backward()
+    grad = W.grad.detach().clone()
+    W.requires_grad_(False)
+    W.grad = None
+    # oracle gradient
+    p = orc_params(case.params())
+    Wh = host(W).astype(np.float64)
+    c = oracle.colors(Wh)
+    gS_ref = oracle.grad_s(p, 4, A, c, oracle.mtilde(c), oracle.class_sizes(c, case.k))
+    gW_ref = oracle.grad_w(Wh, gS_ref)
+    assert normwise(host(grad), gW_ref) <= TOL
+    # central differences (h = 1e-3, FP64) of the surrogate sum_l G_l softmax(w)_l with G frozen
+    _, gs, _ = s.loss_grad(0)
+    G = host(gs).astype(np.float64)
+    h = 1e-3
+    for (d, i, j) in tcolgen.fd_entries(32, case.D, case.n, case.k, seed=2):
+        w = Wh[d, i].copy()
+
+        def phi(x):
+            e = np.exp(x - x.max())
+            return float((G[d, i] * e / e.sum()).sum())
+        wp, wm = w.copy(), w.copy()
+        wp[j] += h
+        wm[j] -= h
+        fd = (phi(wp) - phi(wm)) / (2 * h)
+        assert abs(fd - float(host(grad)[d, i, j])) <= 1e-4 * max(1e-3, abs(fd)) + 1e-6
+    # W - eta * grad equals the library's own update step
+    W_exp = host(W) - np.float32(case.eta) * host(grad)
+    s.step(1)
+    assert normwise(host(s.W[0]), W_exp) <= 1e-6
+    s.close()
+
+
+@pytest.mark.parametrize("mk", [lambda: tcolgen.case_c4(BF16), lambda: tcolgen.case_c3(FP8), lambda: tcolgen.case_c3(BF16)],
+                         ids=["C4_ecp_bf16", "C3_fp8", "C3_bf16"])
+def test_full_size_conflicts_and_equity_exact(mk):
+    case = mk()
+    s, (A,) = make_solver([case])
+    for it in range(3):
+        c, fc, fe = s.conflicts(0)
+        W = host(s.W[0])
+        c_ref = oracle.colors(W)
+        assert np.array_equal(host(c), c_ref)
+        assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
+        if case.problem == ECP:
+            assert np.array_equal(host(fe), oracle.feq(oracle.class_sizes(c_ref, case.k), case.n))
+        s.step(7)
+    s.close()
+
+
+def test_c5_full_size_fp8():
+    case = tcolgen.case_c5(FP8)
+    s, (A,) = make_solver([case])
+    s.set_t(100)
+    c, fc, fe = s.conflicts(0)
+    W = host(s.W[0])
+    c_ref = oracle.colors(W)
+    assert np.array_equal(host(c), c_ref)
+    assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
+    # sampled gradient rows against the oracle (bf16 penalty operand: reported, loosely bounded)
+    loss, gs, gw = s.loss_grad(0)
+    p = orc_params(case.params())
+    Mt = oracle.mtilde(c_ref)
+    assert np.array_equal(host(s.mtilde(0)), Mt)
+    V = oracle.class_sizes(c_ref, case.k)
+    gS_ref = oracle.grad_s(p, 100, A, c_ref, Mt, V)
+    eS = normwise(host(gs), gS_ref)
+    eW = normwise(host(gw), oracle.grad_w(W.astype(np.float64), gS_ref))
+    print(f"C5 fp8: gradS {eS:.2e} gradW {eW:.2e}")
+    assert eS <= 1e-2 and eW <= 1e-2
+    s.close()
