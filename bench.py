@@ -85,11 +85,13 @@ def cpu_baseline(case, A, W0, budget_s: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=list(PREC))
-    ap.add_argument("--path", default="separate", choices=["separate", "fused"])
+    ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
+    ap.add_argument("--penalty", default="auto", choices=["auto", "dense", "sparse"])
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -115,8 +117,12 @@ def main():
     Wt = torch.from_numpy(W0).to(dev)
     At = torch.from_numpy(A).to(dev)
     s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
-    s.set_options(use_graph=0 if args.no_graph else 1, fused=1 if args.path == "fused" else 0,
-                  tile_bm=args.tile_bm, tile_ntw=args.tile_ntw)
+    s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
+                  tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
+                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
+    if args.autotune:
+        print("[bench] autotuning tile shape / penalty mode", file=sys.stderr, flush=True)
+        s.autotune()
     opts = s.options()
     print(f"[bench] options {opts}; warmup {args.warmup}", file=sys.stderr, flush=True)
     s.step(args.warmup)
@@ -170,7 +176,8 @@ def main():
         "data": "synthetic (seeded Philox G(n,p) graph and N(0, 0.01^2) weights)",
         "config": {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
                    "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
-                   "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"]},
+                   "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
+                   "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]},
         "roofline": roof,
         "roofline_as_only": roof_as,
         "phases_ms": ph,

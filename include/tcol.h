@@ -89,12 +89,24 @@ typedef struct {
 
 /* Execution options of a context. */
 typedef struct {
-    int32_t fused;          /* 1: one GEMM kernel per step that also applies softmax, gradient,
-                               update and the next argmax (default); 0: separate kernels */
+    int32_t fused;          /* step schedule: 0 = plain path (argmax, dense penalty operand,
+                               contraction, update as separate kernels every iteration);
+                               1 = fast path (default): penalty rows from the sparse kernel when
+                               chosen, the update kernel also colours the updated rows, no
+                               separate argmax pass (k <= 288, else the plain order);
+                               2 = epilogue path: the contraction kernel itself applies softmax,
+                               gradient, update and the next argmax, into a second weight
+                               buffer (k <= 288) */
     int32_t use_graph;      /* 1: replay each step from a captured hipGraph (default) */
     int32_t unroll;         /* steps per captured graph (1..64, default 8) */
-    int32_t tile_bm;        /* GEMM rows per block: 64 or 128; 0 = autotuned/default */
-    int32_t tile_ntw;       /* GEMM 16-column subtiles per wave (2..18); 0 = autotuned/default */
+    int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */
+    int32_t tile_ntw;       /* GEMM 16-column subtiles per wave; the instantiated (tile_bm, tile_ntw)
+                               pairs are (64,2) (64,4) (128,4) (128,8) (64,9) (128,9) (256,4) */
+    int32_t penalty;        /* fused path, penalty term (A o Mt^(alpha-1) and (J-A) o Mt^(beta-1)
+                               times S): 0 = choose per graph (default), 1 = dense operand pass on
+                               MFMA, 2 = sparse pair lists in FP32 whenever they fit (the penalty
+                               operand is non-zero only where two vertices share a colour in some
+                               member, so it is sparse when D is small against k) */
 } tcol_options;
 
 typedef struct tcol_ctx tcol_ctx;

@@ -25,7 +25,7 @@ class GraphParams(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("tile_bm", ctypes.c_int32), ("tile_ntw", ctypes.c_int32)]
+                ("tile_bm", ctypes.c_int32), ("tile_ntw", ctypes.c_int32), ("penalty", ctypes.c_int32)]
 
 
 class TcolError(RuntimeError):

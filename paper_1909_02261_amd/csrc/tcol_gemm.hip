@@ -11,8 +11,11 @@
 // Layout: 256 threads = 4 waves as 2 (rows) x 2 (columns); block tile BM x BN
 // with BN = 32 * NTW; each wave owns (BM/2) x (16 NTW) as 16x16 MFMA subtiles.
 // Both operands are K-contiguous; a K-stage moves 128 bytes of every operand
-// row into LDS (stride 144 B), double buffered, prefetching the next stage
-// into registers while the current one feeds the MFMAs.
+// row straight from global memory into LDS (global_load_lds, 16 bytes per
+// lane, no registers on the way), double buffered: the loads of stage s+1 are
+// in flight while stage s feeds the MFMAs.  Within a 128-byte LDS row the
+// 16-byte chunk c of row r sits in slot c ^ (r mod 8), so the fragment reads of
+// 8 consecutive rows hit 8 different bank groups.
 //
 // Mode 0 stores G as [D][n][k] fp32 for the separate update kernel.
 // Mode 1 (fused): column tiles hold whole members; the accumulators go through
@@ -45,30 +48,32 @@ template <int BM, int NTW>
 struct Tile {
     static constexpr int BN = 32 * NTW;
     static constexpr int MT = BM / 32;                       // 16-row subtiles per wave
-    static constexpr int STAGE = (BM + BN) * kLdsStride;     // bytes per LDS stage
-    static constexpr int NCH = (BM + BN) * 8 / 256;          // 16-byte chunks per thread per stage
-    static_assert((BM + BN) * 8 % 256 == 0, "chunk split");
+    static constexpr int STAGE = (BM + BN) * kStageRowBytes; // bytes per LDS stage
+    static constexpr int GROUPS = (BM + BN) / 32;            // 8-row load groups per wave per stage
+    static_assert((BM + BN) % 32 == 0, "load split");
 };
 
-// compute one LDS stage into acc (operand format PREC)
+// compute one LDS stage into acc (operand format PREC); chunk c of row r is at slot c ^ (r & 7)
 template <int PREC, int BM, int NTW>
 __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, int lane, int wm, int wn) {
     constexpr int MT = BM / 32;
     const int ra = wm * (BM / 2) + (lane & 15);
     const int rb = BM + wn * (NTW * 16) + (lane & 15);
     const int q = lane >> 4;
+    const int swz = lane & 7;          // = row & 7 for every row this lane reads
     if constexpr (PREC == kPrecFP8) {
+        const int o0 = ((2 * q) ^ swz) * 16, o1 = ((2 * q + 1) ^ swz) * 16;
         i32x8 a[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const uint4* p = (const uint4*)(L + (ra + mt * 16) * kLdsStride + q * 32);
-            uint4 x0 = p[0], x1 = p[1];
+            const uint8_t* p = L + (ra + mt * 16) * kStageRowBytes;
+            const uint4 x0 = *(const uint4*)(p + o0), x1 = *(const uint4*)(p + o1);
             a[mt] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
         }
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
-            const uint4* p = (const uint4*)(L + (rb + nt * 16) * kLdsStride + q * 32);
-            uint4 x0 = p[0], x1 = p[1];
+            const uint8_t* p = L + (rb + nt * 16) * kStageRowBytes;
+            const uint4 x0 = *(const uint4*)(p + o0), x1 = *(const uint4*)(p + o1);
             i32x8 b{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_fp8(a[mt], b, acc[mt][nt]);
@@ -76,13 +81,13 @@ __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, i
     } else if constexpr (PREC == kPrecBF16) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
+            const int o = ((ks * 4 + q) ^ swz) * 16;
             bf16x8 a[MT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                a[mt] = *(const bf16x8*)(L + (ra + mt * 16) * kLdsStride + ks * 64 + q * 16);
+            for (int mt = 0; mt < MT; ++mt) a[mt] = *(const bf16x8*)(L + (ra + mt * 16) * kStageRowBytes + o);
 #pragma unroll
             for (int nt = 0; nt < NTW; ++nt) {
-                bf16x8 b = *(const bf16x8*)(L + (rb + nt * 16) * kLdsStride + ks * 64 + q * 16);
+                bf16x8 b = *(const bf16x8*)(L + (rb + nt * 16) * kStageRowBytes + o);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(a[mt], b, acc[mt][nt]);
             }
@@ -92,13 +97,13 @@ __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, i
         // use the same k order, so the sum is the plain product
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
+            const int o = ((ks * 4 + q) ^ swz) * 16;
             float4 a[MT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                a[mt] = *(const float4*)(L + (ra + mt * 16) * kLdsStride + ks * 64 + q * 16);
+            for (int mt = 0; mt < MT; ++mt) a[mt] = *(const float4*)(L + (ra + mt * 16) * kStageRowBytes + o);
 #pragma unroll
             for (int nt = 0; nt < NTW; ++nt) {
-                float4 b = *(const float4*)(L + (rb + nt * 16) * kLdsStride + ks * 64 + q * 16);
+                float4 b = *(const float4*)(L + (rb + nt * 16) * kStageRowBytes + o);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     acc[mt][nt] = mfma_f32(a[mt].x, b.x, acc[mt][nt]);
@@ -111,30 +116,30 @@ __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, i
     }
 }
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(1))) u32x4 gbl_u32x4;
+typedef const __attribute__((address_space(1))) void* gbl_ptr;
+typedef __attribute__((address_space(3))) void* lds_ptr;
 
-template <int BM, int NCH>
-__device__ __forceinline__ void stage_gload(u32x4 (&pre)[NCH], const uint8_t* __restrict__ Arow,
-                                            const uint8_t* __restrict__ Brow, size_t ld, int s, int tid) {
+// Issue the direct-to-LDS loads of one K-stage.  Wave w moves the 8-row groups
+// w, w+4, ...; lane L of a group writes LDS bytes [16L, 16L+16) of the group, i.e.
+// row L/8, slot L%8, which receives global chunk (L%8) ^ (row & 7).
+template <int BM, int NTW>
+__device__ __forceinline__ void stage_load(const uint8_t* __restrict__ Arow, const uint8_t* __restrict__ Brow,
+                                           size_t ld, int s, uint8_t* buf, int lane, int wave) {
+    using T = Tile<BM, NTW>;
+    const int rsub = lane >> 3, slot = lane & 7;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int ch = tid + c * 256;
-        const int row = ch >> 3, part = ch & 7;
-        const uint8_t* src = row < BM ? Arow + (size_t)row * ld : Brow + (size_t)(row - BM) * ld;
-        pre[c] = *(gbl_u32x4*)(src + (size_t)s * kStageRowBytes + part * 16);
+    for (int gi = 0; gi < T::GROUPS; ++gi) {
+        const int grp = wave + 4 * gi;
+        const int r = grp * 8 + rsub;
+        const int c = slot ^ (r & 7);
+        const uint8_t* src = (r < BM ? Arow + (size_t)r * ld : Brow + (size_t)(r - BM) * ld) +
+                             (size_t)s * kStageRowBytes + c * 16;
+        __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(buf + grp * 8 * kStageRowBytes), 16, 0, 0);
     }
 }
 
-template <int NCH>
-__device__ __forceinline__ void stage_lstore(const u32x4 (&pre)[NCH], uint8_t* buf, int tid) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int ch = tid + c * 256;
-        const int row = ch >> 3, part = ch & 7;
-        *(u32x4*)(buf + row * kLdsStride + part * 16) = pre[c];
-    }
-}
+// vmcnt(0): this wave's loads, including those that write LDS, have landed
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // One K-sweep: acc += Arows[m0.., :] . Brows[n0.., :]^T over `nstages` stages
 // of 128 bytes.  Arow / Brow point at the first row of the tile; ld in bytes.
@@ -146,16 +151,15 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[BM / 32][NTW], const uin
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    u32x4 pre[T::NCH];
-    stage_gload<BM, T::NCH>(pre, Arow, Brow, ld, 0, tid);
-    stage_lstore<T::NCH>(pre, lds, tid);
+    stage_load<BM, NTW>(Arow, Brow, ld, 0, lds, lane, wave);
+    wait_vm();
     __syncthreads();
     for (int s = 0; s < nstages; ++s) {
         const int buf = s & 1;
         // the last iteration reloads its own stage into the idle buffer; nobody reads it
-        stage_gload<BM, T::NCH>(pre, Arow, Brow, ld, min(s + 1, nstages - 1), tid);
+        stage_load<BM, NTW>(Arow, Brow, ld, min(s + 1, nstages - 1), lds + (buf ^ 1) * T::STAGE, lane, wave);
         stage_mma<PREC, BM, NTW>(acc, lds + buf * T::STAGE, lane, wm, wn);
-        stage_lstore<T::NCH>(pre, lds + (buf ^ 1) * T::STAGE, tid);
+        wait_vm();
         __syncthreads();
     }
 }
@@ -170,16 +174,17 @@ __device__ inline int xcd_remap(int b, int nb) {
     return x * q + min(x, r) + i;
 }
 
-template <int BM, int NTW>
+template <int MODE>
 __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, int& tm, int& tn) {
-    g = find_graph(gd, G, tile, [](const GraphDev& x) { return x.gm_begin; });
+    g = find_graph(gd, G, tile, [](const GraphDev& x) { return x.gm_begin[MODE]; });
     const GraphDev& d = gd[g];
-    const int local = tile - d.gm_begin;
+    const int local = tile - d.gm_begin[MODE];
+    const int TM = d.gm_tm[MODE], TN = d.gm_tn[MODE];
     // groups of 4 row tiles sweep the column tiles together
     constexpr int GM = 4;
-    const int per_group = GM * d.gm_tn;
+    const int per_group = GM * TN;
     const int grp = local / per_group;
-    const int rows_in = min(GM, d.gm_tm - grp * GM);
+    const int rows_in = min(GM, TM - grp * GM);
     const int w = local - grp * per_group;
     tm = grp * GM + w % rows_in;
     tn = w / rows_in;
@@ -187,7 +192,7 @@ __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, 
 
 template <int PREC, int BM, int NTW, int MODE>
 __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, int G, int total_tiles,
-                                              int honor_stop, int passes) {
+                                              int honor_stop, int passes, int cstage) {
     using T = Tile<BM, NTW>;
     constexpr int MT = T::MT;
     constexpr int BN = T::BN;
@@ -196,21 +201,26 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
 
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     int g, tm, tn;
-    decode_tile<BM, NTW>(gd, G, tile, g, tm, tn);
+    decode_tile<MODE>(gd, G, tile, g, tm, tn);
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     const int pS = st->pS;
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
+    // a graph takes either the dense operand pass or the penalty rows of the sparse
+    // kernel (already in G); the plain path (passes bit 3) always takes the dense pass
+    const bool sparse_pen = pen && d.sparse && !(passes & 8);
+    const bool dense_pen = pen && !sparse_pen;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = tm * BM;
-    // column range of the tile in the flattened (d, l) space
-    int n0, ncol_end;
+    // column range of the tile in the flattened (member, colour) space
+    int n0, ncol_end, d0 = 0;
     if (MODE == 1) {
-        n0 = tn * d.gm_mpb * d.k;
+        d0 = tn * d.gm_mpb;
+        n0 = d0 * d.k;
         ncol_end = min(d.ncols, n0 + d.gm_mpb * d.k);
     } else {
         n0 = tn * BN;
@@ -256,7 +266,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 if (i < d.n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt) {
-                        if (cm[nt] >= 0 && d.c[pS][(size_t)cm[nt] * d.n + i] == cl[nt])
+                        if (cm[nt] >= 0 && d.c[pS][(size_t)cm[nt] * d.cs + i] == cl[nt])
                             atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
                     }
                 }
@@ -266,7 +276,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
         for (int e = tid; e <= dlast - dfirst; e += 256)
             if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);
     }
-    if ((passes & 2) && pen) {
+    if ((passes & 2) && dense_pen) {
         __syncthreads();
         if constexpr (PREC == kPrecFP8) {
             const size_t ld2 = (size_t)d.n_pad * 2;
@@ -289,59 +299,169 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 if (i < d.n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
-                        if (cm[nt] >= 0)
-                            d.G[((size_t)cm[nt] * d.n + i) * d.k + cl[nt]] = acc[mt][nt][r];
+                        if (cm[nt] >= 0) {
+                            float* gp = d.G + ((size_t)cm[nt] * d.n + i) * d.k + cl[nt];
+                            *gp = sparse_pen ? acc[mt][nt][r] + *gp : acc[mt][nt][r];
+                        }
                 }
             }
+    } else {
+        // ---- fused epilogue: the tile's gradient rows go through LDS, at most 128 rows at a time ----
+        constexpr int EPI = BM < 128 ? BM : 128;
+        constexpr int LDG = BN + 4;
+        float* Gt = (float*)lds;
+        const int k = d.k, n = d.n;
+        const int nmem = min(d.gm_mpb, d.D - d0);
+        const int g16 = tid >> 4, l16 = tid & 15;
+        const long long t = st->t;
+        const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+        const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
+        const int pW = st->pW;
+        const float* Wc = d.W[pW];
+        float* Wn = d.W[pW ^ 1];
+        int16_t* cn = d.c[pS ^ 1];
+#pragma unroll 1
+        for (int h = 0; h < BM / EPI; ++h) {
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
+                        const int col = wn * (NTW * 16) + nt * 16 + (lane & 15);
+                        if (row / EPI == h) Gt[(row - h * EPI) * LDG + col] = acc[mt][nt][r];
+                    }
+            __syncthreads();
+            // rows (member, vertex): softmax along k, straight-through gradient, update,
+            // smoothing, and the argmax colouring of the updated weights
+            for (int rr = g16; rr < EPI * nmem; rr += 16) {
+                const int r = rr % EPI, dm = rr / EPI;
+                const int i = m0 + h * EPI + r;
+                if (i >= n) continue;
+                const int dd = d0 + dm;
+                const size_t rowoff = ((size_t)dd * n + i) * k;
+                const float* w = Wc + rowoff;
+                float* wo = Wn + rowoff;
+                const float* gr = Gt + r * LDG + dm * k;
+                const float* g1 = d.G + rowoff;      // penalty rows of the sparse kernel
+                const int32_t* V = d.V[pS] + (size_t)dd * k;
+                float mx = -INFINITY;
+                for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
+                for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+                float z = 0.0f, q = 0.0f;
+                for (int l = l16; l < k; l += 16) {
+                    const float e = expf(w[l] - mx);
+                    float gv = gr[l];
+                    if (sparse_pen) gv += g1[l];
+                    if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+                    z += e;
+                    q += e * gv;
+                }
+                for (int s = 8; s >= 1; s >>= 1) {
+                    z += __shfl_xor(z, s, 16);
+                    q += __shfl_xor(q, s, 16);
+                }
+                const float rz = 1.0f / z;
+                const float rq = q * rz;
+                float best = -INFINITY;
+                int bi = 0x7FFFFFFF, bad = 0;
+                for (int l = l16; l < k; l += 16) {
+                    const float e = expf(w[l] - mx) * rz;
+                    float gv = gr[l];
+                    if (sparse_pen) gv += g1[l];
+                    if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+                    float nw = w[l] - d.eta * (e * (gv - rq));
+                    if (smooth) nw = nw / d.rho;
+                    wo[l] = nw;
+                    if ((__float_as_uint(nw) & 0x7F800000u) == 0x7F800000u) bad = 1;
+                    if (nw > best) { best = nw; bi = l; }
+                }
+                for (int s = 8; s >= 1; s >>= 1) {
+                    const float ob = __shfl_xor(best, s, 16);
+                    const int oi = __shfl_xor(bi, s, 16);
+                    bad |= __shfl_xor(bad, s, 16);
+                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+                }
+                if (l16 == 0) {
+                    if (bad || bi >= k) {
+                        bi = 0;
+                        atomicExch(&st->next_bad, 1);
+                    }
+                    cn[(size_t)dd * d.cs + i] = (int16_t)bi;
+                }
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------- dispatch ------
 
-template <int PREC, int BM, int NTW, int MODE>
-static size_t lds_bytes() {
-    return 2 * Tile<BM, NTW>::STAGE + sizeof(int) * (Tile<BM, NTW>::BN + 2);
+constexpr int kMaxLds = 160 * 1024;
+
+template <int BM, int NTW, int MODE>
+static size_t lds_bytes(int cstage) {
+    using T = Tile<BM, NTW>;
+    const size_t sweep = 2 * T::STAGE + sizeof(int) * (T::BN + 2);
+    if (MODE == 0) return sweep;
+    const size_t epi = (size_t)(BM < 128 ? BM : 128) * (T::BN + 4) * sizeof(float) + (size_t)cstage;
+    return sweep > epi ? sweep : epi;
 }
 
 template <int PREC, int BM, int NTW, int MODE>
 static hipError_t prep_one() {
     return hipFuncSetAttribute((const void*)k_gemm<PREC, BM, NTW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes<PREC, BM, NTW, MODE>());
+                               kMaxLds);
 }
 
 template <int PREC, int BM, int NTW, int MODE>
-static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int honor_stop, int passes, hipStream_t s) {
-    const size_t shm = lds_bytes<PREC, BM, NTW, MODE>();
-    k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop, passes);
+static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int honor_stop, int passes, int cstage,
+                             hipStream_t s) {
+    const size_t shm = lds_bytes<BM, NTW, MODE>(cstage);
+    if (shm > (size_t)kMaxLds) return hipErrorInvalidValue;
+    k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop, passes,
+                                                                         cstage);
     return hipGetLastError();
 }
 
 // instantiated tile shapes: (BM, NTW)
 #define TCOL_GEMM_SHAPES(X, PREC, MODE) \
     X(PREC, 64, 2, MODE) X(PREC, 64, 4, MODE) X(PREC, 128, 4, MODE) X(PREC, 128, 8, MODE) X(PREC, 64, 9, MODE) \
-    X(PREC, 128, 9, MODE)
+    X(PREC, 128, 9, MODE) X(PREC, 256, 4, MODE)
 
 #define TCOL_GEMM_CASE(PREC, BM, NTW, MODE)                                                             \
     if (s.prec == PREC && s.bm == BM && s.ntw == NTW && s.mode == MODE) {                               \
         if (op == 0) return hipSuccess;                                                                 \
         if (op == 1) return prep_one<PREC, BM, NTW, MODE>();                                             \
-        return launch_one<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, st);            \
+        if (op == 3) { *lds_out = lds_bytes<BM, NTW, MODE>(cstage); return hipSuccess; }                 \
+        return launch_one<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, cstage, st);     \
     }
 
 static hipError_t gemm_dispatch(int op, const GemmShape& s, const GraphDev* gd, int G, int total_tiles,
-                                int honor_stop, int passes, hipStream_t st) {
+                                int honor_stop, int passes, int cstage, hipStream_t st, size_t* lds_out) {
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP32, 0)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecBF16, 0)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP8, 0)
+    TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP32, 1)
+    TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecBF16, 1)
+    TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP8, 1)
     return hipErrorInvalidValue;
 }
 
-bool gemm_supported(const GemmShape& s) { return gemm_dispatch(0, s, nullptr, 0, 0, 0, 0, nullptr) == hipSuccess; }
-hipError_t gemm_prepare(const GemmShape& s) { return gemm_dispatch(1, s, nullptr, 0, 0, 0, 0, nullptr); }
+bool gemm_supported(const GemmShape& s) {
+    return gemm_dispatch(0, s, nullptr, 0, 0, 0, 0, 0, nullptr, nullptr) == hipSuccess;
+}
+hipError_t gemm_prepare(const GemmShape& s) { return gemm_dispatch(1, s, nullptr, 0, 0, 0, 0, 0, nullptr, nullptr); }
 hipError_t launch_gemm(const GemmShape& s, const GraphDev* gd, int G, int total_tiles, int honor_stop, int passes,
-                       hipStream_t st) {
+                       int cstage, hipStream_t st) {
     if (total_tiles <= 0) return hipSuccess;
-    return gemm_dispatch(2, s, gd, G, total_tiles, honor_stop, passes, st);
+    return gemm_dispatch(2, s, gd, G, total_tiles, honor_stop, passes, cstage, st, nullptr);
+}
+size_t gemm_lds_bytes(const GemmShape& s, int cstage) {
+    size_t b = 0;
+    if (gemm_dispatch(3, s, nullptr, 0, 0, 0, 0, cstage, nullptr, &b) != hipSuccess) return 0;
+    return b;
 }
 int gemm_bn(int ntw) { return 32 * ntw; }
 

@@ -4,9 +4,19 @@
 // workspace (caller-provided or allocated here): a head with the descriptor
 // and state arrays of all graphs, then one region per graph.  Each launch in a
 // step covers every graph of the context through flattened work indices, and
-// the step sequence can be captured once into a hipGraph and replayed, since
-// every kernel reads the iteration counter and the stop flags from device
-// memory.
+// the step sequence is captured once into a hipGraph and replayed, since every
+// kernel reads the iteration counter, the buffer parities and the stop flags
+// from device memory.
+//
+// Three step sequences (tcol_options.fused):
+//   0 plain: colours -> classes -> one-hot S -> dense penalty operand -> contraction
+//     storing G -> fitness / stop -> update -> counter;
+//   1 fast: classes -> penalty rows (sparse kernel) or dense operand -> one-hot S ->
+//     contraction storing G -> fitness / stop -> update that also colours the new rows
+//     -> counter (the colours of the first iteration come from one argmax pass);
+//   2 epilogue: classes -> penalty -> one-hot S -> contraction whose epilogue updates W
+//     into the second buffer and colours the result -> fitness / stop, which accepts
+//     the update by flipping the buffers.
 #include "tcol_internal.h"
 #include "tcol_launch.h"
 #include "../../include/tcol.h"
@@ -23,11 +33,12 @@ using namespace tcol;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxLdsBytes = 160 * 1024;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_COUNT
 };
 
 struct Layout {
@@ -58,13 +69,14 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_POP] = n2 * (p.precision == TCOL_FP32 ? 4 : 2);
     sz[B_S0] = sz[B_S1] = (size_t)L.rows_S * L.n_pad * L.eb;
     sz[B_SP0] = sz[B_SP1] = p.precision == TCOL_FP8 ? (size_t)L.rows_S * L.n_pad * 2 : 0;
-    sz[B_C0] = sz[B_C1] = sizeof(int16_t) * ((size_t)p.D * p.n + 64);
+    sz[B_C0] = sz[B_C1] = sizeof(int16_t) * ((size_t)p.D * round_up(p.n, 64) + 64);
     sz[B_V0] = sz[B_V1] = sizeof(int32_t) * (size_t)p.D * p.k;
     sz[B_G] = sizeof(float) * dnk;
     sz[B_F2] = sizeof(int32_t) * p.D;
     sz[B_FCOL] = sz[B_FEQ] = sz[B_F] = sizeof(int64_t) * p.D;
     sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
     sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
+    sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -86,10 +98,14 @@ tcol_status check_params(const tcol_graph_params& p) {
     if (p.lambda > 0.0f && !(p.alpha > 1.0f)) return TCOL_EINVAL;
     if (p.mu > 0.0f && !(p.beta > 1.0f)) return TCOL_EINVAL;
     if (!isfinite(p.alpha) || !isfinite(p.beta) || !isfinite(p.eta) || !isfinite(p.rho)) return TCOL_EINVAL;
+    if (!isfinite(p.lambda) || !isfinite(p.mu) || !isfinite(p.nu)) return TCOL_EINVAL;
     return TCOL_OK;
 }
 
 double pow0(double x, double p) { return x == 0.0 ? 0.0 : pow(x, p); }
+
+// shapes the contraction kernel is instantiated for: (rows per block, 16-column subtiles per wave)
+const int kShapes[][2] = {{64, 2}, {64, 4}, {128, 4}, {128, 8}, {64, 9}, {128, 9}, {256, 4}};
 
 }  // namespace
 
@@ -99,7 +115,6 @@ struct tcol_ctx {
     hipStream_t cap = nullptr;
     std::vector<tcol_graph_params> params;
     std::vector<Layout> layouts;
-    std::vector<size_t> base;       // workspace offset of each graph region
     std::vector<GraphDev> hdesc;
     GraphDev* ddesc = nullptr;
     GraphState* dstate = nullptr;
@@ -108,20 +123,33 @@ struct tcol_ctx {
     size_t ws_bytes = 0;
     bool ws_owned = false;
     tcol_options opt{};
-    GemmShape shape{};
-    int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0, total_gm = 0, kmax = 0;
+    GemmShape shape{};              // separate-path tiling (also used by tcol_conflicts / tcol_loss_grad)
+    GemmShape fshape{};             // fused-path tiling
+    bool fused_ok = false;          // the fused path is available for these graphs
+    int sparse_rpw = 0;             // sparse penalty kernel: rows per wave (0: no graph uses it)
+    int sparse_dk = 0;              // largest D*k of a graph on the sparse penalty
+    int total_rows = 0, total_mem = 0, total_vtx = 0, total_mt = 0, total_ex = 0;
+    int total_gm[2] = {0, 0};
+    int kmax = 0, nmax = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [0] = unroll steps, [1] = one step
     hipGraph_t graph[2] = {nullptr, nullptr};
     int graph_unroll = 0;
+    int graph_fused = -1;
 };
 
-#define HIPCHK(x)                                                    \
-    do {                                                             \
-        hipError_t e_ = (x);                                         \
-        if (e_ != hipSuccess) {                                      \
+#define HIPCHK(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess) {                                                     \
             fprintf(stderr, "libtcol: %s failed: %s\n", #x, hipGetErrorString(e_)); \
-            return TCOL_EHIP;                                        \
-        }                                                            \
+            return TCOL_EHIP;                                                       \
+        }                                                                           \
+    } while (0)
+
+#define HIPRET(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return e_;            \
     } while (0)
 
 static void drop_graphs(tcol_ctx* c) {
@@ -132,41 +160,90 @@ static void drop_graphs(tcol_ctx* c) {
         c->graph[i] = nullptr;
     }
     c->graph_unroll = 0;
+    c->graph_fused = -1;
 }
 
-// choose the GEMM tile shape for the current options
-static GemmShape pick_shape(const tcol_ctx* c) {
+static int common_precision(const tcol_ctx* c) {
     int prec = c->params[0].precision;
     for (auto& p : c->params)
-        if (p.precision != prec) prec = -1;
-    GemmShape s{prec < 0 ? 0 : prec, 128, 8, c->opt.fused ? 1 : 0};
-    if (c->opt.tile_bm) s.bm = c->opt.tile_bm;
-    if (c->opt.tile_ntw) s.ntw = c->opt.tile_ntw;
-    else {
-        long long cols = 0;
-        for (auto& p : c->params) cols = std::max<long long>(cols, (long long)p.D * p.k);
-        if (cols <= 512) s.ntw = 4;
-        if (cols <= 128) s.ntw = 2;
-    }
-    if (!c->opt.tile_bm) {
-        int nmin = 1 << 30;
-        for (auto& p : c->params) nmin = std::min(nmin, p.n);
-        if (nmin <= 256) s.bm = 64;
-    }
-    return s;
+        if (p.precision != prec) return -1;
+    return prec;
 }
 
-// recompute flattened work offsets for the tile shape and upload the descriptors
-static tcol_status rebuild_schedule(tcol_ctx* c) {
-    c->shape = pick_shape(c);
-    if (!gemm_supported(c->shape)) {
-        c->shape.bm = 128;
-        c->shape.ntw = 8;
-        if (!gemm_supported(c->shape)) return TCOL_EINVAL;
+static bool shape_listed(int bm, int ntw) {
+    for (auto& s : kShapes)
+        if (s[0] == bm && s[1] == ntw) return true;
+    return false;
+}
+
+// tiles of a shape over all graphs
+static long long tiles_for(const tcol_ctx* c, int bm, int ntw, int mode) {
+    long long t = 0;
+    const int BN = gemm_bn(ntw);
+    for (int g = 0; g < c->G; ++g) {
+        const auto& p = c->params[g];
+        const int tm = c->layouts[g].n_pad / bm;
+        int tn;
+        if (mode == 1) {
+            if (BN < p.k) return -1;
+            tn = ceil_div(p.D, BN / p.k);
+        } else {
+            tn = ceil_div(p.D * p.k, BN);
+        }
+        t += (long long)tm * tn;
     }
+    return t;
+}
+
+// tile shapes: options first, else a default that keeps the chip busy
+static void pick_shapes(tcol_ctx* c) {
+    const int prec = std::max(0, common_precision(c));
+    long long cols = 0;
+    for (auto& p : c->params) cols = std::max<long long>(cols, (long long)p.D * p.k);
+    GemmShape s{prec, 128, 8, 0};
+    if (cols <= 512) s.ntw = 4;
+    if (cols <= 128) s.ntw = 2;
+    if (c->nmax <= 256) {
+        s.bm = 64;
+        s.ntw = std::min(s.ntw, 4);
+    }
+    if (!shape_listed(s.bm, s.ntw)) s.bm = shape_listed(64, s.ntw) ? 64 : 128;
+    if (!shape_listed(s.bm, s.ntw)) s.ntw = 4;
+    if (c->opt.tile_bm && c->opt.tile_ntw && shape_listed(c->opt.tile_bm, c->opt.tile_ntw)) {
+        s.bm = c->opt.tile_bm;
+        s.ntw = c->opt.tile_ntw;
+    }
+    c->shape = s;
+    // fused: whole members per column tile, so 32 * ntw >= k; the smallest such width,
+    // with 128-row blocks when that still gives at least 512 tiles
+    GemmShape f{prec, 0, 0, 1};
+    if (c->opt.tile_bm && c->opt.tile_ntw && shape_listed(c->opt.tile_bm, c->opt.tile_ntw) &&
+        tiles_for(c, c->opt.tile_bm, c->opt.tile_ntw, 1) > 0) {
+        f.bm = c->opt.tile_bm;
+        f.ntw = c->opt.tile_ntw;
+    } else {
+        for (int ntw : {2, 4, 8, 9}) {
+            if (gemm_bn(ntw) < c->kmax) continue;
+            f.ntw = ntw;
+            f.bm = shape_listed(64, ntw) ? 64 : 128;
+            if (shape_listed(128, ntw) && tiles_for(c, 128, ntw, 1) >= 512) f.bm = 128;
+            break;
+        }
+    }
+    c->fshape = f;
+    c->fused_ok = f.ntw > 0 && common_precision(c) >= 0;
+}
+
+// recompute flattened work offsets for the tile shapes and upload the descriptors
+static tcol_status rebuild_schedule(tcol_ctx* c) {
+    pick_shapes(c);
     HIPCHK(gemm_prepare(c->shape));
-    const int BN = gemm_bn(c->shape.ntw);
-    int rows = 0, mem = 0, mt = 0, ex = 0, gm = 0, kmax = 0;
+    if (c->fused_ok) HIPCHK(gemm_prepare(c->fshape));
+    HIPCHK(penalty_rows_prepare());
+    const int BN0 = gemm_bn(c->shape.ntw);
+    const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
+    int rows = 0, mem = 0, vtx = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
+    int sp_rpw = 2, sp_dk = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const Layout& L = c->layouts[g];
@@ -175,6 +252,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         rows += p.D * p.n;
         d.mem_begin = mem;
         mem += p.D;
+        d.vtx_begin = vtx;
+        vtx += p.n;
         d.mt_begin = mt;
         d.mt_T = L.mt_T;
         mt += L.mt_tiles;
@@ -182,50 +261,105 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         const long long items = (long long)p.D * p.k * (L.n_pad / 16);
         d.ex_cblocks = (int)((items + 255) / 256);
         ex += d.ex_cblocks;
-        d.gm_begin = gm;
-        d.gm_tm = L.n_pad / c->shape.bm;
-        if (c->shape.mode == 1) {
-            d.gm_mpb = std::max(1, BN / p.k);
-            d.gm_tn = ceil_div(p.D, d.gm_mpb);
-        } else {
-            d.gm_mpb = 0;
-            d.gm_tn = ceil_div(p.D * p.k, BN);
+        d.gm_begin[0] = gm0;
+        d.gm_tm[0] = L.n_pad / c->shape.bm;
+        d.gm_tn[0] = ceil_div(p.D * p.k, BN0);
+        gm0 += d.gm_tm[0] * d.gm_tn[0];
+        if (c->fused_ok) {
+            d.gm_mpb = BN1 / p.k;
+            d.gm_begin[1] = gm1;
+            d.gm_tm[1] = L.n_pad / c->fshape.bm;
+            d.gm_tn[1] = ceil_div(p.D, d.gm_mpb);
+            gm1 += d.gm_tm[1] * d.gm_tn[1];
         }
-        gm += d.gm_tm * d.gm_tn;
-        kmax = std::max(kmax, p.k);
+        // sparse penalty rows: one lane per member (D <= 64) and one D x k histogram per row in
+        // LDS; chosen by default when the operand is sparse (expected density D/k <= 1/4)
+        const int pen = c->opt.penalty;
+        const bool feasible = p.D <= 64 && (long long)p.D * p.k * 4 <= 160 * 1024;
+        d.sparse = feasible && (pen == 2 || (pen == 0 && 4LL * p.D <= p.k)) ? 1 : 0;
+        if (d.sparse) {
+            if (p.D > 32) sp_rpw = 1;
+            sp_dk = std::max(sp_dk, p.D * p.k);
+        }
     }
     c->total_rows = rows;
     c->total_mem = mem;
+    c->total_vtx = vtx;
     c->total_mt = mt;
     c->total_ex = ex;
-    c->total_gm = gm;
-    c->kmax = kmax;
+    c->total_gm[0] = gm0;
+    c->total_gm[1] = gm1;
+    c->sparse_rpw = sp_dk > 0 ? sp_rpw : 0;
+    if (c->sparse_rpw == 2 && 2LL * sp_dk * 4 > kMaxLdsBytes) c->sparse_rpw = 1;
+    c->sparse_dk = sp_dk;
     HIPCHK(hipMemcpyAsync(c->ddesc, c->hdesc.data(), sizeof(GraphDev) * c->G, hipMemcpyHostToDevice, c->stream));
     drop_graphs(c);
     return TCOL_OK;
 }
 
+// step schedule actually used: 2 needs the epilogue tiling, 1 needs the row-update kernel
+static int path_of(const tcol_ctx* c) {
+    if (c->opt.fused == 2 && c->fused_ok) return 2;
+    if (c->opt.fused >= 1 && update_rows_kpl(c->kmax)) return 1;
+    return 0;
+}
+static bool use_fused(const tcol_ctx* c) { return path_of(c) == 2; }
+
+static hipError_t launch_update_any(tcol_ctx* c, int honor, int mode, int gsel, float* gs, float* gw, hipStream_t s) {
+    if (update_rows_kpl(c->kmax))
+        return launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, honor, mode, gsel, gs, gw, s);
+    return launch_update(c->ddesc, c->G, c->total_rows, honor, mode, gsel, gs, gw, s);
+}
+
 // ---------------------------------------------------------------- sequences --
 
-// one Algorithm-1 iteration for every running graph (separate-kernel path)
-static hipError_t enqueue_step_separate(tcol_ctx* c, hipStream_t s) {
-    hipError_t e;
-    if ((e = launch_colors(c->ddesc, c->G, c->total_rows, 1, s)) != hipSuccess) return e;
-    if ((e = launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s)) != hipSuccess) return e;
-    if ((e = launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, s)) != hipSuccess) return e;
-    if ((e = launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s)) != hipSuccess) return e;
-    if ((e = launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 1, 7, s)) != hipSuccess) return e;
-    if ((e = launch_fitness(c->ddesc, c->G, 1, 0, -1, s)) != hipSuccess) return e;
-    if ((e = launch_update(c->ddesc, c->G, c->total_rows, 1, 0, -1, nullptr, nullptr, s)) != hipSuccess) return e;
-    if ((e = launch_advance(c->ddesc, c->G, s)) != hipSuccess) return e;
+// one Algorithm-1 iteration for every running graph (plain path)
+static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
+    HIPRET(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 0, s));
+    HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
+    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 15, 0, s));
+    HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+    HIPRET(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
+    HIPRET(launch_advance(c->ddesc, c->G, s));
+    return hipSuccess;
+}
+
+// penalty of the fast and epilogue paths: sparse rows or the dense operand, per graph
+static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
+    if (c->sparse_rpw)
+        HIPRET(launch_penalty_rows(c->ddesc, c->G, c->total_vtx, 1, c->sparse_dk, s));
+    HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
+    return hipSuccess;
+}
+
+// one iteration on the fast path; c[pS] holds the colours of the current weights
+static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(enqueue_penalty(c, s));
+    HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
+    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
+    HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+    HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, 1, 0, -1, nullptr, nullptr, s));
+    HIPRET(launch_advance(c->ddesc, c->G, s));
+    return hipSuccess;
+}
+
+// one iteration on the epilogue path; c[pS] holds the colours of the current weights
+static hipError_t enqueue_step_fused(tcol_ctx* c, hipStream_t s) {
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(enqueue_penalty(c, s));
+    HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
+    HIPRET(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
+    HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFused, -1, s));
     return hipSuccess;
 }
 
 static hipError_t enqueue_steps(tcol_ctx* c, int n, hipStream_t s) {
-    for (int i = 0; i < n; ++i) {
-        hipError_t e = enqueue_step_separate(c, s);
-        if (e != hipSuccess) return e;
-    }
+    const int path = path_of(c);
+    for (int i = 0; i < n; ++i)
+        HIPRET(path == 2 ? enqueue_step_fused(c, s) : (path == 1 ? enqueue_step_fast(c, s) : enqueue_step_plain(c, s)));
     return hipSuccess;
 }
 
@@ -247,6 +381,43 @@ static tcol_status build_graphs(tcol_ctx* c) {
         HIPCHK(hipGraphInstantiate(&c->gexec[i], gr, nullptr, nullptr, 0));
     }
     c->graph_unroll = U;
+    c->graph_fused = path_of(c);
+    return TCOL_OK;
+}
+
+// run `steps` iterations (graph replays or eager launches); no synchronisation
+static tcol_status run_steps(tcol_ctx* c, int steps) {
+    if (steps <= 0) return TCOL_OK;
+    // the fast and epilogue paths colour the updated rows themselves: one argmax pass first
+    if (path_of(c) != 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, c->stream));
+    if (c->opt.use_graph) {
+        const int U = std::max(1, std::min(64, c->opt.unroll));
+        if (c->graph_unroll != U || !c->gexec[0] || c->graph_fused != path_of(c)) {
+            tcol_status s = build_graphs(c);
+            if (s != TCOL_OK) return s;
+        }
+        for (int i = 0; i < steps / U; ++i) HIPCHK(hipGraphLaunch(c->gexec[0], c->stream));
+        for (int i = 0; i < steps % U; ++i) HIPCHK(hipGraphLaunch(c->gexec[1], c->stream));
+    } else {
+        HIPCHK(enqueue_steps(c, steps, c->stream));
+    }
+    return TCOL_OK;
+}
+
+// read the graph states (synchronises) and move fused-path weights back into the caller's buffer
+static tcol_status settle(tcol_ctx* c) {
+    HIPCHK(hipMemcpyAsync(c->hstate, c->dstate, sizeof(GraphState) * c->G, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (int g = 0; g < c->G; ++g) {
+        if (c->hstate[g].pW == 1) {
+            const auto& p = c->params[g];
+            HIPCHK(hipMemcpyAsync(c->hdesc[g].W[0], c->hdesc[g].W[1], sizeof(float) * (size_t)p.D * p.n * p.k,
+                                  hipMemcpyDeviceToDevice, c->stream));
+            any = true;
+        }
+    }
+    if (any) HIPCHK(launch_state(c->ddesc, c->G, 3, -1, 0, c->stream));
     return TCOL_OK;
 }
 
@@ -306,9 +477,13 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
     c->G = G;
     c->stream = (hipStream_t)stream;
     c->params.assign(p, p + G);
-    c->opt.fused = 0;
+    c->opt.fused = 1;
     c->opt.use_graph = 1;
     c->opt.unroll = 8;
+    for (auto& q : c->params) {
+        c->kmax = std::max(c->kmax, q.k);
+        c->nmax = std::max(c->nmax, q.n);
+    }
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return TCOL_EHIP;
@@ -339,9 +514,10 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
     size_t off = head_bytes(G);
     c->hdesc.resize(G);
     c->layouts.resize(G);
-    c->base.resize(G);
     int* dbad = nullptr;
-    if (hipMalloc((void**)&dbad, sizeof(int)) != hipSuccess || hipMemsetAsync(dbad, 0, sizeof(int), c->stream) != hipSuccess) {
+    if (hipMalloc((void**)&dbad, sizeof(int)) != hipSuccess ||
+        hipMemsetAsync(dbad, 0, sizeof(int), c->stream) != hipSuccess) {
+        if (dbad) hipFree(dbad);
         tcol_destroy(c);
         return TCOL_EHIP;
     }
@@ -350,7 +526,6 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         const tcol_graph_params& q = p[g];
         Layout L = make_layout(q);
         c->layouts[g] = L;
-        c->base[g] = off;
         uint8_t* b = c->ws + off;
         off += L.total;
         GraphDev& d = c->hdesc[g];
@@ -359,6 +534,7 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.k = q.k;
         d.D = q.D;
         d.n_pad = L.n_pad;
+        d.cs = round_up(q.n, 64);
         d.ncols = q.D * q.k;
         d.rows_S = L.rows_S;
         d.problem = q.problem;
@@ -398,6 +574,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.part = (double*)(b + L.off[B_PART]);
         d.snap = (int16_t*)(b + L.off[B_SNAP]);
         d.st = c->dstate + g;
+        d.cT = (int16_t*)(b + L.off[B_CT]);
+        d.cTs = round_up(q.D, 8);
         // look-up tables over the group concentration m = 0..D (host libm, FP64)
         std::vector<float> lp(q.D + 1), lb(q.D + 1);
         std::vector<double> lka(q.D + 1), lvb(q.D + 1);
@@ -446,12 +624,12 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
 tcol_status tcol_set_options(tcol_ctx* c, const tcol_options* o) {
     if (!c || !o) return TCOL_EINVAL;
     if (o->unroll < 0 || o->unroll > 64) return TCOL_EINVAL;
-    if (o->tile_bm && o->tile_bm != 64 && o->tile_bm != 128) return TCOL_EINVAL;
-    if (o->tile_ntw < 0 || o->tile_ntw > 18) return TCOL_EINVAL;
+    if (o->penalty < 0 || o->penalty > 2) return TCOL_EINVAL;
+    if (o->fused < 0 || o->fused > 2) return TCOL_EINVAL;
+    if ((o->tile_bm || o->tile_ntw) && !shape_listed(o->tile_bm, o->tile_ntw)) return TCOL_EINVAL;
     tcol_options old = c->opt;
     c->opt = *o;
     if (c->opt.unroll == 0) c->opt.unroll = 8;
-    c->opt.fused = 0;   // the fused epilogue is selected only where it is built
     tcol_status s = rebuild_schedule(c);
     if (s != TCOL_OK) {
         c->opt = old;
@@ -463,8 +641,10 @@ tcol_status tcol_set_options(tcol_ctx* c, const tcol_options* o) {
 tcol_status tcol_get_options(tcol_ctx* c, tcol_options* o) {
     if (!c || !o) return TCOL_EINVAL;
     *o = c->opt;
-    if (!o->tile_bm) o->tile_bm = c->shape.bm;
-    if (!o->tile_ntw) o->tile_ntw = c->shape.ntw;
+    const GemmShape& s = path_of(c) == 2 ? c->fshape : c->shape;
+    if (!o->tile_bm) o->tile_bm = s.bm;
+    if (!o->tile_ntw) o->tile_ntw = s.ntw;
+    o->fused = path_of(c);
     return TCOL_OK;
 }
 
@@ -472,21 +652,10 @@ tcol_status tcol_step(tcol_ctx* c, int32_t max_steps, int32_t* steps_done, int32
                       int16_t* const* colors_out_dev) {
     if (!c || max_steps < 0) return TCOL_EINVAL;
     HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
-    if (max_steps > 0) {
-        if (c->opt.use_graph) {
-            if (c->graph_unroll != std::max(1, std::min(64, c->opt.unroll)) || !c->gexec[0]) {
-                tcol_status s = build_graphs(c);
-                if (s != TCOL_OK) return s;
-            }
-            const int U = c->graph_unroll;
-            for (int i = 0; i < max_steps / U; ++i) HIPCHK(hipGraphLaunch(c->gexec[0], c->stream));
-            for (int i = 0; i < max_steps % U; ++i) HIPCHK(hipGraphLaunch(c->gexec[1], c->stream));
-        } else {
-            HIPCHK(enqueue_steps(c, max_steps, c->stream));
-        }
-    }
-    HIPCHK(hipMemcpyAsync(c->hstate, c->dstate, sizeof(GraphState) * c->G, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    tcol_status rs = run_steps(c, max_steps);
+    if (rs != TCOL_OK) return rs;
+    tcol_status s = settle(c);
+    if (s != TCOL_OK) return s;
     int done = 0;
     tcol_status rc = TCOL_OK;
     for (int g = 0; g < c->G; ++g) {
@@ -506,13 +675,9 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     // steps 1-2 for all graphs of the context (cheap), reporting only
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
-    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, c->stream));
-    GemmShape s = c->shape;
-    s.mode = 0;
-    if (s.mode != c->shape.mode) HIPCHK(gemm_prepare(s));
-    // separate-mode tiling is needed for the gather over arbitrary column tiles
-    HIPCHK(launch_gemm(s, c->ddesc, c->G, c->total_gm, 0, 1, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
+    HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, c->stream));
     HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
     HIPCHK(launch_copy_report(c->ddesc, g, colors_dev, f_color_dev, f_eq_dev, c->stream));
     return TCOL_OK;
@@ -521,14 +686,13 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
 tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* gradS_dev, float* gradW_dev) {
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
-    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagLoss | kFlagForcePen, g, nullptr, c->stream));
-    HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 0, 7, c->stream));
+    HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 15, 0, c->stream));
     HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
     if (loss_dev) HIPCHK(launch_loss(c->ddesc, g, c->layouts[g].mt_tiles, loss_dev, c->stream));
-    if (gradS_dev || gradW_dev)
-        HIPCHK(launch_update(c->ddesc, c->G, c->total_rows, 0, 1, g, gradS_dev, gradW_dev, c->stream));
+    if (gradS_dev || gradW_dev) HIPCHK(launch_update_any(c, 0, 1, g, gradS_dev, gradW_dev, c->stream));
     return TCOL_OK;
 }
 
@@ -567,24 +731,32 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     for (int i = 0; i < NP; ++i) HIPCHK(hipEventCreate(&ev[i]));
     double acc[NP] = {0};
     hipStream_t s = c->stream;
+    const int path = path_of(c);
     HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, s));
+    if (path != 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
     for (int it = 0; it < steps; ++it) {
         HIPCHK(hipEventRecord(ev[0], s));
-        HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
+        if (path == 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
         HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(launch_class_sizes(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
         HIPCHK(hipEventRecord(ev[2], s));
-        HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, s));
+        HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, path != 0 ? 1 : 0, s));
         HIPCHK(hipEventRecord(ev[3], s));
-        HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
+        if (path != 0)
+            HIPCHK(enqueue_penalty(c, s));
+        else
+            HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
         HIPCHK(hipEventRecord(ev[4], s));
-        HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm, 1, 7, s));
+        if (path == 2)
+            HIPCHK(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
+        else
+            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
-        HIPCHK(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
         HIPCHK(hipEventRecord(ev[6], s));
-        HIPCHK(launch_update(c->ddesc, c->G, c->total_rows, 1, 0, -1, nullptr, nullptr, s));
+        if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
         HIPCHK(hipEventRecord(ev[7], s));
-        HIPCHK(launch_advance(c->ddesc, c->G, s));
+        if (path != 2) HIPCHK(launch_advance(c->ddesc, c->G, s));
         HIPCHK(hipEventRecord(ev[8], s));
         HIPCHK(hipEventSynchronize(ev[8]));
         for (int i = 0; i < 8; ++i) {
@@ -593,15 +765,18 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
             acc[i] += x;
         }
     }
+    tcol_status st = settle(c);
+    if (st != TCOL_OK) return st;
     for (int i = 0; i < 8; ++i) ms[i] = (float)(acc[i] / steps);
     ms[8] = 0.0f;
     if (as_only) {
         double a = 0;
-        GemmShape sh = c->shape;
-        sh.mode = 0;
+        HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, s));
+        HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
         for (int it = 0; it < steps; ++it) {
             HIPCHK(hipEventRecord(ev[0], s));
-            HIPCHK(launch_gemm(sh, c->ddesc, c->G, c->total_gm, 0, 1, s));
+            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, s));
             HIPCHK(hipEventRecord(ev[1], s));
             HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, s));
             HIPCHK(hipEventSynchronize(ev[1]));
@@ -615,10 +790,95 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     return TCOL_OK;
 }
 
+// Time a few steps of each candidate tile shape (and penalty mode) and keep the fastest.
+// The weights and counters are restored after every candidate.
 tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
     if (!c) return TCOL_EINVAL;
-    if (best_bm) *best_bm = c->shape.bm;
-    if (best_ntw) *best_ntw = c->shape.ntw;
+    // backups of W and t
+    std::vector<float*> backup(c->G, nullptr);
+    std::vector<long long> t0(c->G);
+    HIPCHK(hipMemcpyAsync(c->hstate, c->dstate, sizeof(GraphState) * c->G, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int g = 0; g < c->G; ++g) {
+        const auto& p = c->params[g];
+        const size_t bytes = sizeof(float) * (size_t)p.D * p.n * p.k;
+        t0[g] = c->hstate[g].t;
+        if (hipMalloc((void**)&backup[g], bytes) != hipSuccess) {
+            for (auto b : backup) if (b) hipFree(b);
+            return TCOL_ENOMEM;
+        }
+        HIPCHK(hipMemcpyAsync(backup[g], c->hdesc[g].W[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    auto restore = [&]() -> tcol_status {
+        for (int g = 0; g < c->G; ++g) {
+            const auto& p = c->params[g];
+            HIPCHK(hipMemcpyAsync(c->hdesc[g].W[0], backup[g], sizeof(float) * (size_t)p.D * p.n * p.k,
+                                  hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(launch_state(c->ddesc, c->G, 1, g, t0[g], c->stream));
+        }
+        return TCOL_OK;
+    };
+    // stop rule off while timing
+    std::vector<int> stop(c->G);
+    for (int g = 0; g < c->G; ++g) {
+        stop[g] = c->hdesc[g].stop_on_legal;
+        c->hdesc[g].stop_on_legal = 0;
+    }
+    const tcol_options base = c->opt;
+    tcol_options best = base;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<tcol_options> cands;
+    const std::vector<int> paths = base.fused == 0 ? std::vector<int>{0} : std::vector<int>{1, 2};
+    for (int path : paths)
+        for (auto& sh : kShapes) {
+            tcol_options o = base;
+            o.fused = path;
+            o.tile_bm = sh[0];
+            o.tile_ntw = sh[1];
+            if (path == 2 && tiles_for(c, sh[0], sh[1], 1) <= 0) continue;
+            if (path == 0) {
+                cands.push_back(o);
+                continue;
+            }
+            for (int pen : {1, 2}) {
+                o.penalty = pen;
+                cands.push_back(o);
+            }
+        }
+    const int warm = 2, timed = 6;
+    for (auto& o : cands) {
+        c->opt = o;
+        if (rebuild_schedule(c) != TCOL_OK) continue;
+        HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
+        if (run_steps(c, warm) != TCOL_OK) continue;
+        HIPCHK(hipEventRecord(e0, c->stream));
+        if (run_steps(c, timed) != TCOL_OK) continue;
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (settle(c) != TCOL_OK) continue;
+        if (restore() != TCOL_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = o;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (int g = 0; g < c->G; ++g) c->hdesc[g].stop_on_legal = stop[g];
+    c->opt = best;
+    tcol_status s = rebuild_schedule(c);
+    HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (auto b : backup) hipFree(b);
+    if (s != TCOL_OK) return s;
+    const GemmShape& sh = path_of(c) == 2 ? c->fshape : c->shape;
+    if (best_bm) *best_bm = sh.bm;
+    if (best_ntw) *best_ntw = sh.ntw;
     return TCOL_OK;
 }
 

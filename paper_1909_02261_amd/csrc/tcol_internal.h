@@ -15,12 +15,11 @@ constexpr int kMaxK = 4096;
 constexpr int kMaxD = 1024;
 
 // operand rows and columns are padded to this multiple (GEMM tile in M and K)
-constexpr int kPadN = 128;
+constexpr int kPadN = 256;
 // extra zero rows after the D*k rows of S^T so any column tile can read a full tile
 constexpr int kSRowSlack = 576;
-// bytes per operand row per GEMM K-stage, and its padded LDS stride
+// bytes per operand row per GEMM K-stage (one LDS row)
 constexpr int kStageRowBytes = 128;
-constexpr int kLdsStride = 144;
 
 // device-resident per-graph state (iteration counter, stop flags, parities)
 struct GraphState {
@@ -31,12 +30,15 @@ struct GraphState {
     int steps_done;     // updates made since the last reset by the host
     int pW;             // fused path: which W buffer holds the current weights (0 = caller's)
     int pS;             // fused path: which colour / S buffer set is current
+    int next_bad;       // fused path: the update produced a non-finite weight
+    int pad_;
 };
 
 // per-graph descriptor, uploaded once at init
 struct GraphDev {
     int n, k, D;
     int n_pad;          // padded n (rows and K of the operands)
+    int cs;             // row stride of the colour arrays c[p] (n rounded up to 64)
     int ncols;          // D * k
     int rows_S;         // rows of S^T (D*k + slack)
     int problem, precision, bonus_diag, stop_on_legal, nb_iter;
@@ -54,7 +56,7 @@ struct GraphDev {
     void* Pop;                // [n_pad][n_pad] penalty operand (fp32, or bf16 for BF16/FP8)
     void* Sop[2];             // [rows_S][n_pad] S^T in the A.S operand precision
     void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 penalty pass (else null)
-    int16_t* c[2];            // colours [D][n]
+    int16_t* c[2];            // colours [D][cs] (member-major; entries n..cs-1 unused)
     int32_t* V[2];            // class sizes [D][k]
     float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)
     int32_t* f2;              // [D] 2 * f_color accumulated by the GEMM
@@ -64,16 +66,20 @@ struct GraphDev {
     double* part;             // [mt_tiles][2] kappa / varpi partial sums
     int16_t* snap;            // [n] colouring of the legal member
     GraphState* st;
+    int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
+    int cTs;                  // row stride of cT (D rounded up to 8)
+    int sparse;               // fused path: penalty rows by the sparse kernel (else dense operand pass)
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
+    int vtx_begin;            // vertices i for per-vertex kernels
     int mt_begin;             // tiles of the group-concentration kernel
     int mt_T;                 // 64-row tiles per side
     int ex_begin;             // blocks of the S^T expansion kernel
     int ex_cblocks;           // column blocks per S^T row group
-    int gm_begin;             // GEMM tiles
-    int gm_tm, gm_tn;         // GEMM tiles along rows and along columns
-    int gm_mpb;               // fused path: members per column tile
+    int gm_begin[2];          // GEMM tiles of the separate (0) and fused (1) tilings
+    int gm_tm[2], gm_tn[2];   // tiles along rows and along columns
+    int gm_mpb;               // fused tiling: members per column tile
 };
 
 // run-time flags passed to the kernels of one launch sequence
@@ -82,6 +88,8 @@ enum : int {
     kFlagMtOut = 2,       // ... and Mt to an output buffer
     kFlagForcePen = 4,    // build the penalty operand even when lambda t = mu t = 0
     kFlagReport = 8,      // fitness kernel only reports (no stop, no state change)
+    kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty
+    kFlagFused = 32,      // fitness kernel of the fused path: accept the update by flipping buffers
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

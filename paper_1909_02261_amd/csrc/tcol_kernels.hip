@@ -93,14 +93,16 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
             atomicExch(&st->error, -5);
             atomicExch(&st->stopped, 1);
         }
-        d.c[st->pS][r] = (int16_t)bi;
+        const int m = r / d.n, i = r - m * d.n;
+        d.c[st->pS][(size_t)m * d.cs + i] = (int16_t)bi;
     }
 }
 
-// #V_{d,l}: class sizes of member d; one block per member (all graphs).
-__global__ __launch_bounds__(256) void k_class_sizes(const GraphDev* __restrict__ gd, int G, int total_mem,
-                                                     int honor_stop, int next) {
-    extern __shared__ int hist[];
+// Class sizes #V_{d,l} of member d and the vertex-major copy of its colours.
+// One block per member (all graphs).  Dynamic LDS: k ints.
+__global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
+                                              int next) {
+    extern __shared__ int cnt[];
     const int mem = blockIdx.x;
     if (mem >= total_mem) return;
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
@@ -108,24 +110,135 @@ __global__ __launch_bounds__(256) void k_class_sizes(const GraphDev* __restrict_
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     const int m = mem - d.mem_begin;
-    for (int l = threadIdx.x; l < d.k; l += blockDim.x) hist[l] = 0;
+    const int k = d.k, n = d.n, tid = threadIdx.x;
+    const int16_t* c = d.c[p] + (size_t)m * d.cs;
+    for (int l = tid; l < k; l += 256) cnt[l] = 0;
     __syncthreads();
-    const int16_t* c = d.c[p] + (size_t)m * d.n;
-    for (int i = threadIdx.x; i < d.n; i += blockDim.x) atomicAdd(&hist[c[i]], 1);
+    for (int i = tid; i < n; i += 256) {
+        const int16_t x = c[i];
+        atomicAdd(&cnt[x], 1);
+        d.cT[(size_t)i * d.cTs + m] = x;
+    }
     __syncthreads();
-    for (int l = threadIdx.x; l < d.k; l += blockDim.x) d.V[p][(size_t)m * d.k + l] = hist[l];
+    int32_t* V = d.V[p] + (size_t)m * k;
+    for (int l = tid; l < k; l += 256) V[l] = cnt[l];
+}
+
+// ------------------------------------------------------ sparse penalty rows ----
+
+__device__ inline bool pen_active(const GraphDev& d, const GraphState* st) {
+    const float tf = (float)st->t;
+    return (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// number of equal 16-bit halves of a and b (colours are < 2^15)
+__device__ inline int equal_halves(uint32_t a, uint32_t b) {
+    const uint32_t x = a ^ b;
+    // a half is zero exactly when subtracting one inside that half sets its top bit while
+    // the half itself does not have it set
+    u16x2 h = __builtin_bit_cast(u16x2, x);
+    const u16x2 one = {1, 1};
+    const uint32_t y = __builtin_bit_cast(uint32_t, (u16x2)(h - one));
+    return __builtin_popcount(y & ~x & 0x80008000u);
+}
+
+// Penalty rows without the dense operand, for populations with few members
+// against many colours: the penalty operand
+//   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
+// m = Mt_ij, vanishes unless i and j share a colour in some member.  One wave
+// per row i works through j in chunks of 64:
+//   1. lane jj takes j = j0 + jj and counts m = #{d : c_d(j) = c_d(i)} from the
+//      vertex-major colours (two members per 32-bit compare), then P_ij;
+//   2. a ballot marks the j with P_ij != 0, and for each of them every lane d
+//      (one lane per member) adds P_ij to its histogram at colour c_d(j).
+// Each lane owns the histogram of its member, so the FP32 sums run in the order
+// j = 0..n-1 on every run.  The histograms, (P.S_d)[i, l], are written to
+// G[d][i][l], where the contraction kernel adds A.S_d.  D <= 64.
+__global__ __launch_bounds__(256) void k_penalty_rows(const GraphDev* __restrict__ gd, int G, int total_vtx,
+                                                      int honor_stop, int wpb, int hist_floats) {
+    extern __shared__ float hist_all[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave >= wpb) return;
+    const int v = blockIdx.x * wpb + wave;
+    if (v >= total_vtx) return;
+    const GraphDev& d = gd[find_graph(gd, G, v, [](const GraphDev& x) { return x.vtx_begin; })];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    if (!d.sparse || !pen_active(d, st)) return;
+    const int D = d.D, k = d.k, n = d.n;
+    const int i = v - d.vtx_begin;
+    const bool act = lane < D;                  // member lane
+    float* h = hist_all + (size_t)wave * hist_floats;
+    if (act)
+        for (int l = 0; l < k; ++l) h[(size_t)lane * k + l] = 0.0f;
+    const int16_t* crow = d.c[st->pS] + (size_t)lane * d.cs;   // member lane's colours
+    const float tf = (float)st->t;
+    // look-up tables: lane q holds the entries of m = q + 1; a lane reads entry m from lane m - 1
+    const float lutp = act ? d.lut_pen[lane + 1] : 0.0f;
+    const float lutb = act ? d.lut_bon[lane + 1] : 0.0f;
+    const bool diag = d.bonus_diag != 0;
+    const uint8_t* arow = d.A8 + (size_t)i * d.n_pad;
+    // colours of vertex i, two members per word (D even or the last half is padding)
+    const uint32_t* ciw = (const uint32_t*)(d.cT + (size_t)i * d.cTs);
+    const int nw = D >> 1;
+    const bool odd = D & 1;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        // member lanes: colours c_lane(j0 .. j0+63), eight 16-byte loads
+        uint4 w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = act ? *(const uint4*)(crow + j0 + 8 * q) : make_uint4(0, 0, 0, 0);
+        // vertex lanes: m and P for j = j0 + lane
+        const int j = j0 + lane;
+        float P = 0.0f;
+        int m = 0;
+        if (j < n) {
+            const int16_t* cj = d.cT + (size_t)j * d.cTs;
+            for (int q = 0; q < nw; ++q) m += equal_halves(ciw[q], *(const uint32_t*)(cj + 2 * q));
+            if (odd) m += (cj[D - 1] == d.cT[(size_t)i * d.cTs + D - 1]) ? 1 : 0;
+        }
+        const float lp = __shfl(lutp, m > 0 ? m - 1 : 0, 64);
+        const float lb = __shfl(lutb, m > 0 ? m - 1 : 0, 64);
+        if (m > 0) {
+            if (arow[j]) P = tf * lp;
+            else if (i != j || diag) P = -(tf * lb);
+        }
+        const unsigned long long hits = __ballot(P != 0.0f);
+        if (hits == 0) continue;
+#pragma unroll
+        for (int jj = 0; jj < 64; ++jj) {
+            if (!((hits >> jj) & 1ull)) continue;     // uniform over the wave
+            const float pv = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, P), jj));
+            const uint4 x = w[jj >> 3];
+            const int e = (jj >> 1) & 3;
+            const uint32_t word = e == 0 ? x.x : (e == 1 ? x.y : (e == 2 ? x.z : x.w));
+            const int cjm = (int)((word >> (16 * (jj & 1))) & 0xFFFFu);
+            if (act) atomicAdd(&h[(size_t)lane * k + cjm], pv);
+        }
+    }
+    // the write-out reads other lanes' histograms: wait for this wave's LDS writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    float* G1 = d.G;
+    for (int e = lane; e < D * k; e += 64) {
+        const int mm = e / k, l = e - mm * k;
+        G1[((size_t)mm * n + i) * k + l] = h[e];
+    }
 }
 
 // One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread.
 // For FP8 graphs the bf16 copy used by the penalty pass is written as well.
 __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                int honor_stop, int next) {
+                                                int honor_stop, int next, int gate) {
     const int b = blockIdx.x;
     if (b >= total_blocks) return;
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ex_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
+    // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
+    const bool want_sp2 = d.precision == kPrecFP8 && (!gate || !d.sparse);
     const int cgs = d.n_pad / 16;
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
     const int row = (int)(item / cgs);
@@ -133,13 +246,19 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
     if (row >= d.ncols) return;
     const int dm = row / d.k;
     const int l = row - dm * d.k;
-    const int16_t* c = d.c[p] + (size_t)dm * d.n;
+    const int16_t* c = d.c[p] + (size_t)dm * d.cs;
     const int j0 = cg * 16;
     uint32_t mask = 0;   // bit q set when column j0+q has colour l
+    if (j0 < d.n) {
+        // 16 colours in two 16-byte loads (rows are padded to 64 entries)
+        const uint4 a = *(const uint4*)(c + j0);
+        const uint4 b = *(const uint4*)(c + j0 + 8);
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        int j = j0 + q;
-        if (j < d.n && c[j] == l) mask |= 1u << q;
+        for (int q = 0; q < 16; ++q) {
+            const int col = (int)((w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
+            if (j0 + q < d.n && col == l) mask |= 1u << q;
+        }
     }
     const size_t off = (size_t)row * d.n_pad + j0;
     if (d.precision == kPrecFP32) {
@@ -158,6 +277,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
         uint4* o = (uint4*)(sb + off);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
+            if (!want_sp2 && d.precision == kPrecFP8) break;
             uint32_t w[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -203,6 +323,7 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
     if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
+    if ((flags & kFlagGate) && d.sparse) return;
     const int p = st->pS;
     // upper-triangle tile (ti <= tj)
     int u = b - d.mt_begin, ti = 0, T = d.mt_T;
@@ -220,7 +341,7 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
         __syncthreads();
         for (int e = threadIdx.x; e < dn * 64; e += 256) {
             int dm = e >> 6, x = e & 63;
-            const int16_t* cr = d.c[p] + (size_t)(dbase + dm) * d.n;
+            const int16_t* cr = d.c[p] + (size_t)(dbase + dm) * d.cs;
             // out-of-range vertices get distinct sentinels so they never match
             ci[dm][x] = (i0 + x < d.n) ? cr[i0 + x] : (int16_t)-1;
             cj[dm][x] = (j0 + x < d.n) ? cr[j0 + x] : (int16_t)-2;
@@ -331,11 +452,23 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
     __syncthreads();
     if (flags & kFlagReport) return;
     const int ld = best == 0x7FFFFFFF ? -1 : best;
-    if (ld >= 0 && d.stop_on_legal) {
-        const int16_t* c = d.c[p] + (size_t)ld * d.n;
+    const bool stop = ld >= 0 && d.stop_on_legal;
+    if (stop) {
+        const int16_t* c = d.c[p] + (size_t)ld * d.cs;
         for (int i = threadIdx.x; i < d.n; i += blockDim.x) d.snap[i] = c[i];
         if (threadIdx.x == 0) {
             st->legal_d = ld;
+            st->stopped = 1;
+        }
+    }
+    if ((flags & kFlagFused) && threadIdx.x == 0 && !stop) {
+        // fused path: the contraction kernel wrote the update into the other buffers
+        st->pW ^= 1;
+        st->pS ^= 1;
+        st->t += 1;
+        st->steps_done += 1;
+        if (st->next_bad) {
+            st->error = -5;
             st->stopped = 1;
         }
     }
@@ -397,6 +530,103 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
     }
 }
 
+// Step 4 with the row held in registers, one (member, vertex) row per 16-lane
+// group, k <= 16 KPL: softmax along k (max subtracted), straight-through
+// gradient gW = s^ (G - sum_l s^_l G_l), update, smoothing, and in mode 0 the
+// argmax colouring of the updated row for the next iteration (written over
+// this iteration's colours).  Mode 1 writes gS and gW of graph gsel instead.
+template <int KPL>
+__global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict__ gd, int G, int total_rows,
+                                                     int honor_stop, int mode, int gsel, float* __restrict__ gS_out,
+                                                     float* __restrict__ gW_out) {
+    const int l16 = threadIdx.x & 15;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (row >= total_rows) return;
+    const int g = graph_of_row(gd, G, row);
+    if (gsel >= 0 && g != gsel) return;
+    const GraphDev& d = gd[g];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    const int r = row - d.row_begin;
+    const int k = d.k;
+    const int m = r / d.n, i = r - m * d.n;
+    float* w = d.W[0] + (size_t)r * k;
+    const float* gs = d.G + (size_t)r * k;
+    const long long t = st->t;
+    const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+    const int32_t* V = d.V[st->pS] + (size_t)m * k;
+    float wv[KPL], gv[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        const int l = l16 + 16 * q;
+        if (l < k) {
+            wv[q] = w[l];
+            float x = gs[l];
+            if (nut != 0.0f) x += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+            gv[q] = x;
+        } else {
+            wv[q] = -INFINITY;
+            gv[q] = 0.0f;
+        }
+    }
+    float mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) mx = fmaxf(mx, wv[q]);
+    for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+    float ev[KPL];
+    float z = 0.0f, qs = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        ev[q] = (l16 + 16 * q < k) ? expf(wv[q] - mx) : 0.0f;
+        z += ev[q];
+        qs += ev[q] * gv[q];
+    }
+    for (int s = 8; s >= 1; s >>= 1) {
+        z += __shfl_xor(z, s, 16);
+        qs += __shfl_xor(qs, s, 16);
+    }
+    const float rz = 1.0f / z;
+    const float rq = qs * rz;
+    if (mode == 1) {
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+            const int l = l16 + 16 * q;
+            if (l < k) {
+                if (gS_out) gS_out[(size_t)r * k + l] = gv[q];
+                if (gW_out) gW_out[(size_t)r * k + l] = ev[q] * rz * (gv[q] - rq);
+            }
+        }
+        return;
+    }
+    const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
+    float best = -INFINITY;
+    int bi = 0x7FFFFFFF, bad = 0;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        const int l = l16 + 16 * q;
+        if (l < k) {
+            float nw = wv[q] - d.eta * (ev[q] * rz * (gv[q] - rq));
+            if (smooth) nw = nw / d.rho;
+            w[l] = nw;
+            if (!finite_f(nw)) bad = 1;
+            if (nw > best) { best = nw; bi = l; }
+        }
+    }
+    for (int s = 8; s >= 1; s >>= 1) {
+        const float ob = __shfl_xor(best, s, 16);
+        const int oi = __shfl_xor(bi, s, 16);
+        bad |= __shfl_xor(bad, s, 16);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (l16 == 0) {
+        if (bad || bi >= k) {
+            bi = 0;
+            atomicExch(&st->next_bad, 1);
+        }
+        d.c[st->pS][(size_t)m * d.cs + i] = (int16_t)bi;
+    }
+}
+
 // t <- t + 1 for every graph still running.
 __global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -405,6 +635,11 @@ __global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
     if (st->stopped) return;
     st->t += 1;
     st->steps_done += 1;
+    if (st->next_bad) {
+        // the update just made produced a non-finite weight
+        st->error = -5;
+        st->stopped = 1;
+    }
 }
 
 // FP64 loss of one graph: L = sum f_color + nu t sum f_eq + lambda t kappa - mu t varpi.
@@ -447,7 +682,10 @@ __global__ void k_copy_report(const GraphDev* __restrict__ gd, int g, int16_t* c
     const int p = d.st->pS;
     const size_t total = (size_t)d.D * d.n;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        if (colors) colors[e] = d.c[p][e];
+        if (colors) {
+            const size_t m = e / d.n;
+            colors[e] = d.c[p][m * d.cs + (e - m * d.n)];
+        }
         if (e < (size_t)d.D) {
             if (fcol) fcol[e] = d.fcol[e];
             if (feq) feq[e] = d.feq[e];
@@ -460,11 +698,13 @@ __global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_on
     if (g >= G || (g_only >= 0 && g != g_only)) return;
     GraphState* st = gd[g].st;
     if (op == 0) {            // reset run state (keeps t)
-        st->stopped = 0; st->error = 0; st->legal_d = -1; st->steps_done = 0;
+        st->stopped = 0; st->error = 0; st->legal_d = -1; st->steps_done = 0; st->next_bad = 0;
     } else if (op == 1) {     // set t
         st->t = t;
     } else if (op == 2) {     // clear steps counter only
         st->steps_done = 0; st->legal_d = -1;
+    } else if (op == 3) {     // the caller's buffer holds the weights again
+        st->pW = 0;
     }
 }
 
@@ -488,18 +728,34 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
     return hipSuccess;
 }
 
-hipError_t launch_class_sizes(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next,
-                              hipStream_t s) {
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next, hipStream_t s) {
     if (total_mem <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_class_sizes, dim3(total_mem), dim3(256), sizeof(int) * kmax, s, gd, G, total_mem,
+    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), sizeof(int) * (size_t)kmax, s, gd, G, total_mem,
                        honor_stop, next);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, hipStream_t s) {
+hipError_t penalty_rows_prepare() {
+    return hipFuncSetAttribute((const void*)k_penalty_rows, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t launch_penalty_rows(const GraphDev* gd, int G, int total_vtx, int honor_stop, int dk_max, hipStream_t s) {
+    if (total_vtx <= 0 || dk_max <= 0) return hipSuccess;
+    const size_t per_row = sizeof(float) * (size_t)dk_max;
+    int wpb = (int)((160 * 1024) / per_row);
+    wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+    const int blocks = ceil_div(total_vtx, wpb);
+    hipLaunchKernelGGL(k_penalty_rows, dim3(blocks), dim3(256), per_row * wpb, s, gd, G, total_vtx, honor_stop, wpb,
+                       dk_max);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
+                         hipStream_t s) {
     if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand, dim3(total_blocks), dim3(256), 0, s, gd, G, total_blocks, honor_stop, next);
+    hipLaunchKernelGGL(k_expand, dim3(total_blocks), dim3(256), 0, s, gd, G, total_blocks, honor_stop, next, gate);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -524,6 +780,30 @@ hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_st
     if (total_rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_update, dim3(ceil_div(total_rows, 16)), dim3(256), 0, s, gd, G, total_rows, honor_stop,
                        mode, gsel, gS_out, gW_out);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int update_rows_kpl(int kmax) {
+    const int need = (kmax + 15) / 16;
+    for (int kpl : {2, 4, 6, 8, 12, 18})
+        if (kpl >= need) return kpl;
+    return 0;
+}
+
+hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int honor_stop, int mode, int gsel,
+                              float* gS_out, float* gW_out, hipStream_t s) {
+    if (total_rows <= 0) return hipSuccess;
+    const dim3 grid(ceil_div(total_rows, 16)), blk(256);
+    switch (update_rows_kpl(kmax)) {
+        case 2: hipLaunchKernelGGL(k_update_rows<2>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 4: hipLaunchKernelGGL(k_update_rows<4>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 6: hipLaunchKernelGGL(k_update_rows<6>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 8: hipLaunchKernelGGL(k_update_rows<8>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 12: hipLaunchKernelGGL(k_update_rows<12>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 18: hipLaunchKernelGGL(k_update_rows<18>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        default: return hipErrorInvalidValue;
+    }
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -8,14 +8,21 @@ namespace tcol {
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
                              hipStream_t s);
 hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s);
-hipError_t launch_class_sizes(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next,
-                              hipStream_t s);
-hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, hipStream_t s);
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next, hipStream_t s);
+hipError_t penalty_rows_prepare();
+// dk_max: largest D*k of a graph on the sparse penalty
+hipError_t launch_penalty_rows(const GraphDev* gd, int G, int total_vtx, int honor_stop, int dk_max, hipStream_t s);
+hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
+                         hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
                          int32_t* mt_out, hipStream_t s);
 hipError_t launch_fitness(const GraphDev* gd, int G, int honor_stop, int flags, int gsel, hipStream_t s);
 hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_stop, int mode, int gsel,
                          float* gS_out, float* gW_out, hipStream_t s);
+// register-resident row update for k <= 288 (update_rows_kpl(kmax) != 0); mode 0 also colours the new rows
+int update_rows_kpl(int kmax);
+hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int honor_stop, int mode, int gsel,
+                              float* gS_out, float* gW_out, hipStream_t s);
 hipError_t launch_advance(const GraphDev* gd, int G, hipStream_t s);
 hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipStream_t s);
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
@@ -24,14 +31,17 @@ hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long
 
 // MFMA contraction G = A.S (+ P.S) with the conflict gather.
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
-//   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue
+//   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
+//           bit 3 = dense penalty operand even for graphs on the sparse penalty rows
 struct GemmShape {
     int prec, bm, ntw, mode;
 };
 bool gemm_supported(const GemmShape& s);
 hipError_t gemm_prepare(const GemmShape& s);       // sets the LDS attribute of the instantiation
 hipError_t launch_gemm(const GemmShape& s, const GraphDev* gd, int G, int total_tiles, int honor_stop,
-                       int passes, hipStream_t st);
+                       int passes, int cstage, hipStream_t st);
+// dynamic LDS of a GEMM launch (cstage: bytes of member colours staged by the fused epilogue)
+size_t gemm_lds_bytes(const GemmShape& s, int cstage);
 int gemm_bn(int ntw);
 
 }  // namespace tcol

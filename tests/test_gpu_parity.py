@@ -93,11 +93,13 @@ def test_loss_and_gradients(case, t):
     s.close()
 
 
-def run_resynced(case, steps, tol, check_every=1):
+def run_resynced(case, steps, tol, check_every=1, t0=0, W=None, **opts):
     """Step the GPU one iteration at a time; before each step feed its W to the oracle and compare."""
-    s, (A,) = make_solver([case])
+    s, (A,) = make_solver([case], Ws=None if W is None else [W], **opts)
     p = orc_params(case.params())
-    t = 0
+    t = t0
+    if t0:
+        s.set_t(t0)
     worst = 0.0
     for it in range(steps):
         W0 = host(s.W[0])
@@ -123,22 +125,53 @@ def run_resynced(case, steps, tol, check_every=1):
     return worst
 
 
-def test_c1_resynced_200_steps():
-    worst = run_resynced(tcolgen.case_c1(), 200, TOL, check_every=10)
-    print(f"C1 worst W error {worst:.2e}")
+PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_sparse": dict(fused=1, penalty=2),
+         "epi_dense": dict(fused=2, penalty=1), "epi_sparse": dict(fused=2, penalty=2)}
 
 
+@pytest.mark.parametrize("path", list(PATHS))
+def test_c1_resynced_200_steps(path):
+    worst = run_resynced(tcolgen.case_c1(), 200, TOL, check_every=10, **PATHS[path])
+    print(f"C1 {path} worst W error {worst:.2e}")
+
+
+@pytest.mark.parametrize("path", [p for p in PATHS if p != "plain"])
+@pytest.mark.parametrize("prec", [FP32, BF16, FP8])
+def test_fused_large_k_resynced(path, prec):
+    """Many colours against few members (the shape where the penalty operand is sparse),
+    ECP so every loss term is active, a ragged n and several tiles."""
+    case = GraphCase(f"ecp_n600_k120_D8_p{prec}", ECP, 600, 120, 8, prec, "gnp", 0.5, graph_seed=31, rho=10.0,
+                     lam=2e-2, mu=5e-3, nu=0.05)
+    tol = TOL if (prec == FP32 or path.endswith("sparse")) else 1e-2
+    worst = run_resynced(case, 8, tol, t0=3, **PATHS[path])
+    print(f"{case.name} {path}: worst W error vs FP64 {worst:.2e}")
+
+
+@pytest.mark.parametrize("path", [p for p in PATHS if p != "plain"])
+def test_degenerate_population(path):
+    """Every vertex in one colour in every member: Mt is all D, the penalty operand is dense
+    and every row of the sparse kernel visits all n vertices."""
+    n, k, D = 300, 100, 8
+    case = GraphCase("degenerate", KCOL, n, k, D, FP32, "gnp", 0.5, graph_seed=33, lam=1e-2, mu=1e-3)
+    W = case.weights()
+    W[:, :, 0] += 1.0
+    worst = run_resynced(case, 3, TOL, t0=2, W=W, **PATHS[path])
+    print(f"degenerate worst W error {worst:.2e}")
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("prec", [BF16, FP8])
-def test_small_resynced_low_precision(prec):
+def test_small_resynced_low_precision(prec, path):
     case = GraphCase("kcol90", KCOL, 90, 9, 6, prec, "gnp", 0.5, graph_seed=12, rho=10.0, lam=1e-2, mu=3e-3)
     # bf16 penalty operand: errors against FP64 are reported; the bound only catches wrong arithmetic
-    worst = run_resynced(case, 30, 1e-2)
+    worst = run_resynced(case, 30, TOL if path.endswith("sparse") else 1e-2, **PATHS[path])
     print(f"prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
-def test_c2_resynced_steps():
-    worst = run_resynced(tcolgen.case_c2(FP32), 12, TOL, check_every=4)
-    print(f"C2 worst W error {worst:.2e}")
+@pytest.mark.parametrize("path", list(PATHS))
+def test_c2_resynced_steps(path):
+    worst = run_resynced(tcolgen.case_c2(FP32), 12, TOL, check_every=4, **PATHS[path])
+    print(f"C2 {path} worst W error {worst:.2e}")
 
 
 def test_planted_stops_at_step0():
@@ -146,9 +179,9 @@ def test_planted_stops_at_step0():
     P = tcolgen.planted(case.n, case.k, case.graph_seed)
     W = case.weights()
     W[5, np.arange(case.n), P.classes] += 1.0     # member 5 holds the hidden legal colouring
-    for prec in (FP8, BF16, FP32):
+    for prec, fused in ((FP8, 1), (BF16, 2), (FP32, 0), (FP8, 0), (FP8, 2)):
         case.precision = prec
-        s, _ = make_solver([case], As=[P.A], Ws=[W])
+        s, _ = make_solver([case], As=[P.A], Ws=[W], fused=fused)
         c, fc, fe = s.conflicts(0)
         assert int(host(fc)[5]) == 0
         c_ref = oracle.colors(W)
@@ -209,14 +242,15 @@ def test_nonfinite_and_bad_graph():
 def test_graph_replay_matches_eager_and_is_deterministic():
     case = GraphCase("det", KCOL, 200, 20, 8, BF16, "gnp", 0.5, graph_seed=5, rho=10.0, lam=1e-3, mu=1e-4,
                      stop_on_legal=0)
-    outs = []
-    for use_graph, unroll in ((0, 1), (1, 4), (1, 8)):
-        s, _ = make_solver([case], use_graph=use_graph, unroll=unroll)
-        done, _ = s.step(23)
-        assert done == 23 and s.get_t() == 23
-        outs.append(host(s.W[0]).copy())
-        s.close()
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for fused, pen in ((0, 0), (1, 1), (1, 2), (2, 1), (2, 2)):
+        outs = []
+        for use_graph, unroll in ((0, 1), (1, 4), (1, 8)):
+            s, _ = make_solver([case], use_graph=use_graph, unroll=unroll, fused=fused, penalty=pen)
+            done, _ = s.step(23)
+            assert done == 23 and s.get_t() == 23
+            outs.append(host(s.W[0]).copy())
+            s.close()
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
 def test_checkpoint_resume():
@@ -243,17 +277,20 @@ def test_batch_of_uneven_graphs_matches_separate_contexts():
     cases = [GraphCase("b0", KCOL, 130, 12, 4, BF16, "gnp", 0.5, graph_seed=21, lam=1e-3, mu=1e-4, stop_on_legal=0),
              GraphCase("b1", ECP, 257, 19, 3, BF16, "gnp", 0.1, graph_seed=22, mu=0.0, nu=1e-3, stop_on_legal=0),
              GraphCase("b2", KCOL, 64, 30, 7, BF16, "gnp", 0.9, graph_seed=23, alpha=1.5, stop_on_legal=0)]
-    sb, _ = make_solver(cases)
-    sb.step(9)
-    batch_W = [host(w).copy() for w in sb.W]
-    batch_f = [host(sb.conflicts(g)[1]) for g in range(3)]
-    sb.close()
-    for g, c in enumerate(cases):
-        s1, _ = make_solver([c])
-        s1.step(9)
-        assert np.array_equal(host(s1.W[0]), batch_W[g])
-        assert np.array_equal(host(s1.conflicts(0)[1]), batch_f[g])
-        s1.close()
+    for fused in (0, 1, 2):
+        sb, _ = make_solver(cases, fused=fused)
+        o = sb.options()
+        sb.step(9)
+        batch_W = [host(w).copy() for w in sb.W]
+        batch_f = [host(sb.conflicts(g)[1]) for g in range(3)]
+        sb.close()
+        for g, c in enumerate(cases):
+            # same tile shape as the batch: the per-element arithmetic is then identical
+            s1, _ = make_solver([c], fused=fused, tile_bm=o["tile_bm"], tile_ntw=o["tile_ntw"])
+            s1.step(9)
+            assert np.array_equal(host(s1.W[0]), batch_W[g])
+            assert np.array_equal(host(s1.conflicts(0)[1]), batch_f[g])
+            s1.close()
 
 
 def test_autograd_backward_matches_step_and_finite_differences():
