@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--tile-bm", type=int, default=0)
     ap.add_argument("--tile-ntw", type=int, default=0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the population step on a single MI355X "
@@ -155,6 +157,14 @@ def main():
                "frac": f_as / as_s / PEAK[prec], "ms_per_launch": ph["gemm_as_only"]}
     print(f"[bench] phases ms {json.dumps({k: round(v, 4) for k, v in ph.items()})}", file=sys.stderr, flush=True)
     s.close()
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the others
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

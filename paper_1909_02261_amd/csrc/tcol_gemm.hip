@@ -12,10 +12,12 @@
 // with BN = 32 * NTW; each wave owns (BM/2) x (16 NTW) as 16x16 MFMA subtiles.
 // Both operands are K-contiguous; a K-stage moves 128 bytes of every operand
 // row straight from global memory into LDS (global_load_lds, 16 bytes per
-// lane, no registers on the way), double buffered: the loads of stage s+1 are
-// in flight while stage s feeds the MFMAs.  Within a 128-byte LDS row the
-// 16-byte chunk c of row r sits in slot c ^ (r mod 8), so the fragment reads of
-// 8 consecutive rows hit 8 different bank groups.
+// lane, no registers on the way), triple buffered: the loads of stages s+1 and
+// s+2 are in flight while stage s feeds the MFMAs.  Within a 128-byte LDS row the
+// 16-byte chunk c of row r sits in slot c ^ ((r / 2) mod 8): a fragment read
+// covers 16 consecutive rows at one chunk, and with 64 four-byte banks the bank
+// of (row, slot) depends on (row mod 2, slot), so those 16 reads land in 16
+// different bank groups.
 //
 // Mode 0 stores G as [D][n][k] fp32 for the separate update kernel.
 // Mode 1 (fused): column tiles hold whole members; the accumulators go through
@@ -53,14 +55,14 @@ struct Tile {
     static_assert((BM + BN) % 32 == 0, "load split");
 };
 
-// compute one LDS stage into acc (operand format PREC); chunk c of row r is at slot c ^ (r & 7)
+// compute one LDS stage into acc (operand format PREC); chunk c of row r is at slot c ^ ((r >> 1) & 7)
 template <int PREC, int BM, int NTW>
 __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, int lane, int wm, int wn) {
     constexpr int MT = BM / 32;
     const int ra = wm * (BM / 2) + (lane & 15);
     const int rb = BM + wn * (NTW * 16) + (lane & 15);
     const int q = lane >> 4;
-    const int swz = lane & 7;          // = row & 7 for every row this lane reads
+    const int swz = (lane & 15) >> 1;  // = (row >> 1) & 7 for every row this lane reads
     if constexpr (PREC == kPrecFP8) {
         const int o0 = ((2 * q) ^ swz) * 16, o1 = ((2 * q + 1) ^ swz) * 16;
         i32x8 a[MT];
@@ -121,7 +123,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 
 // Issue the direct-to-LDS loads of one K-stage.  Wave w moves the 8-row groups
 // w, w+4, ...; lane L of a group writes LDS bytes [16L, 16L+16) of the group, i.e.
-// row L/8, slot L%8, which receives global chunk (L%8) ^ (row & 7).
+// row L/8, slot L%8, which receives global chunk (L%8) ^ ((row >> 1) & 7).
 template <int BM, int NTW>
 __device__ __forceinline__ void stage_load(const uint8_t* __restrict__ Arow, const uint8_t* __restrict__ Brow,
                                            size_t ld, int s, uint8_t* buf, int lane, int wave) {
@@ -131,15 +133,31 @@ __device__ __forceinline__ void stage_load(const uint8_t* __restrict__ Arow, con
     for (int gi = 0; gi < T::GROUPS; ++gi) {
         const int grp = wave + 4 * gi;
         const int r = grp * 8 + rsub;
-        const int c = slot ^ (r & 7);
+        const int c = slot ^ ((r >> 1) & 7);
         const uint8_t* src = (r < BM ? Arow + (size_t)r * ld : Brow + (size_t)(r - BM) * ld) +
                              (size_t)s * kStageRowBytes + c * 16;
         __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(buf + grp * 8 * kStageRowBytes), 16, 0, 0);
     }
 }
 
-// vmcnt(0): this wave's loads, including those that write LDS, have landed
-__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt vmcnt(N) (N <= 63) with expcnt / lgkmcnt left alone: at most N of this
+// wave's vector memory operations, including the ones that write LDS, are in flight
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+constexpr int kStages = 3;   // LDS stage buffers
+
+// Workgroup barrier without the memory fence of __syncthreads(): that fence would
+// make every wave drain all its loads, including the prefetches of later stages.
+// Visibility of the LDS stages is ordered explicitly by wait_vm before it.
+__device__ __forceinline__ void stage_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 // One K-sweep: acc += Arows[m0.., :] . Brows[n0.., :]^T over `nstages` stages
 // of 128 bytes.  Arow / Brow point at the first row of the tile; ld in bytes.
@@ -152,15 +170,18 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[BM / 32][NTW], const uin
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     stage_load<BM, NTW>(Arow, Brow, ld, 0, lds, lane, wave);
-    wait_vm();
-    __syncthreads();
+    stage_load<BM, NTW>(Arow, Brow, ld, min(1, nstages - 1), lds + T::STAGE, lane, wave);
+    wait_vm<T::GROUPS>();          // stage 0 has landed, stage 1 may be in flight
+    stage_barrier();
+    int cur = 0;
     for (int s = 0; s < nstages; ++s) {
-        const int buf = s & 1;
-        // the last iteration reloads its own stage into the idle buffer; nobody reads it
-        stage_load<BM, NTW>(Arow, Brow, ld, min(s + 1, nstages - 1), lds + (buf ^ 1) * T::STAGE, lane, wave);
-        stage_mma<PREC, BM, NTW>(acc, lds + buf * T::STAGE, lane, wm, wn);
-        wait_vm();
-        __syncthreads();
+        const int nxt = cur >= kStages - 2 ? cur - (kStages - 2) : cur + 2;   // (s + 2) mod 3
+        // stages past the end reload the last one into the idle buffer; nobody reads it
+        stage_load<BM, NTW>(Arow, Brow, ld, min(s + 2, nstages - 1), lds + nxt * T::STAGE, lane, wave);
+        stage_mma<PREC, BM, NTW>(acc, lds + cur * T::STAGE, lane, wm, wn);
+        wait_vm<T::GROUPS>();      // stage s+1 has landed, stage s+2 may be in flight
+        stage_barrier();
+        cur = cur == kStages - 1 ? 0 : cur + 1;
     }
 }
 
@@ -197,7 +218,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     constexpr int MT = T::MT;
     constexpr int BN = T::BN;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int* f2l = (int*)(lds + 2 * T::STAGE);     // BN + 2 gather counters
+    int* f2l = (int*)(lds + kStages * T::STAGE);     // BN + 2 gather counters
 
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     int g, tm, tn;
@@ -403,7 +424,7 @@ constexpr int kMaxLds = 160 * 1024;
 template <int BM, int NTW, int MODE>
 static size_t lds_bytes(int cstage) {
     using T = Tile<BM, NTW>;
-    const size_t sweep = 2 * T::STAGE + sizeof(int) * (T::BN + 2);
+    const size_t sweep = kStages * T::STAGE + sizeof(int) * (T::BN + 2);
     if (MODE == 0) return sweep;
     const size_t epi = (size_t)(BM < 128 ? BM : 128) * (T::BN + 4) * sizeof(float) + (size_t)cstage;
     return sweep > epi ? sweep : epi;
