@@ -219,6 +219,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     constexpr int BN = T::BN;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int* f2l = (int*)(lds + kStages * T::STAGE);     // BN + 2 gather counters
+    static_assert((BN + 2) * BM * 2 <= kStages * T::STAGE, "gather colours fit the stage buffers");
 
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     int g, tm, tn;
@@ -233,6 +234,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     // kernel (already in G); the plain path (passes bit 3) always takes the dense pass
     const bool sparse_pen = pen && d.sparse && !(passes & 8);
     const bool dense_pen = pen && !sparse_pen;
+
+    // graph fields in registers: reading them through gd after a store or an
+    // atomic would reload them, one dependent round trip per use
+    const int n = d.n, k = d.k, cs = d.cs;
+    const int16_t* __restrict__ colr = d.c[pS];
+    float* __restrict__ Gg = d.G;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -276,25 +283,32 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     if (passes & 1) {
         gemm_sweep<PREC, BM, NTW>(acc, (const uint8_t*)d.Aop + (size_t)m0 * ld,
                                   (const uint8_t*)d.Sop[pS] + (size_t)n0 * ld, ld, nst, lds);
-        // gather 2 f_color: sum over rows i of (A.S_d)[i, c_d(i)]
-        for (int e = tid; e < BN + 2; e += 256) f2l[e] = 0;
+        // gather 2 f_color: sum over rows i of (A.S_d)[i, c_d(i)].  The colours of
+        // the tile's rows for its members go to LDS first (the stage buffers are
+        // free once every wave is past the barrier), in coalesced loads.
+        __syncthreads();
+        const int dlast = (ncol_end - 1) / k;
+        const int nm = dlast - dfirst + 1;
+        int16_t* ct = (int16_t*)lds;   // [nm][BM]
+        for (int e = tid; e < nm * BM; e += 256) {
+            const int dm = e / BM, r = e - dm * BM;
+            ct[e] = m0 + r < n ? colr[(size_t)(dfirst + dm) * cs + m0 + r] : (int16_t)-1;
+        }
+        for (int e = tid; e < nm; e += 256) f2l[e] = 0;
         __syncthreads();
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = m0 + wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
-                if (i < d.n) {
+                const int ri = wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
 #pragma unroll
-                    for (int nt = 0; nt < NTW; ++nt) {
-                        if (cm[nt] >= 0 && d.c[pS][(size_t)cm[nt] * d.cs + i] == cl[nt])
-                            atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
-                    }
+                for (int nt = 0; nt < NTW; ++nt) {
+                    if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
+                        atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
                 }
             }
         __syncthreads();
-        const int dlast = (ncol_end - 1) / d.k;
-        for (int e = tid; e <= dlast - dfirst; e += 256)
+        for (int e = tid; e < nm; e += 256)
             if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);
     }
     if ((passes & 2) && dense_pen) {
@@ -317,11 +331,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = m0 + wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
-                if (i < d.n) {
+                if (i < n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
                         if (cm[nt] >= 0) {
-                            float* gp = d.G + ((size_t)cm[nt] * d.n + i) * d.k + cl[nt];
+                            float* gp = Gg + ((size_t)cm[nt] * n + i) * k + cl[nt];
                             *gp = sparse_pen ? acc[mt][nt][r] + *gp : acc[mt][nt][r];
                         }
                 }
@@ -331,16 +345,18 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
         constexpr int EPI = BM < 128 ? BM : 128;
         constexpr int LDG = BN + 4;
         float* Gt = (float*)lds;
-        const int k = d.k, n = d.n;
         const int nmem = min(d.gm_mpb, d.D - d0);
         const int g16 = tid >> 4, l16 = tid & 15;
         const long long t = st->t;
         const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
         const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
         const int pW = st->pW;
-        const float* Wc = d.W[pW];
-        float* Wn = d.W[pW ^ 1];
-        int16_t* cn = d.c[pS ^ 1];
+        const float* __restrict__ Wc = d.W[pW];
+        float* __restrict__ Wn = d.W[pW ^ 1];
+        int16_t* __restrict__ cn = d.c[pS ^ 1];
+        const int32_t* __restrict__ Vp = d.V[pS];
+        const float eta = d.eta, rho = d.rho;
+        const int c1 = d.c1, c2 = d.c2;
 #pragma unroll 1
         for (int h = 0; h < BM / EPI; ++h) {
             __syncthreads();
@@ -366,8 +382,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 const float* w = Wc + rowoff;
                 float* wo = Wn + rowoff;
                 const float* gr = Gt + r * LDG + dm * k;
-                const float* g1 = d.G + rowoff;      // penalty rows of the sparse kernel
-                const int32_t* V = d.V[pS] + (size_t)dd * k;
+                const float* g1 = Gg + rowoff;      // penalty rows of the sparse kernel
+                const int32_t* V = Vp + (size_t)dd * k;
                 float mx = -INFINITY;
                 for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
                 for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
@@ -376,7 +392,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                     const float e = expf(w[l] - mx);
                     float gv = gr[l];
                     if (sparse_pen) gv += g1[l];
-                    if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+                    if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
                     z += e;
                     q += e * gv;
                 }
@@ -392,9 +408,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                     const float e = expf(w[l] - mx) * rz;
                     float gv = gr[l];
                     if (sparse_pen) gv += g1[l];
-                    if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
-                    float nw = w[l] - d.eta * (e * (gv - rq));
-                    if (smooth) nw = nw / d.rho;
+                    if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
+                    float nw = w[l] - eta * (e * (gv - rq));
+                    if (smooth) nw = nw / rho;
                     wo[l] = nw;
                     if ((__float_as_uint(nw) & 0x7F800000u) == 0x7F800000u) bad = 1;
                     if (nw > best) { best = nw; bi = l; }
@@ -410,7 +426,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                         bi = 0;
                         atomicExch(&st->next_bad, 1);
                     }
-                    cn[(size_t)dd * d.cs + i] = (int16_t)bi;
+                    cn[(size_t)dd * cs + i] = (int16_t)bi;
                 }
             }
         }

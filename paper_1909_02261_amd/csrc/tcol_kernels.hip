@@ -184,6 +184,8 @@ __global__ __launch_bounds__(256) void k_penalty_rows(const GraphDev* __restrict
     const uint32_t* ciw = (const uint32_t*)(d.cT + (size_t)i * d.cTs);
     const int nw = D >> 1;
     const bool odd = D & 1;
+    const int16_t* __restrict__ cT = d.cT;
+    const size_t cTs = d.cTs;
     for (int j0 = 0; j0 < n; j0 += 64) {
         // member lanes: colours c_lane(j0 .. j0+63), eight 16-byte loads
         uint4 w[8];
@@ -194,9 +196,9 @@ __global__ __launch_bounds__(256) void k_penalty_rows(const GraphDev* __restrict
         float P = 0.0f;
         int m = 0;
         if (j < n) {
-            const int16_t* cj = d.cT + (size_t)j * d.cTs;
+            const int16_t* cj = cT + (size_t)j * cTs;
             for (int q = 0; q < nw; ++q) m += equal_halves(ciw[q], *(const uint32_t*)(cj + 2 * q));
-            if (odd) m += (cj[D - 1] == d.cT[(size_t)i * d.cTs + D - 1]) ? 1 : 0;
+            if (odd) m += (cj[D - 1] == cT[(size_t)i * cTs + D - 1]) ? 1 : 0;
         }
         const float lp = __shfl(lutp, m > 0 ? m - 1 : 0, 64);
         const float lb = __shfl(lutb, m > 0 ? m - 1 : 0, 64);
@@ -361,6 +363,16 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
     const bool mirror = ti != tj;
     double ka = 0.0, vb = 0.0;
     const bool fp32 = d.precision == kPrecFP32;
+    // fields used between the stores below stay in registers (no reload through gd)
+    const int n = d.n;
+    const size_t n_pad = d.n_pad;
+    const uint8_t* __restrict__ A8 = d.A8;
+    const float* __restrict__ lut_pen = d.lut_pen;
+    const float* __restrict__ lut_bon = d.lut_bon;
+    const double* __restrict__ lut_ka = d.lut_ka;
+    const double* __restrict__ lut_vb = d.lut_vb;
+    const bool bdiag = d.bonus_diag != 0;
+    void* __restrict__ Pop = d.Pop;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int i = i0 + ty * 4 + a;
@@ -368,30 +380,30 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
         for (int q = 0; q < 4; ++q) {
             const int j = j0 + tx * 4 + q;
             float val = 0.0f;
-            if (i < d.n && j < d.n) {
+            if (i < n && j < n) {
                 const int m = cnt[a][q];
-                const bool edge = d.A8[(size_t)i * d.n_pad + j] != 0;
-                const bool bon = !edge && (i != j || d.bonus_diag);
-                if (edge) val = tf * d.lut_pen[m];
-                else if (bon) val = -(tf * d.lut_bon[m]);
+                const bool edge = A8[(size_t)i * n_pad + j] != 0;
+                const bool bon = !edge && (i != j || bdiag);
+                if (edge) val = tf * lut_pen[m];
+                else if (bon) val = -(tf * lut_bon[m]);
                 if (flags & kFlagLoss) {
                     const double wgt = mirror ? 2.0 : 1.0;
-                    if (edge) ka += wgt * d.lut_ka[m];
-                    else if (bon) vb += wgt * d.lut_vb[m];
+                    if (edge) ka += wgt * lut_ka[m];
+                    else if (bon) vb += wgt * lut_vb[m];
                 }
                 if ((flags & kFlagMtOut) && mt_out) {
-                    mt_out[(size_t)i * d.n + j] = m;
-                    if (mirror) mt_out[(size_t)j * d.n + i] = m;
+                    mt_out[(size_t)i * n + j] = m;
+                    if (mirror) mt_out[(size_t)j * n + i] = m;
                 }
             }
             if (pen || (flags & kFlagForcePen)) {
                 if (fp32) {
-                    ((float*)d.Pop)[(size_t)i * d.n_pad + j] = val;
-                    if (mirror) ((float*)d.Pop)[(size_t)j * d.n_pad + i] = val;
+                    ((float*)Pop)[(size_t)i * n_pad + j] = val;
+                    if (mirror) ((float*)Pop)[(size_t)j * n_pad + i] = val;
                 } else {
                     const uint16_t h = f32_to_bf16_rne(val);
-                    ((uint16_t*)d.Pop)[(size_t)i * d.n_pad + j] = h;
-                    if (mirror) ((uint16_t*)d.Pop)[(size_t)j * d.n_pad + i] = h;
+                    ((uint16_t*)Pop)[(size_t)i * n_pad + j] = h;
+                    if (mirror) ((uint16_t*)Pop)[(size_t)j * n_pad + i] = h;
                 }
             }
         }
@@ -555,6 +567,10 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     const long long t = st->t;
     const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
     const int32_t* V = d.V[st->pS] + (size_t)m * k;
+    // fields used after the stores below stay in registers (no reload through gd)
+    const int c1 = d.c1, c2 = d.c2;
+    const float eta = d.eta, rho = d.rho;
+    int16_t* __restrict__ cnext = d.c[st->pS] + (size_t)m * d.cs;
     float wv[KPL], gv[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
@@ -562,7 +578,7 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
         if (l < k) {
             wv[q] = w[l];
             float x = gs[l];
-            if (nut != 0.0f) x += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+            if (nut != 0.0f) x += nut * (float)((V[l] > c2) - (V[l] < c1));
             gv[q] = x;
         } else {
             wv[q] = -INFINITY;
@@ -605,8 +621,8 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     for (int q = 0; q < KPL; ++q) {
         const int l = l16 + 16 * q;
         if (l < k) {
-            float nw = wv[q] - d.eta * (ev[q] * rz * (gv[q] - rq));
-            if (smooth) nw = nw / d.rho;
+            float nw = wv[q] - eta * (ev[q] * rz * (gv[q] - rq));
+            if (smooth) nw = nw / rho;
             w[l] = nw;
             if (!finite_f(nw)) bad = 1;
             if (nw > best) { best = nw; bi = l; }
@@ -623,7 +639,7 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
             bi = 0;
             atomicExch(&st->next_bad, 1);
         }
-        d.c[st->pS][(size_t)m * d.cs + i] = (int16_t)bi;
+        cnext[i] = (int16_t)bi;
     }
 }
 
