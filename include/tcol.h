@@ -3,7 +3,7 @@
  *
  * The method (Goudet, Duval, Hao: "Population-based Gradient Descent Weight
  * Learning for Graph Coloring Problems") keeps D weight tensors W_d (n x k)
- * per graph.  One iteration (Section 2, Algorithm 1, steps 1-4):
+ * per graph.  One iteration (Section 3, Algorithm 1, steps 1-4):
  *   1. S = one_hot(argmax(W)) along the colour axis;
  *   2. fitness f_color(S_d) = 1/2 sum(A o S_d S_d^T)   (eq. individual fitness),
  *      plus the equity fitness f_eq for the ECP           (eq. equity fitness);
@@ -14,7 +14,7 @@
  *   4. straight-through softmax gradient gW = S^ o (gS - (S^ o gS).J)
  *      (eq. tensor gradient), W <- W - eta gW, and W <- W / rho every nb_iter
  *      iterations (eq. smoothing).
- * The loop stops when some member is legal (f = 0, Section 2 general scheme).
+ * The loop stops when some member is legal (f = 0, Section 3.3, general scheme).
  *
  * Conventions fixed by this library where the paper leaves a choice:
  *  - argmax ties go to the lowest colour;
@@ -60,7 +60,7 @@ enum {
     TCOL_ESTATE = -7       /* call not valid in the current state */
 };
 
-/* Problem statement (Section 2): k-COL is one step of the GCP (fitness =
+/* Problem statement (Sections 3.1-3.2): k-COL is one step of the GCP (fitness =
  * conflicts); the ECP adds the equity fitness to the fitness and the loss. */
 enum { TCOL_KCOL = 0, TCOL_ECP = 1 };
 
@@ -102,11 +102,13 @@ typedef struct {
     int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */
     int32_t tile_ntw;       /* GEMM 16-column subtiles per wave; the instantiated (tile_bm, tile_ntw)
                                pairs are (64,2) (64,4) (128,4) (128,8) (64,9) (128,9) (256,4) */
-    int32_t penalty;        /* fused path, penalty term (A o Mt^(alpha-1) and (J-A) o Mt^(beta-1)
-                               times S): 0 = choose per graph (default), 1 = dense operand pass on
-                               MFMA, 2 = sparse pair lists in FP32 whenever they fit (the penalty
-                               operand is non-zero only where two vertices share a colour in some
-                               member, so it is sparse when D is small against k) */
+    int32_t penalty;        /* fast and epilogue paths, penalty term (A o Mt^(alpha-1) and
+                               (J-A) o Mt^(beta-1) times S, eq. 17): 0 = choose (default),
+                               1 = dense operand pass on MFMA, 2 = sparse: per-row lists of the
+                               non-zero entries of the operand and FP32 histograms over the
+                               members' colours (the operand is non-zero only where two vertices
+                               share a colour in some member, so it is sparse when D is small
+                               against k) */
 } tcol_options;
 
 typedef struct tcol_ctx tcol_ctx;

@@ -1,7 +1,7 @@
 """Literal numpy float64 transcription of the paper's tensor formulas -- TEST INFRASTRUCTURE.
 
 For tiny inputs only: it materialises the D x n x n association and conflict
-tensors exactly as the paper writes them (Section 2, steps 1-4), with library
+tensors exactly as the paper writes them (Section 3, steps 1-4), with library
 matrix products as its only building blocks.  It is used to pin the C oracle,
 which computes the same quantities by one-hot gathers.
 """

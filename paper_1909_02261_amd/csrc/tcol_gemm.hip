@@ -152,9 +152,14 @@ constexpr int kStages = 3;   // LDS stage buffers
 
 // Workgroup barrier without the memory fence of __syncthreads(): that fence would
 // make every wave drain all its loads, including the prefetches of later stages.
-// Visibility of the LDS stages is ordered explicitly by wait_vm before it.
+// Visibility of the LDS stages is ordered explicitly by wait_vm before it.  The
+// barrier itself waits for this wave's LDS reads (lgkmcnt 0): the compiler may
+// issue the fragment reads of a stage before the barrier and consume them after
+// it, and once every wave has passed, the next stage's direct-to-LDS loads may
+// overwrite that buffer.
 __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));   // lgkmcnt(0), others untouched
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }

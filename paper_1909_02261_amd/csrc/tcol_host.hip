@@ -38,7 +38,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_LST, B_LCNT, B_COUNT
 };
 
 struct Layout {
@@ -77,6 +77,8 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
     sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
+    sz[B_LST] = sizeof(uint32_t) * (size_t)p.n * L.n_pad;
+    sz[B_LCNT] = sizeof(int32_t) * (size_t)p.n;
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -126,9 +128,10 @@ struct tcol_ctx {
     GemmShape shape{};              // separate-path tiling (also used by tcol_conflicts / tcol_loss_grad)
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
-    int sparse_rpw = 0;             // sparse penalty kernel: rows per wave (0: no graph uses it)
-    int sparse_dk = 0;              // largest D*k of a graph on the sparse penalty
-    int total_rows = 0, total_mem = 0, total_vtx = 0, total_mt = 0, total_ex = 0;
+    int sp_R = 0, sp_DM = 0;        // sparse penalty tiles: rows x members (0: no graph uses it)
+    size_t sp_lds = 0;              // dynamic LDS of the sparse scatter kernel
+    int total_pl = 0, total_ps = 0; // blocks of the sparse list and scatter kernels
+    int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0;
     int total_gm[2] = {0, 0};
     int kmax = 0, nmax = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // [0] = unroll steps, [1] = one step
@@ -195,20 +198,33 @@ static long long tiles_for(const tcol_ctx* c, int bm, int ntw, int mode) {
     return t;
 }
 
-// tile shapes: options first, else a default that keeps the chip busy
+// Estimated time of one contraction launch with a tile shape: tiles run in
+// rounds of (CUs x resident blocks), and a tile costs its MFMA work (BM x BN per
+// K-stage) plus its operand staging (BM + BN rows per K-stage).  Small tiles fit
+// two blocks per CU (LDS and registers); the large ones one.
+static double shape_cost(const tcol_ctx* c, int bm, int ntw) {
+    const long long tiles = tiles_for(c, bm, ntw, 0);
+    const int bn = gemm_bn(ntw);
+    const int lds = 3 * (bm + bn) * 128;
+    const int per_cu = (bm * bn <= 64 * 128 && 2 * lds <= kMaxLdsBytes) ? 2 : 1;
+    const long long rounds = (tiles + 256LL * per_cu - 1) / (256LL * per_cu);
+    return (double)rounds * ((double)bm * bn + 32.0 * (bm + bn));
+}
+
+// tile shapes: options first, else the listed shape of least estimated time
 static void pick_shapes(tcol_ctx* c) {
     const int prec = std::max(0, common_precision(c));
-    long long cols = 0;
-    for (auto& p : c->params) cols = std::max<long long>(cols, (long long)p.D * p.k);
     GemmShape s{prec, 128, 8, 0};
-    if (cols <= 512) s.ntw = 4;
-    if (cols <= 128) s.ntw = 2;
-    if (c->nmax <= 256) {
-        s.bm = 64;
-        s.ntw = std::min(s.ntw, 4);
+    double best = -1.0;
+    for (auto& sh : kShapes) {
+        const double cost = shape_cost(c, sh[0], sh[1]);
+        // ties go to the larger tile (fewer operand re-reads)
+        if (best < 0.0 || cost < best || (cost == best && sh[0] * sh[1] > s.bm * s.ntw)) {
+            best = cost;
+            s.bm = sh[0];
+            s.ntw = sh[1];
+        }
     }
-    if (!shape_listed(s.bm, s.ntw)) s.bm = shape_listed(64, s.ntw) ? 64 : 128;
-    if (!shape_listed(s.bm, s.ntw)) s.ntw = 4;
     if (c->opt.tile_bm && c->opt.tile_ntw && shape_listed(c->opt.tile_bm, c->opt.tile_ntw)) {
         s.bm = c->opt.tile_bm;
         s.ntw = c->opt.tile_ntw;
@@ -239,11 +255,33 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     pick_shapes(c);
     HIPCHK(gemm_prepare(c->shape));
     if (c->fused_ok) HIPCHK(gemm_prepare(c->fshape));
-    HIPCHK(penalty_rows_prepare());
+    HIPCHK(penalty_sparse_prepare());
     const int BN0 = gemm_bn(c->shape.ntw);
     const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
-    int rows = 0, mem = 0, vtx = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
-    int sp_rpw = 2, sp_dk = 0;
+    // sparse penalty: a graph takes it on request; tiles of R rows x DM members with the
+    // DM x R x k histograms in LDS (DM a power of two <= 8, R a multiple of 4)
+    int sp_k = 0, sp_D = 0;
+    for (int g = 0; g < c->G; ++g) {
+        const tcol_graph_params& p = c->params[g];
+        c->hdesc[g].sparse = c->opt.penalty == 2 ? 1 : 0;
+        if (c->hdesc[g].sparse) {
+            sp_k = std::max(sp_k, p.k);
+            sp_D = std::max(sp_D, p.D);
+        }
+    }
+    c->sp_R = c->sp_DM = 0;
+    c->sp_lds = 0;
+    if (sp_k > 0) {
+        int DM = 8;
+        while (DM > 1 && DM / 2 >= sp_D) DM /= 2;
+        while (DM > 1 && 4LL * DM * sp_k * 4 > 150 * 1024) DM /= 2;
+        int R = (int)std::min<long long>(64, (64LL * 1024) / (4LL * DM * sp_k)) & ~3;
+        R = std::max(R, 4);
+        c->sp_R = R;
+        c->sp_DM = DM;
+        c->sp_lds = sizeof(float) * ((size_t)DM * R * sp_k + 2 * (size_t)(sp_D + 1));
+    }
+    int rows = 0, mem = 0, pl = 0, ps = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const Layout& L = c->layouts[g];
@@ -252,8 +290,12 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         rows += p.D * p.n;
         d.mem_begin = mem;
         mem += p.D;
-        d.vtx_begin = vtx;
-        vtx += p.n;
+        d.pl_begin = pl;
+        d.ps_begin = ps;
+        if (d.sparse) {
+            pl += ceil_div(p.n, kPlRows);
+            ps += ceil_div(p.n, c->sp_R) * ceil_div(p.D, c->sp_DM);
+        }
         d.mt_begin = mt;
         d.mt_T = L.mt_T;
         mt += L.mt_tiles;
@@ -272,26 +314,15 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
             d.gm_tn[1] = ceil_div(p.D, d.gm_mpb);
             gm1 += d.gm_tm[1] * d.gm_tn[1];
         }
-        // sparse penalty rows: one lane per member (D <= 64) and one D x k histogram per row in
-        // LDS; chosen by default when the operand is sparse (expected density D/k <= 1/4)
-        const int pen = c->opt.penalty;
-        const bool feasible = p.D <= 64 && (long long)p.D * p.k * 4 <= 160 * 1024;
-        d.sparse = feasible && (pen == 2 || (pen == 0 && 4LL * p.D <= p.k)) ? 1 : 0;
-        if (d.sparse) {
-            if (p.D > 32) sp_rpw = 1;
-            sp_dk = std::max(sp_dk, p.D * p.k);
-        }
     }
     c->total_rows = rows;
     c->total_mem = mem;
-    c->total_vtx = vtx;
+    c->total_pl = pl;
+    c->total_ps = ps;
     c->total_mt = mt;
     c->total_ex = ex;
     c->total_gm[0] = gm0;
     c->total_gm[1] = gm1;
-    c->sparse_rpw = sp_dk > 0 ? sp_rpw : 0;
-    if (c->sparse_rpw == 2 && 2LL * sp_dk * 4 > kMaxLdsBytes) c->sparse_rpw = 1;
-    c->sparse_dk = sp_dk;
     HIPCHK(hipMemcpyAsync(c->ddesc, c->hdesc.data(), sizeof(GraphDev) * c->G, hipMemcpyHostToDevice, c->stream));
     drop_graphs(c);
     return TCOL_OK;
@@ -328,8 +359,8 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 
 // penalty of the fast and epilogue paths: sparse rows or the dense operand, per graph
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
-    if (c->sparse_rpw)
-        HIPRET(launch_penalty_rows(c->ddesc, c->G, c->total_vtx, 1, c->sparse_dk, s));
+    if (c->total_ps > 0)
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_pl, c->total_ps, c->sp_R, c->sp_DM, c->sp_lds, 1, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
@@ -576,6 +607,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.st = c->dstate + g;
         d.cT = (int16_t*)(b + L.off[B_CT]);
         d.cTs = round_up(q.D, 8);
+        d.lst = (uint32_t*)(b + L.off[B_LST]);
+        d.lcnt = (int32_t*)(b + L.off[B_LCNT]);
         // look-up tables over the group concentration m = 0..D (host libm, FP64)
         std::vector<float> lp(q.D + 1), lb(q.D + 1);
         std::vector<double> lka(q.D + 1), lvb(q.D + 1);

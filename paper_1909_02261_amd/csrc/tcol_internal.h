@@ -68,11 +68,14 @@ struct GraphDev {
     GraphState* st;
     int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
     int cTs;                  // row stride of cT (D rounded up to 8)
-    int sparse;               // fused path: penalty rows by the sparse kernel (else dense operand pass)
+    int sparse;               // fused path: penalty rows by the sparse kernels (else dense operand pass)
+    uint32_t* lst;            // [n][n_pad] sparse penalty entries of row i (see k_pen_list)
+    int32_t* lcnt;            // [n] entries per row
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
-    int vtx_begin;            // vertices i for per-vertex kernels
+    int pl_begin;             // blocks of the penalty-list kernel (kPlRows rows each)
+    int ps_begin;             // blocks of the penalty-scatter kernel (row tile x member group)
     int mt_begin;             // tiles of the group-concentration kernel
     int mt_T;                 // 64-row tiles per side
     int ex_begin;             // blocks of the S^T expansion kernel
@@ -81,6 +84,9 @@ struct GraphDev {
     int gm_tm[2], gm_tn[2];   // tiles along rows and along columns
     int gm_mpb;               // fused tiling: members per column tile
 };
+
+// rows per block of the penalty-list kernel
+constexpr int kPlRows = 16;
 
 // run-time flags passed to the kernels of one launch sequence
 enum : int {

@@ -144,88 +144,174 @@ __device__ inline int equal_halves(uint32_t a, uint32_t b) {
     return __builtin_popcount(y & ~x & 0x80008000u);
 }
 
-// Penalty rows without the dense operand, for populations with few members
-// against many colours: the penalty operand
+// equal 16-bit halves of a and b among those whose top bit is set in `valid`
+// (0x8000 for the low half, 0x80000000 for the high half)
+__device__ inline int equal_halves_in(uint32_t a, uint32_t b, uint32_t valid) {
+    const uint32_t x = a ^ b;
+    u16x2 h = __builtin_bit_cast(u16x2, x);
+    const u16x2 one = {1, 1};
+    const uint32_t y = __builtin_bit_cast(uint32_t, (u16x2)(h - one));
+    return __builtin_popcount(y & ~x & valid);
+}
+
+// Sparse penalty, for populations with few members against many colours.  The
+// penalty operand
 //   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
-// m = Mt_ij, vanishes unless i and j share a colour in some member.  One wave
-// per row i works through j in chunks of 64:
-//   1. lane jj takes j = j0 + jj and counts m = #{d : c_d(j) = c_d(i)} from the
-//      vertex-major colours (two members per 32-bit compare), then P_ij;
-//   2. a ballot marks the j with P_ij != 0, and for each of them every lane d
-//      (one lane per member) adds P_ij to its histogram at colour c_d(j).
-// Each lane owns the histogram of its member, so the FP32 sums run in the order
-// j = 0..n-1 on every run.  The histograms, (P.S_d)[i, l], are written to
-// G[d][i][l], where the contraction kernel adds A.S_d.  D <= 64.
-__global__ __launch_bounds__(256) void k_penalty_rows(const GraphDev* __restrict__ gd, int G, int total_vtx,
-                                                      int honor_stop, int wpb, int hist_floats) {
-    extern __shared__ float hist_all[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (wave >= wpb) return;
-    const int v = blockIdx.x * wpb + wave;
-    if (v >= total_vtx) return;
-    const GraphDev& d = gd[find_graph(gd, G, v, [](const GraphDev& x) { return x.vtx_begin; })];
+// m = Mt_ij, vanishes unless i and j share a colour in some member, and with
+// one-hot S_d the product (P.S_d)[i, l] is the sum of P_ij over the j with
+// c_d(j) = l.  Two kernels compute it without the dense operand:
+//
+// k_pen_list: row i's non-zero entries in increasing j, packed as
+// j | m << 15 | a_ij << 26, and their count.  A block takes kPlRows rows (four
+// per wave); lane jj of a wave takes j = j0 + jj, counts m for its four rows
+// from the vertex-major colours (two members per 32-bit compare), and a ballot
+// places the non-zero entries.
+__global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                  int honor_stop) {
+    __shared__ __attribute__((aligned(16))) uint32_t ci[kPlRows][kMaxD / 2];
+    __shared__ float lpen[kMaxD + 1], lbon[kMaxD + 1];
+    const int b = blockIdx.x;
+    if (b >= total_blocks) return;
+    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.pl_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     if (!d.sparse || !pen_active(d, st)) return;
-    const int D = d.D, k = d.k, n = d.n;
-    const int i = v - d.vtx_begin;
-    const bool act = lane < D;                  // member lane
-    float* h = hist_all + (size_t)wave * hist_floats;
-    if (act)
-        for (int l = 0; l < k; ++l) h[(size_t)lane * k + l] = 0.0f;
-    const int16_t* crow = d.c[st->pS] + (size_t)lane * d.cs;   // member lane's colours
-    const float tf = (float)st->t;
-    // look-up tables: lane q holds the entries of m = q + 1; a lane reads entry m from lane m - 1
-    const float lutp = act ? d.lut_pen[lane + 1] : 0.0f;
-    const float lutb = act ? d.lut_bon[lane + 1] : 0.0f;
-    const bool diag = d.bonus_diag != 0;
-    const uint8_t* arow = d.A8 + (size_t)i * d.n_pad;
-    // colours of vertex i, two members per word (D even or the last half is padding)
-    const uint32_t* ciw = (const uint32_t*)(d.cT + (size_t)i * d.cTs);
-    const int nw = D >> 1;
-    const bool odd = D & 1;
+    const int n = d.n, D = d.D;
+    const size_t cTs = d.cTs, n_pad = d.n_pad;
     const int16_t* __restrict__ cT = d.cT;
-    const size_t cTs = d.cTs;
+    const uint8_t* __restrict__ A8 = d.A8;
+    uint32_t* __restrict__ lst = d.lst;
+    int32_t* __restrict__ lcnt = d.lcnt;
+    const bool diag = d.bonus_diag != 0;
+    const int i0 = (b - d.pl_begin) * kPlRows;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nw = (D + 1) >> 1;       // 32-bit words holding the members of a vertex
+    const int ngrp = (D + 7) >> 3;     // 16-byte groups of eight members (cT rows are padded to 8)
+    const float tf = (float)st->t;
+    for (int e = tid; e < kPlRows * nw; e += 256) {
+        const int r = e / nw, q = e - r * nw;
+        const int i = i0 + r;
+        ci[r][q] = i < n ? *(const uint32_t*)(cT + (size_t)i * cTs + 2 * q) : 0u;
+    }
+    for (int m = tid; m <= D; m += 256) {
+        lpen[m] = tf * d.lut_pen[m];
+        lbon[m] = -(tf * d.lut_bon[m]);
+    }
+    __syncthreads();
+    int cnt[4] = {0, 0, 0, 0};
     for (int j0 = 0; j0 < n; j0 += 64) {
-        // member lanes: colours c_lane(j0 .. j0+63), eight 16-byte loads
-        uint4 w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = act ? *(const uint4*)(crow + j0 + 8 * q) : make_uint4(0, 0, 0, 0);
-        // vertex lanes: m and P for j = j0 + lane
         const int j = j0 + lane;
-        float P = 0.0f;
-        int m = 0;
-        if (j < n) {
-            const int16_t* cj = cT + (size_t)j * cTs;
-            for (int q = 0; q < nw; ++q) m += equal_halves(ciw[q], *(const uint32_t*)(cj + 2 * q));
-            if (odd) m += (cj[D - 1] == cT[(size_t)i * cTs + D - 1]) ? 1 : 0;
-        }
-        const float lp = __shfl(lutp, m > 0 ? m - 1 : 0, 64);
-        const float lb = __shfl(lutb, m > 0 ? m - 1 : 0, 64);
-        if (m > 0) {
-            if (arow[j]) P = tf * lp;
-            else if (i != j || diag) P = -(tf * lb);
-        }
-        const unsigned long long hits = __ballot(P != 0.0f);
-        if (hits == 0) continue;
+        const bool valid = j < n;
+        const int16_t* cj = cT + (size_t)(valid ? j : 0) * cTs;
+        int m[4] = {0, 0, 0, 0};
+        for (int g8 = 0; g8 < ngrp; ++g8) {
+            const uint4 w = *(const uint4*)(cj + 8 * g8);
+            const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int jj = 0; jj < 64; ++jj) {
-            if (!((hits >> jj) & 1ull)) continue;     // uniform over the wave
-            const float pv = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, P), jj));
-            const uint4 x = w[jj >> 3];
-            const int e = (jj >> 1) & 3;
-            const uint32_t word = e == 0 ? x.x : (e == 1 ? x.y : (e == 2 ? x.z : x.w));
-            const int cjm = (int)((word >> (16 * (jj & 1))) & 0xFFFFu);
-            if (act) atomicAdd(&h[(size_t)lane * k + cjm], pv);
+            for (int r = 0; r < 4; ++r) {
+                const uint4 c4 = *(const uint4*)&ci[wave * 4 + r][4 * g8];
+                const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int q = 4 * g8 + h;
+                    const uint32_t vm = (2 * q < D ? 0x8000u : 0u) | (2 * q + 1 < D ? 0x80000000u : 0u);
+                    m[r] += equal_halves_in(cv[h], wv[h], vm);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + wave * 4 + r;
+            if (i >= n) break;                       // uniform over the wave
+            const bool edge = valid && A8[(size_t)i * n_pad + j] != 0;
+            const int mm = m[r];
+            float P = 0.0f;
+            if (valid && mm > 0) P = edge ? lpen[mm] : ((i != j || diag) ? lbon[mm] : 0.0f);
+            const bool hit = P != 0.0f;
+            const unsigned long long bal = __ballot(hit);
+            if (hit) {
+                const int pos = cnt[r] + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                lst[(size_t)i * n_pad + pos] = (uint32_t)j | ((uint32_t)mm << 15) | (edge ? (1u << 26) : 0u);
+            }
+            cnt[r] += __builtin_popcountll(bal);
         }
     }
-    // the write-out reads other lanes' histograms: wait for this wave's LDS writes
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    float* G1 = d.G;
-    for (int e = lane; e < D * k; e += 64) {
-        const int mm = e / k, l = e - mm * k;
-        G1[((size_t)mm * n + i) * k + l] = h[e];
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (i0 + wave * 4 + r < n) lcnt[i0 + wave * 4 + r] = cnt[r];
+    }
+}
+
+// k_pen_scatter: histograms (P.S_d)[i, :] of a tile of R rows for DM members
+// (DM in {1, 2, 4, 8}, so the members of a tile sit in one 16-byte group of a cT
+// row) in LDS, written to G[d][i][:], where the contraction adds A.S_d.  Each row
+// belongs to one wave, which walks its entries in list order, so the FP32 sums
+// run in the same order on every run.  Dynamic LDS: DM*R*k + 2(D+1) floats.
+__global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                     int honor_stop, int R, int DM) {
+    extern __shared__ float sh[];
+    const int b = blockIdx.x;
+    if (b >= total_blocks) return;
+    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    if (!d.sparse || !pen_active(d, st)) return;
+    const int n = d.n, k = d.k, D = d.D;
+    const size_t cTs = d.cTs, n_pad = d.n_pad;
+    const int16_t* __restrict__ cT = d.cT;
+    const uint32_t* __restrict__ lst = d.lst;
+    const int32_t* __restrict__ lcnt = d.lcnt;
+    float* __restrict__ Gg = d.G;
+    const int ndg = ceil_div(D, DM);
+    const int local = b - d.ps_begin;
+    const int rt = local / ndg, dg = local - rt * ndg;
+    const int i0 = rt * R, d0 = dg * DM;
+    const int nmem = min(DM, D - d0);
+    const int rows = min(R, n - i0);
+    const int sub = d0 & 7;                  // first member's slot in its 16-byte group
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int slab = R * k;                  // floats per member
+    float* hist = sh;
+    float* lpen = sh + DM * slab;
+    float* lbon = lpen + (D + 1);
+    const float tf = (float)st->t;
+    for (int e = tid; e < DM * slab; e += 256) hist[e] = 0.0f;
+    for (int m = tid; m <= D; m += 256) {
+        lpen[m] = tf * d.lut_pen[m];
+        lbon[m] = -(tf * d.lut_bon[m]);
+    }
+    __syncthreads();
+    for (int ri = wave; ri < rows; ri += 4) {
+        const int i = i0 + ri;
+        const int cnt = lcnt[i];
+        const uint32_t* row = lst + (size_t)i * n_pad;
+        float* h = hist + ri * k;
+        for (int e0 = 0; e0 < cnt; e0 += 64) {
+            const int e = e0 + lane;
+            if (e < cnt) {
+                const uint32_t v = row[e];
+                const int j = (int)(v & 0x7FFFu), m = (int)((v >> 15) & 0x7FFu);
+                const float P = (v >> 26) & 1u ? lpen[m] : lbon[m];
+                const uint4 cc = *(const uint4*)(cT + (size_t)j * cTs + (d0 - sub));
+                const uint32_t cw[4] = {cc.x, cc.y, cc.z, cc.w};
+#pragma unroll
+                for (int dm = 0; dm < 8; ++dm) {
+                    if (dm < nmem) {
+                        const int s = sub + dm;
+                        const int col = (int)((cw[s >> 1] >> (16 * (s & 1))) & 0xFFFFu);
+                        atomicAdd(&h[dm * slab + col], P);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // member dm's rows i0 .. i0+rows-1 are contiguous in G
+    for (int dm = 0; dm < nmem; ++dm) {
+        float* out = Gg + ((size_t)(d0 + dm) * n + i0) * k;
+        const float* src = hist + dm * slab;
+        for (int e = tid; e < rows * k; e += 256) out[e] = src[e];
     }
 }
 
@@ -752,20 +838,19 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int h
     return hipSuccess;
 }
 
-hipError_t penalty_rows_prepare() {
-    return hipFuncSetAttribute((const void*)k_penalty_rows, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+hipError_t penalty_sparse_prepare() {
+    return hipFuncSetAttribute((const void*)k_pen_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-hipError_t launch_penalty_rows(const GraphDev* gd, int G, int total_vtx, int honor_stop, int dk_max, hipStream_t s) {
-    if (total_vtx <= 0 || dk_max <= 0) return hipSuccess;
-    const size_t per_row = sizeof(float) * (size_t)dk_max;
-    int wpb = (int)((160 * 1024) / per_row);
-    wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
-    const int blocks = ceil_div(total_vtx, wpb);
-    hipLaunchKernelGGL(k_penalty_rows, dim3(blocks), dim3(256), per_row * wpb, s, gd, G, total_vtx, honor_stop, wpb,
-                       dk_max);
-    TCOL_LAUNCH_CHECK();
-    return hipSuccess;
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int list_blocks, int scatter_blocks, int R, int DM,
+                                 size_t lds, int honor_stop, hipStream_t s) {
+    if (list_blocks <= 0 || scatter_blocks <= 0) return hipSuccess;
+    if (R < 1 || (DM != 1 && DM != 2 && DM != 4 && DM != 8) || lds > 160 * 1024) return hipErrorInvalidValue;
+    k_pen_list<<<list_blocks, 256, 0, s>>>(gd, G, list_blocks, honor_stop);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pen_scatter<<<scatter_blocks, 256, lds, s>>>(gd, G, scatter_blocks, honor_stop, R, DM);
+    return hipGetLastError();
 }
 
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
