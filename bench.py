@@ -27,6 +27,8 @@ import numpy as np
 import tcolgen
 
 PEAK = {"fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
+GEMM_SRC = os.path.join(ROOT, "paper_1909_02261_amd", "csrc", "tcol_gemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_fp8_hbm_traffic.txt")
 HBM_PEAK = 8.0e12
 PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8}
 
@@ -63,6 +65,27 @@ def mixed_peak(prec: str, f_as: float, f_pen: float) -> float:
     return (f_as + f_pen) / ideal
 
 
+def measured_traffic(config: dict):
+    """HBM bytes per contraction launch from the committed counter summary, when it was taken
+    on this workload and tiling with the current kernel source; else None."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip()
+        sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+        if fields.get("source_sha256") != sha:
+            return None
+        for key in ("workload", "tile_bm", "tile_ntw", "penalty", "path"):
+            if fields.get(key) != str(config[key]):
+                return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(case, A, W0, budget_s: float):
     import oracle
     p = oracle.Params.from_dict(case.params())
@@ -85,8 +108,8 @@ def cpu_baseline(case, A, W0, budget_s: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
@@ -171,6 +194,11 @@ def main():
         print(f"[bench] oracle baseline ({args.cpu_seconds:.0f} s budget)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(case, A, W0, args.cpu_seconds)
 
+    config = {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
+              "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
+              "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
+              "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]}
+    roof["traffic"] = measured_traffic(config)
     out = {
         "metric": "population-iterations/s (D*steps/s)",
         "value": value,
@@ -184,10 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": prec,
         "data": "synthetic (seeded Philox G(n,p) graph and N(0, 0.01^2) weights)",
-        "config": {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
-                   "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
-                   "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
-                   "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]},
+        "config": config,
         "roofline": roof,
         "roofline_as_only": roof_as,
         "phases_ms": ph,

@@ -78,7 +78,7 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     sz[B_LST] = sizeof(uint32_t) * (size_t)p.n * L.n_pad;
-    sz[B_LCNT] = sizeof(int32_t) * (size_t)p.n;
+    sz[B_LCNT] = sizeof(int32_t) * (size_t)p.n * (L.n_pad / kPlSeg);
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -129,7 +129,7 @@ struct tcol_ctx {
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
     int sp_R = 0, sp_DM = 0;        // sparse penalty tiles: rows x members (0: no graph uses it)
-    size_t sp_lds = 0;              // dynamic LDS of the sparse scatter kernel
+    size_t sp_lds = 0, pl_lds = 0;  // dynamic LDS of the sparse scatter and list kernels
     int total_pl = 0, total_ps = 0; // blocks of the sparse list and scatter kernels
     int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0;
     int total_gm[2] = {0, 0};
@@ -260,17 +260,18 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
     // sparse penalty: a graph takes it on request; tiles of R rows x DM members with the
     // DM x R x k histograms in LDS (DM a power of two <= 8, R a multiple of 4)
-    int sp_k = 0, sp_D = 0;
+    int sp_k = 0, sp_D = 0, sp_n = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         c->hdesc[g].sparse = c->opt.penalty == 2 ? 1 : 0;
         if (c->hdesc[g].sparse) {
             sp_k = std::max(sp_k, p.k);
             sp_D = std::max(sp_D, p.D);
+            sp_n = std::max(sp_n, p.n);
         }
     }
     c->sp_R = c->sp_DM = 0;
-    c->sp_lds = 0;
+    c->sp_lds = c->pl_lds = 0;
     if (sp_k > 0) {
         int DM = 8;
         while (DM > 1 && DM / 2 >= sp_D) DM /= 2;
@@ -279,7 +280,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         R = std::max(R, 4);
         c->sp_R = R;
         c->sp_DM = DM;
-        c->sp_lds = sizeof(float) * ((size_t)DM * R * sp_k + 2 * (size_t)(sp_D + 1));
+        c->sp_lds = penalty_scatter_lds(R, DM, sp_k, sp_D, sp_n);
+        c->pl_lds = penalty_list_lds(sp_D);
     }
     int rows = 0, mem = 0, pl = 0, ps = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
     for (int g = 0; g < c->G; ++g) {
@@ -293,7 +295,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         d.pl_begin = pl;
         d.ps_begin = ps;
         if (d.sparse) {
-            pl += ceil_div(p.n, kPlRows);
+            pl += ceil_div(p.n, kPlRows) * (L.n_pad / kPlSeg);
             ps += ceil_div(p.n, c->sp_R) * ceil_div(p.D, c->sp_DM);
         }
         d.mt_begin = mt;
@@ -360,7 +362,8 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 // penalty of the fast and epilogue paths: sparse rows or the dense operand, per graph
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
     if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_pl, c->total_ps, c->sp_R, c->sp_DM, c->sp_lds, 1, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_pl, c->total_ps, c->sp_R, c->sp_DM, c->pl_lds,
+                                     c->sp_lds, 1, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }

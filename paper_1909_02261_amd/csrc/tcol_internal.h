@@ -69,8 +69,8 @@ struct GraphDev {
     int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
     int cTs;                  // row stride of cT (D rounded up to 8)
     int sparse;               // fused path: penalty rows by the sparse kernels (else dense operand pass)
-    uint32_t* lst;            // [n][n_pad] sparse penalty entries of row i (see k_pen_list)
-    int32_t* lcnt;            // [n] entries per row
+    uint32_t* lst;            // [n][n_pad] sparse penalty entries of row i, by segment (see k_pen_list)
+    int32_t* lcnt;            // [n][n_pad / kPlSeg] entries per row and segment
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
@@ -85,8 +85,10 @@ struct GraphDev {
     int gm_mpb;               // fused tiling: members per column tile
 };
 
-// rows per block of the penalty-list kernel
+// rows per block of the penalty-list kernel, and columns per list segment
+// (a divisor of kPadN, so a padded row holds a whole number of segments)
 constexpr int kPlRows = 16;
+constexpr int kPlSeg = 256;
 
 // run-time flags passed to the kernels of one launch sequence
 enum : int {

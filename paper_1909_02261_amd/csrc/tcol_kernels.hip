@@ -154,22 +154,39 @@ __device__ inline int equal_halves_in(uint32_t a, uint32_t b, uint32_t valid) {
     return __builtin_popcount(y & ~x & valid);
 }
 
+// global-address-space views: loads through them are not ordered against LDS
+// operations (a flat pointer may alias LDS, which pins every flat load behind
+// the LDS atomics and barriers before it)
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gview(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+typedef unsigned int u32x4n __attribute__((ext_vector_type(4)));
+// order this wave's LDS accesses across lanes (LDS executes a wave's operations in issue order)
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// 16-byte global load (p 16-byte aligned)
+__device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((address_space(1))) u32x4n*)p; }
+
 // Sparse penalty, for populations with few members against many colours.  The
 // penalty operand
 //   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
 // m = Mt_ij, vanishes unless i and j share a colour in some member, and with
 // one-hot S_d the product (P.S_d)[i, l] is the sum of P_ij over the j with
-// c_d(j) = l.  Two kernels compute it without the dense operand:
+// c_d(j) = l.  Two kernels compute it without the dense operand.
 //
-// k_pen_list: row i's non-zero entries in increasing j, packed as
-// j | m << 15 | a_ij << 26, and their count.  A block takes kPlRows rows (four
-// per wave); lane jj of a wave takes j = j0 + jj, counts m for its four rows
-// from the vertex-major colours (two members per 32-bit compare), and a ballot
-// places the non-zero entries.
+// k_pen_list: the non-zero entries of row i, packed as j | m << 15 | a_ij << 26,
+// per segment of kPlSeg columns: segment s of row i lists its entries in
+// increasing j at lst[i][s * kPlSeg ...] and counts them in lcnt[i][s].  A block
+// takes kPlRows rows (four per wave) and one segment; lane jj of a wave takes
+// j = j0 + jj, counts m for its four rows from the vertex-major colours (two
+// members per 32-bit compare, eight members per 16-byte load), and a ballot
+// places the entries.  Dynamic LDS: the rows' colours, then the two tables.
 __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                   int honor_stop) {
-    __shared__ __attribute__((aligned(16))) uint32_t ci[kPlRows][kMaxD / 2];
-    __shared__ float lpen[kMaxD + 1], lbon[kMaxD + 1];
+    extern __shared__ __attribute__((aligned(16))) uint32_t pl_sh[];
     const int b = blockIdx.x;
     if (b >= total_blocks) return;
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.pl_begin; })];
@@ -183,47 +200,70 @@ __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ g
     uint32_t* __restrict__ lst = d.lst;
     int32_t* __restrict__ lcnt = d.lcnt;
     const bool diag = d.bonus_diag != 0;
-    const int i0 = (b - d.pl_begin) * kPlRows;
+    const int nseg = (int)(n_pad / kPlSeg);
+    const int local = b - d.pl_begin;
+    const int rt = local / nseg, sg = local - rt * nseg;
+    const int i0 = rt * kPlRows, js = sg * kPlSeg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nw = (D + 1) >> 1;       // 32-bit words holding the members of a vertex
     const int ngrp = (D + 7) >> 3;     // 16-byte groups of eight members (cT rows are padded to 8)
+    const int rw = 4 * ngrp;           // words per staged row
+    uint32_t* ci = pl_sh;              // [kPlRows][rw]
+    float* lpen = (float*)(pl_sh + kPlRows * rw);
+    float* lbon = lpen + (D + 1);
     const float tf = (float)st->t;
-    for (int e = tid; e < kPlRows * nw; e += 256) {
-        const int r = e / nw, q = e - r * nw;
+    for (int e = tid; e < kPlRows * rw; e += 256) {
+        const int r = e / rw, q = e - r * rw;
         const int i = i0 + r;
-        ci[r][q] = i < n ? *(const uint32_t*)(cT + (size_t)i * cTs + 2 * q) : 0u;
+        ci[e] = i < n ? gview((const uint32_t*)(cT + (size_t)i * cTs))[q] : 0u;
     }
     for (int m = tid; m <= D; m += 256) {
         lpen[m] = tf * d.lut_pen[m];
         lbon[m] = -(tf * d.lut_bon[m]);
     }
     __syncthreads();
+    const int rbase = i0 + wave * 4;
+    const uint32_t* cw0 = ci + (wave * 4) * rw;
     int cnt[4] = {0, 0, 0, 0};
-    for (int j0 = 0; j0 < n; j0 += 64) {
-        const int j = j0 + lane;
+#pragma unroll 1
+    for (int c = 0; c < kPlSeg / 64; ++c) {
+        const int j = js + c * 64 + lane;
+        if (js + c * 64 >= n) break;                 // uniform
         const bool valid = j < n;
+        // the four rows' adjacency bytes, independent of the counts
+        uint8_t ab[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            ab[r] = (valid && rbase + r < n) ? gview(A8)[(size_t)(rbase + r) * n_pad + j] : (uint8_t)0;
         const int16_t* cj = cT + (size_t)(valid ? j : 0) * cTs;
         int m[4] = {0, 0, 0, 0};
-        for (int g8 = 0; g8 < ngrp; ++g8) {
-            const uint4 w = *(const uint4*)(cj + 8 * g8);
-            const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll 1
+        for (int g0 = 0; g0 < ngrp; g0 += 8) {
+            u32x4n w[8];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint4 c4 = *(const uint4*)&ci[wave * 4 + r][4 * g8];
-                const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+            for (int u = 0; u < 8; ++u) w[u] = g0 + u < ngrp ? gload16(cj + 8 * (g0 + u)) : u32x4n{0u, 0u, 0u, 0u};
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const int q = 4 * g8 + h;
-                    const uint32_t vm = (2 * q < D ? 0x8000u : 0u) | (2 * q + 1 < D ? 0x80000000u : 0u);
-                    m[r] += equal_halves_in(cv[h], wv[h], vm);
+            for (int u = 0; u < 8; ++u) {
+                const int g = g0 + u;
+                if (g >= ngrp) break;                // uniform
+                const uint32_t wv[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint4 c4 = *(const uint4*)(cw0 + r * rw + 4 * g);
+                    const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int q = 4 * g + h;
+                        const uint32_t vm = (2 * q < D ? 0x8000u : 0u) | (2 * q + 1 < D ? 0x80000000u : 0u);
+                        m[r] += equal_halves_in(cv[h], wv[h], vm);
+                    }
                 }
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = i0 + wave * 4 + r;
-            if (i >= n) break;                       // uniform over the wave
-            const bool edge = valid && A8[(size_t)i * n_pad + j] != 0;
+            const int i = rbase + r;
+            if (i >= n) break;                       // uniform
+            const bool edge = ab[r] != 0;
             const int mm = m[r];
             float P = 0.0f;
             if (valid && mm > 0) P = edge ? lpen[mm] : ((i != j || diag) ? lbon[mm] : 0.0f);
@@ -231,7 +271,7 @@ __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ g
             const unsigned long long bal = __ballot(hit);
             if (hit) {
                 const int pos = cnt[r] + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-                lst[(size_t)i * n_pad + pos] = (uint32_t)j | ((uint32_t)mm << 15) | (edge ? (1u << 26) : 0u);
+                lst[(size_t)i * n_pad + js + pos] = (uint32_t)j | ((uint32_t)mm << 15) | (edge ? (1u << 26) : 0u);
             }
             cnt[r] += __builtin_popcountll(bal);
         }
@@ -239,15 +279,17 @@ __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ g
     if (lane == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (i0 + wave * 4 + r < n) lcnt[i0 + wave * 4 + r] = cnt[r];
+            if (rbase + r < n) lcnt[(size_t)(rbase + r) * nseg + sg] = cnt[r];
     }
 }
 
 // k_pen_scatter: histograms (P.S_d)[i, :] of a tile of R rows for DM members
 // (DM in {1, 2, 4, 8}, so the members of a tile sit in one 16-byte group of a cT
 // row) in LDS, written to G[d][i][:], where the contraction adds A.S_d.  Each row
-// belongs to one wave, which walks its entries in list order, so the FP32 sums
-// run in the same order on every run.  Dynamic LDS: DM*R*k + 2(D+1) floats.
+// belongs to one wave, which walks its entries segment by segment in increasing
+// j, 64 at a time (a lane finds its segment from the running counts), so the FP32
+// sums run in the same order on every run.  Dynamic LDS: DM*R*k floats of
+// histograms, 2(D+1) floats of tables, 4 (n_pad/kPlSeg + 1) ints of counts.
 __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                      int honor_stop, int R, int DM) {
     extern __shared__ float sh[];
@@ -259,6 +301,7 @@ __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict_
     if (!d.sparse || !pen_active(d, st)) return;
     const int n = d.n, k = d.k, D = d.D;
     const size_t cTs = d.cTs, n_pad = d.n_pad;
+    const int nseg = (int)(n_pad / kPlSeg);
     const int16_t* __restrict__ cT = d.cT;
     const uint32_t* __restrict__ lst = d.lst;
     const int32_t* __restrict__ lcnt = d.lcnt;
@@ -275,6 +318,7 @@ __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict_
     float* hist = sh;
     float* lpen = sh + DM * slab;
     float* lbon = lpen + (D + 1);
+    int* pref = (int*)(lbon + (D + 1)) + wave * (nseg + 1);   // this wave's running counts
     const float tf = (float)st->t;
     for (int e = tid; e < DM * slab; e += 256) hist[e] = 0.0f;
     for (int m = tid; m <= D; m += 256) {
@@ -284,16 +328,32 @@ __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict_
     __syncthreads();
     for (int ri = wave; ri < rows; ri += 4) {
         const int i = i0 + ri;
-        const int cnt = lcnt[i];
-        const uint32_t* row = lst + (size_t)i * n_pad;
+        // running counts of the row's segments (lane 0 sums; at most 128 segments)
+        for (int sgi = lane; sgi < nseg; sgi += 64) pref[sgi + 1] = gview(lcnt)[(size_t)i * nseg + sgi];
+        wave_sync();
+        if (lane == 0) {
+            int acc = 0;
+            pref[0] = 0;
+            for (int sgi = 0; sgi < nseg; ++sgi) {
+                acc += pref[sgi + 1];
+                pref[sgi + 1] = acc;
+            }
+        }
+        wave_sync();
+        const int total = pref[nseg];
+        const __attribute__((address_space(1))) uint32_t* row = gview(lst + (size_t)i * n_pad);
         float* h = hist + ri * k;
-        for (int e0 = 0; e0 < cnt; e0 += 64) {
+        int s0 = 0;                          // segment of entry e0 (uniform)
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            while (pref[s0 + 1] <= e0) ++s0;
             const int e = e0 + lane;
-            if (e < cnt) {
-                const uint32_t v = row[e];
+            if (e < total) {
+                int sgi = s0;
+                while (pref[sgi + 1] <= e) ++sgi;
+                const uint32_t v = row[sgi * kPlSeg + (e - pref[sgi])];
                 const int j = (int)(v & 0x7FFFu), m = (int)((v >> 15) & 0x7FFu);
                 const float P = (v >> 26) & 1u ? lpen[m] : lbon[m];
-                const uint4 cc = *(const uint4*)(cT + (size_t)j * cTs + (d0 - sub));
+                const u32x4n cc = gload16(cT + (size_t)j * cTs + (d0 - sub));
                 const uint32_t cw[4] = {cc.x, cc.y, cc.z, cc.w};
 #pragma unroll
                 for (int dm = 0; dm < 8; ++dm) {
@@ -305,6 +365,7 @@ __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict_
                 }
             }
         }
+        wave_sync();     // pref is reused by the wave's next row
     }
     __syncthreads();
     // member dm's rows i0 .. i0+rows-1 are contiguous in G
@@ -839,17 +900,30 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int h
 }
 
 hipError_t penalty_sparse_prepare() {
+    const hipError_t e =
+        hipFuncSetAttribute((const void*)k_pen_list, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_pen_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
+size_t penalty_list_lds(int dmax) {
+    return sizeof(uint32_t) * (size_t)kPlRows * 4 * ((dmax + 7) / 8) + sizeof(float) * 2 * (size_t)(dmax + 1);
+}
+
+size_t penalty_scatter_lds(int R, int DM, int kmax, int dmax, int nmax) {
+    const int nseg = round_up(nmax, kPadN) / kPlSeg;
+    return sizeof(float) * ((size_t)DM * R * kmax + 2 * (size_t)(dmax + 1)) + sizeof(int) * 4 * (size_t)(nseg + 1);
+}
+
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int list_blocks, int scatter_blocks, int R, int DM,
-                                 size_t lds, int honor_stop, hipStream_t s) {
+                                 size_t list_lds, size_t scatter_lds, int honor_stop, hipStream_t s) {
     if (list_blocks <= 0 || scatter_blocks <= 0) return hipSuccess;
-    if (R < 1 || (DM != 1 && DM != 2 && DM != 4 && DM != 8) || lds > 160 * 1024) return hipErrorInvalidValue;
-    k_pen_list<<<list_blocks, 256, 0, s>>>(gd, G, list_blocks, honor_stop);
+    if (R < 1 || (DM != 1 && DM != 2 && DM != 4 && DM != 8) || list_lds > 160 * 1024 || scatter_lds > 160 * 1024)
+        return hipErrorInvalidValue;
+    k_pen_list<<<list_blocks, 256, list_lds, s>>>(gd, G, list_blocks, honor_stop);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_pen_scatter<<<scatter_blocks, 256, lds, s>>>(gd, G, scatter_blocks, honor_stop, R, DM);
+    k_pen_scatter<<<scatter_blocks, 256, scatter_lds, s>>>(gd, G, scatter_blocks, honor_stop, R, DM);
     return hipGetLastError();
 }
 

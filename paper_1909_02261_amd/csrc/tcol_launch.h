@@ -10,10 +10,12 @@ hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8
 hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s);
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next, hipStream_t s);
 hipError_t penalty_sparse_prepare();
-// sparse penalty: per-row entry lists, then histograms of row tiles of R rows x DM members
-// (DM in {1, 2, 4, 8}); lds = dynamic LDS of the scatter kernel
+// sparse penalty: per-row, per-segment entry lists, then histograms of row tiles of R rows x DM
+// members (DM in {1, 2, 4, 8}); dynamic LDS of the two kernels from the helpers below
+size_t penalty_list_lds(int dmax);
+size_t penalty_scatter_lds(int R, int DM, int kmax, int dmax, int nmax);
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int list_blocks, int scatter_blocks, int R, int DM,
-                                 size_t lds, int honor_stop, hipStream_t s);
+                                 size_t list_lds, size_t scatter_lds, int honor_stop, hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
