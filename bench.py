@@ -26,11 +26,11 @@ import numpy as np
 
 import tcolgen
 
-PEAK = {"fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
+PEAK = {"fp4": 10.1e15, "fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
 GEMM_SRC = os.path.join(ROOT, "paper_1909_02261_amd", "csrc", "tcol_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_fp8_hbm_traffic.txt")
 HBM_PEAK = 8.0e12
-PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8}
+PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8, "fp4": tcolgen.FP4}
 
 
 def workload(name: str, prec: str):
@@ -58,9 +58,9 @@ def gemm_flops(case, t: int):
 
 def mixed_peak(prec: str, f_as: float, f_pen: float) -> float:
     """Peak of a launch whose A.S pass runs at the operand dtype and whose penalty pass runs
-    in bf16 (fp8 precision) or the operand dtype: total flops over the ideal time."""
+    in bf16 (fp8 and fp4 precision) or the operand dtype: total flops over the ideal time."""
     p_as = PEAK[prec]
-    p_pen = PEAK["bf16"] if prec == "fp8" else PEAK[prec]
+    p_pen = PEAK["bf16"] if prec in ("fp8", "fp4") else PEAK[prec]
     ideal = f_as / p_as + f_pen / p_pen
     return (f_as + f_pen) / ideal
 

@@ -66,17 +66,18 @@ enum { TCOL_KCOL = 0, TCOL_ECP = 1 };
 
 /* Operand precision of the contractions A.S and (penalty).S.  The 0/1
  * operands A and S are exact in every format and accumulate in FP32, so the
- * conflict counts are exact in all three; the penalty operand is rounded to
- * bf16 in TCOL_BF16 and TCOL_FP8 (TCOL_FP8 runs A.S in fp8 e4m3 and the
- * penalty product in bf16).  Softmax, gradient and update are FP32. */
-enum { TCOL_FP32 = 0, TCOL_BF16 = 1, TCOL_FP8 = 2 };
+ * conflict counts are exact in all four; the penalty operand is rounded to
+ * bf16 in TCOL_BF16, TCOL_FP8 and TCOL_FP4 (TCOL_FP8 runs A.S in fp8 e4m3,
+ * TCOL_FP4 in fp4 e2m1, both with the penalty product in bf16).  Softmax,
+ * gradient and update are FP32. */
+enum { TCOL_FP32 = 0, TCOL_BF16 = 1, TCOL_FP8 = 2, TCOL_FP4 = 3 };
 
 /* Parameters of one graph (parameter table of the paper: eta 1e-3, nb_iter 5,
  * rho in {1,2,10,100,200}, alpha 2.5, lambda 1e-5, beta 1.2, mu 1e-6 (GCP) or 0
  * (ECP), nu 0 (GCP) or 1e-5 (ECP)). */
 typedef struct {
     int32_t problem;        /* TCOL_KCOL or TCOL_ECP */
-    int32_t precision;      /* TCOL_FP32, TCOL_BF16 or TCOL_FP8 */
+    int32_t precision;      /* TCOL_FP32, TCOL_BF16, TCOL_FP8 or TCOL_FP4 */
     int32_t n, k, D;        /* vertices (1..32768), colours (1..4096), members (1..1024) */
     float eta, rho;         /* learning rate > 0; smoothing divisor >= 1 */
     int32_t nb_iter;        /* smoothing period >= 1 */

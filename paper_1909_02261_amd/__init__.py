@@ -12,9 +12,9 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 from . import _lib
-from ._lib import BF16, ECP, FP8, FP32, KCOL, TcolError
+from ._lib import BF16, ECP, FP4, FP8, FP32, KCOL, TcolError
 
-__all__ = ["Params", "Solver", "TensColLoss", "KCOL", "ECP", "FP32", "BF16", "FP8", "TcolError"]
+__all__ = ["Params", "Solver", "TensColLoss", "KCOL", "ECP", "FP32", "BF16", "FP8", "FP4", "TcolError"]
 
 
 @dataclass

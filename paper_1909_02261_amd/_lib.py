@@ -12,7 +12,7 @@ STATUS = {0: "TCOL_OK", -1: "TCOL_EINVAL", -2: "TCOL_ESHAPE", -3: "TCOL_EGRAPH",
           -5: "TCOL_ENONFINITE", -6: "TCOL_ENOMEM", -7: "TCOL_ESTATE"}
 
 KCOL, ECP = 0, 1
-FP32, BF16, FP8 = 0, 1, 2
+FP32, BF16, FP8, FP4 = 0, 1, 2, 3
 
 
 class GraphParams(ctypes.Structure):

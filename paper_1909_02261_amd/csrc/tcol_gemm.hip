@@ -3,7 +3,7 @@
 // with S_cat = [S_1 ... S_D] (n x D*k, stored transposed as S^T [D*k][n_pad])
 // and P the penalty operand built by the group-concentration kernel.
 //
-// A and S are 0/1, so A.S is exact in fp32, bf16 and fp8 operands with FP32
+// A and S are 0/1, so A.S is exact in fp32, bf16, fp8 and fp4 operands with FP32
 // accumulation; between the two passes each block gathers (A.S_d)[i, c_d(i)]
 // into 2 f_color(S_d) (the gradient's first term is the TabuCol gamma matrix,
 // whose entry at the vertex's own colour counts its conflicts).
@@ -38,6 +38,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ inline f32x4 mfma_fp8(const i32x8& a, const i32x8& b, const f32x4& c) {
     // operand formats 0/0 = fp8 e4m3; zero scale arguments select the unscaled instruction
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+__device__ inline f32x4 mfma_fp4(const i32x8& a, const i32x8& b, const f32x4& c) {
+    // operand formats 4/4 = fp4 e2m1 (the low four registers of each operand)
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, 0, 0, 0);
 }
 __device__ inline f32x4 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -79,6 +83,26 @@ __device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, i
             i32x8 b{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_fp8(a[mt], b, acc[mt][nt]);
+        }
+    } else if constexpr (PREC == kPrecFP4) {
+        // fp4: a 16-byte chunk holds 32 K entries; chunk ks*4+q feeds lane group q of
+        // the ks-th 16x16x128 step, in A and B alike
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int o = ((ks * 4 + q) ^ swz) * 16;
+            i32x8 a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const uint4 x = *(const uint4*)(L + (ra + mt * 16) * kStageRowBytes + o);
+                a[mt] = i32x8{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int nt = 0; nt < NTW; ++nt) {
+                const uint4 x = *(const uint4*)(L + (rb + nt * 16) * kStageRowBytes + o);
+                const i32x8 b{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_fp4(a[mt], b, acc[mt][nt]);
+            }
         }
     } else if constexpr (PREC == kPrecBF16) {
 #pragma unroll
@@ -190,7 +214,6 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[BM / 32][NTW], const uin
     }
 }
 
-__device__ inline int elem_bytes(int prec) { return prec == kPrecFP32 ? 4 : (prec == kPrecBF16 ? 2 : 1); }
 
 // XCD-aware order: hardware deals block b to XCD b mod 8, so give each XCD a
 // contiguous range of tiles (neighbouring tiles share operand panels in its L2)
@@ -206,7 +229,8 @@ __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, 
     const GraphDev& d = gd[g];
     const int local = tile - d.gm_begin[MODE];
     const int TM = d.gm_tm[MODE], TN = d.gm_tn[MODE];
-    // groups of 4 row tiles sweep the column tiles together
+    // groups of 4 row tiles sweep the column tiles together (measured faster than
+    // groups of 8, which cut the L2 misses by a third but not the time)
     constexpr int GM = 4;
     const int per_group = GM * TN;
     const int grp = local / per_group;
@@ -266,9 +290,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int eb = elem_bytes(PREC);
-    const size_t ld = (size_t)d.n_pad * eb;
-    const int nst = d.n_pad * eb / kStageRowBytes;
+    const size_t ld = op_row_bytes(PREC, d.n_pad);
+    const int nst = (int)(ld / kStageRowBytes);
 
     // per-lane columns: member and colour of each 16-column subtile
     int cm[NTW], cl[NTW];
@@ -318,7 +341,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     }
     if ((passes & 2) && dense_pen) {
         __syncthreads();
-        if constexpr (PREC == kPrecFP8) {
+        if constexpr (PREC == kPrecFP8 || PREC == kPrecFP4) {
             const size_t ld2 = (size_t)d.n_pad * 2;
             gemm_sweep<kPrecBF16, BM, NTW>(acc, (const uint8_t*)d.Pop + (size_t)m0 * ld2,
                                            (const uint8_t*)d.Sp2[pS] + (size_t)n0 * ld2, ld2,
@@ -485,9 +508,11 @@ static hipError_t gemm_dispatch(int op, const GemmShape& s, const GraphDev* gd, 
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP32, 0)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecBF16, 0)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP8, 0)
+    TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP4, 0)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP32, 1)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecBF16, 1)
     TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP8, 1)
+    TCOL_GEMM_SHAPES(TCOL_GEMM_CASE, kPrecFP4, 1)
     return hipErrorInvalidValue;
 }
 

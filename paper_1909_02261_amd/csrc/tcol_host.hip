@@ -44,16 +44,14 @@ enum Buf {
 struct Layout {
     size_t off[B_COUNT];
     size_t total;
-    int n_pad, rows_S, eb, mt_T, mt_tiles;
+    int n_pad, rows_S, mt_T, mt_tiles;
 };
 
-int elem_bytes_host(int prec) { return prec == TCOL_FP32 ? 4 : (prec == TCOL_BF16 ? 2 : 1); }
 
 Layout make_layout(const tcol_graph_params& p) {
     Layout L{};
     L.n_pad = round_up(p.n, kPadN);
     L.rows_S = round_up(p.D * p.k, 16) + kSRowSlack;
-    L.eb = elem_bytes_host(p.precision);
     L.mt_T = L.n_pad / 64;
     L.mt_tiles = L.mt_T * (L.mt_T + 1) / 2;
     const size_t n2 = (size_t)L.n_pad * L.n_pad;
@@ -65,10 +63,10 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_LUT_VB] = sizeof(double) * (p.D + 1);
     sz[B_W2] = sizeof(float) * dnk;
     sz[B_A8] = n2;
-    sz[B_AOP] = n2 * L.eb;
+    sz[B_AOP] = (size_t)L.n_pad * op_row_bytes(p.precision, L.n_pad);
     sz[B_POP] = n2 * (p.precision == TCOL_FP32 ? 4 : 2);
-    sz[B_S0] = sz[B_S1] = (size_t)L.rows_S * L.n_pad * L.eb;
-    sz[B_SP0] = sz[B_SP1] = p.precision == TCOL_FP8 ? (size_t)L.rows_S * L.n_pad * 2 : 0;
+    sz[B_S0] = sz[B_S1] = (size_t)L.rows_S * op_row_bytes(p.precision, L.n_pad);
+    sz[B_SP0] = sz[B_SP1] = prec_split(p.precision) ? (size_t)L.rows_S * L.n_pad * 2 : 0;
     sz[B_C0] = sz[B_C1] = sizeof(int16_t) * ((size_t)p.D * round_up(p.n, 64) + 64);
     sz[B_V0] = sz[B_V1] = sizeof(int32_t) * (size_t)p.D * p.k;
     sz[B_G] = sizeof(float) * dnk;
@@ -94,7 +92,7 @@ tcol_status check_params(const tcol_graph_params& p) {
     if (p.n < 1 || p.n > kMaxN || p.k < 1 || p.k > kMaxK || p.D < 1 || p.D > kMaxD) return TCOL_ESHAPE;
     if ((long long)p.D * p.k > (1LL << 26)) return TCOL_ESHAPE;
     if (p.problem != TCOL_KCOL && p.problem != TCOL_ECP) return TCOL_EINVAL;
-    if (p.precision < TCOL_FP32 || p.precision > TCOL_FP8) return TCOL_EINVAL;
+    if (p.precision < TCOL_FP32 || p.precision > TCOL_FP4) return TCOL_EINVAL;
     if (!(p.eta > 0.0f) || !(p.rho >= 1.0f) || p.nb_iter < 1) return TCOL_EINVAL;
     if (!(p.lambda >= 0.0f) || !(p.mu >= 0.0f) || !(p.nu >= 0.0f)) return TCOL_EINVAL;
     if (p.lambda > 0.0f && !(p.alpha > 1.0f)) return TCOL_EINVAL;
@@ -594,8 +592,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.Pop = b + L.off[B_POP];
         d.Sop[0] = b + L.off[B_S0];
         d.Sop[1] = b + L.off[B_S1];
-        d.Sp2[0] = q.precision == TCOL_FP8 ? (void*)(b + L.off[B_SP0]) : nullptr;
-        d.Sp2[1] = q.precision == TCOL_FP8 ? (void*)(b + L.off[B_SP1]) : nullptr;
+        d.Sp2[0] = prec_split(q.precision) ? (void*)(b + L.off[B_SP0]) : nullptr;
+        d.Sp2[1] = prec_split(q.precision) ? (void*)(b + L.off[B_SP1]) : nullptr;
         d.c[0] = (int16_t*)(b + L.off[B_C0]);
         d.c[1] = (int16_t*)(b + L.off[B_C1]);
         d.V[0] = (int32_t*)(b + L.off[B_V0]);

@@ -9,6 +9,15 @@ namespace tcol {
 constexpr int kPrecFP32 = 0;
 constexpr int kPrecBF16 = 1;
 constexpr int kPrecFP8 = 2;
+constexpr int kPrecFP4 = 3;
+
+// A.S in fp8 or fp4: the penalty pass then runs on bf16 copies of the operands
+__host__ __device__ inline bool prec_split(int prec) { return prec == kPrecFP8 || prec == kPrecFP4; }
+// bytes of one operand row of n_pad elements (n_pad a multiple of 256)
+__host__ __device__ inline size_t op_row_bytes(int prec, int n_pad) {
+    return prec == kPrecFP32 ? 4 * (size_t)n_pad
+                             : (prec == kPrecBF16 ? 2 * (size_t)n_pad : (prec == kPrecFP8 ? (size_t)n_pad : (size_t)n_pad / 2));
+}
 
 constexpr int kMaxN = 32768;
 constexpr int kMaxK = 4096;
@@ -55,7 +64,7 @@ struct GraphDev {
     void* Aop;                // [n_pad][n_pad] A in the operand precision
     void* Pop;                // [n_pad][n_pad] penalty operand (fp32, or bf16 for BF16/FP8)
     void* Sop[2];             // [rows_S][n_pad] S^T in the A.S operand precision
-    void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 penalty pass (else null)
+    void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 / FP4 penalty pass (else null)
     int16_t* c[2];            // colours [D][cs] (member-major; entries n..cs-1 unused)
     int32_t* V[2];            // class sizes [D][k]
     float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)

@@ -36,7 +36,8 @@ __device__ inline int graph_of_row(const GraphDev* gd, int G, int w) {
 // ------------------------------------------------------ validation, packing --
 
 // Checks A (n x n, row-major 0/1, symmetric, zero diagonal) and writes the
-// zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]).
+// zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]; in fp4 two
+// entries per byte, the lower column in the low nibble, 1.0 = 0x2).
 __global__ void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
                              uint8_t* __restrict__ A8, void* __restrict__ Aop, int* __restrict__ bad) {
     long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,8 +56,13 @@ __global__ void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, in
         ((float*)Aop)[e] = a ? 1.0f : 0.0f;
     else if (prec == kPrecBF16)
         ((uint16_t*)Aop)[e] = a ? 0x3F80 : 0;
-    else
+    else if (prec == kPrecFP8)
         ((uint8_t*)Aop)[e] = a ? 0x38 : 0;
+    else if ((j & 1) == 0) {
+        // the even column writes the byte of the pair (n_pad is even)
+        const uint8_t a1 = (i < n && j + 1 < n) ? (A[(size_t)i * n + j + 1] ? 1 : 0) : 0;
+        ((uint8_t*)Aop)[e >> 1] = (uint8_t)((a ? 0x2 : 0) | (a1 ? 0x20 : 0));
+    }
 }
 
 // ------------------------------------------------------------ step 1 -----------
@@ -376,8 +382,9 @@ __global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict_
     }
 }
 
-// One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread.
-// For FP8 graphs the bf16 copy used by the penalty pass is written as well.
+// One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread
+// (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
+// and FP4 graphs the bf16 copy used by the penalty pass is written as well.
 __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                 int honor_stop, int next, int gate) {
     const int b = blockIdx.x;
@@ -386,8 +393,8 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
-    // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
-    const bool want_sp2 = d.precision == kPrecFP8 && (!gate || !d.sparse);
+    // the bf16 copy of S feeds only the dense penalty pass of FP8 / FP4 graphs
+    const bool want_sp2 = prec_split(d.precision) && (!gate || !d.sparse);
     const int cgs = d.n_pad / 16;
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
     const int row = (int)(item / cgs);
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
         uint4* o = (uint4*)(sb + off);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            if (!want_sp2 && d.precision == kPrecFP8) break;
+            if (!want_sp2 && prec_split(d.precision)) break;
             uint32_t w[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -446,6 +453,12 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
                 w[h] = x;
             }
             *(uint4*)((uint8_t*)d.Sop[p] + off) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else if (d.precision == kPrecFP4) {
+            uint32_t w[2] = {0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if ((mask >> q) & 1) w[q >> 3] |= 0x2u << (4 * (q & 7));
+            *(uint2*)((uint8_t*)d.Sop[p] + (off >> 1)) = make_uint2(w[0], w[1]);
         }
     }
 }

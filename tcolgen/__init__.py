@@ -242,7 +242,7 @@ def fd_entries(count: int, D: int, n: int, k: int, seed: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 KCOL, ECP = 0, 1
-FP32, BF16, FP8 = 0, 1, 2
+FP32, BF16, FP8, FP4 = 0, 1, 2, 3
 
 
 @dataclass

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import tcolgen
-from tcolgen import BF16, ECP, FP8, FP32, KCOL, GraphCase
+from tcolgen import BF16, ECP, FP4, FP8, FP32, KCOL, GraphCase
 
 from gpu_util import loss_scale, make_solver, normwise, orc_params
 
@@ -23,7 +23,7 @@ TOL = 1e-5
 
 def small_cases():
     out = []
-    for prec in (FP32, BF16, FP8):
+    for prec in (FP32, BF16, FP8, FP4):
         out.append(GraphCase(f"ragged77_kcol_p{prec}", KCOL, 77, 7, 5, prec, "gnp", 0.4, graph_seed=7,
                              rho=10.0, lam=1e-2, mu=3e-3))
         out.append(GraphCase(f"ragged150_ecp_p{prec}", ECP, 150, 11, 6, prec, "gnp", 0.5, graph_seed=8,
@@ -57,7 +57,7 @@ def test_conflicts_bit_exact(case):
 SHAPES = [(64, 2), (64, 4), (128, 4), (128, 8), (64, 9), (128, 9), (256, 4)]
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16, FP8])
+@pytest.mark.parametrize("prec", [FP32, BF16, FP8, FP4])
 def test_conflicts_every_tile_shape(prec):
     """f_color through the contraction's gather is exact for every instantiated tile shape, on a
     graph whose size spans several row tiles with a ragged tail and whose D*k is not a multiple
@@ -161,7 +161,7 @@ def test_c1_resynced_200_steps(path):
 
 
 @pytest.mark.parametrize("path", [p for p in PATHS if p != "plain"])
-@pytest.mark.parametrize("prec", [FP32, BF16, FP8])
+@pytest.mark.parametrize("prec", [FP32, BF16, FP8, FP4])
 def test_fused_large_k_resynced(path, prec):
     """Many colours against few members (the shape where the penalty operand is sparse),
     ECP so every loss term is active, a ragged n and several tiles."""
@@ -185,7 +185,7 @@ def test_degenerate_population(path):
 
 
 @pytest.mark.parametrize("path", list(PATHS))
-@pytest.mark.parametrize("prec", [BF16, FP8])
+@pytest.mark.parametrize("prec", [BF16, FP8, FP4])
 def test_small_resynced_low_precision(prec, path):
     case = GraphCase("kcol90", KCOL, 90, 9, 6, prec, "gnp", 0.5, graph_seed=12, rho=10.0, lam=1e-2, mu=3e-3)
     # bf16 penalty operand: errors against FP64 are reported; the bound only catches wrong arithmetic
@@ -204,7 +204,7 @@ def test_planted_stops_at_step0():
     P = tcolgen.planted(case.n, case.k, case.graph_seed)
     W = case.weights()
     W[5, np.arange(case.n), P.classes] += 1.0     # member 5 holds the hidden legal colouring
-    for prec, fused in ((FP8, 1), (BF16, 2), (FP32, 0), (FP8, 0), (FP8, 2)):
+    for prec, fused in ((FP8, 1), (BF16, 2), (FP32, 0), (FP8, 0), (FP8, 2), (FP4, 1), (FP4, 2)):
         case.precision = prec
         s, _ = make_solver([case], As=[P.A], Ws=[W], fused=fused)
         c, fc, fe = s.conflicts(0)
@@ -361,8 +361,9 @@ def test_autograd_backward_matches_step_and_finite_differences():
     s.close()
 
 
-@pytest.mark.parametrize("mk", [lambda: tcolgen.case_c4(BF16), lambda: tcolgen.case_c3(FP8), lambda: tcolgen.case_c3(BF16)],
-                         ids=["C4_ecp_bf16", "C3_fp8", "C3_bf16"])
+@pytest.mark.parametrize("mk", [lambda: tcolgen.case_c4(BF16), lambda: tcolgen.case_c3(FP8), lambda: tcolgen.case_c3(BF16),
+                                lambda: tcolgen.case_c3(FP4)],
+                         ids=["C4_ecp_bf16", "C3_fp8", "C3_bf16", "C3_fp4"])
 def test_full_size_conflicts_and_equity_exact(mk):
     case = mk()
     s, (A,) = make_solver([case])
@@ -378,8 +379,9 @@ def test_full_size_conflicts_and_equity_exact(mk):
     s.close()
 
 
-def test_c5_full_size_fp8():
-    case = tcolgen.case_c5(FP8)
+@pytest.mark.parametrize("prec", [FP8, FP4], ids=["fp8", "fp4"])
+def test_c5_full_size(prec):
+    case = tcolgen.case_c5(prec)
     s, (A,) = make_solver([case])
     s.set_t(100)
     c, fc, fe = s.conflicts(0)
@@ -396,6 +398,6 @@ def test_c5_full_size_fp8():
     gS_ref = oracle.grad_s(p, 100, A, c_ref, Mt, V)
     eS = normwise(host(gs), gS_ref)
     eW = normwise(host(gw), oracle.grad_w(W.astype(np.float64), gS_ref))
-    print(f"C5 fp8: gradS {eS:.2e} gradW {eW:.2e}")
+    print(f"C5 precision {prec}: gradS {eS:.2e} gradW {eW:.2e}")
     assert eS <= 1e-2 and eW <= 1e-2
     s.close()
