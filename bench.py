@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
-    ap.add_argument("--penalty", default="auto", choices=["auto", "dense", "sparse"])
+    ap.add_argument("--penalty", default="dense", choices=["auto", "dense", "gather"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -133,7 +133,7 @@ def main():
     import torch
     import paper_1909_02261_amd as pk
 
-    prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp8", "c4": "bf16", "c5": "fp8"}[args.workload]
+    prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp4", "c4": "bf16", "c5": "fp4"}[args.workload]
     case = workload(args.workload, prec)
     print(f"[bench] workload {case.name} precision {prec}: generating inputs", file=sys.stderr, flush=True)
     A = case.adjacency()
@@ -144,7 +144,7 @@ def main():
     s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
     s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
-                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
+                  penalty={"auto": 0, "dense": 1, "gather": 2}[args.penalty])
     if args.autotune:
         print("[bench] autotuning tile shape / penalty mode", file=sys.stderr, flush=True)
         s.autotune()
@@ -197,7 +197,7 @@ def main():
     config = {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
               "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
               "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
-              "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]}
+              "penalty": {0: "auto", 1: "dense", 2: "gather"}[opts["penalty"]], "fused": opts["fused"]}
     roof["traffic"] = measured_traffic(config)
     out = {
         "metric": "population-iterations/s (D*steps/s)",

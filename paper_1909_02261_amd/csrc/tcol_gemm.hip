@@ -12,8 +12,9 @@
 // with BN = 32 * NTW; each wave owns (BM/2) x (16 NTW) as 16x16 MFMA subtiles.
 // Both operands are K-contiguous; a K-stage moves 128 bytes of every operand
 // row straight from global memory into LDS (global_load_lds, 16 bytes per
-// lane, no registers on the way), triple buffered: the loads of stages s+1 and
-// s+2 are in flight while stage s feeds the MFMAs.  Within a 128-byte LDS row the
+// lane, no registers on the way) through two or three stage buffers, and the
+// fragments of the next stage are read while the MFMAs of the current one run
+// (see gemm_sweep).  Within a 128-byte LDS row the
 // 16-byte chunk c of row r sits in slot c ^ ((r / 2) mod 8): a fragment read
 // covers 16 consecutive rows at one chunk, and with 64 four-byte banks the bank
 // of (row, slot) depends on (row mod 2, slot), so those 16 reads land in 16
@@ -57,89 +58,78 @@ struct Tile {
     static constexpr int STAGE = (BM + BN) * kStageRowBytes; // bytes per LDS stage
     static constexpr int GROUPS = (BM + BN) / 32;            // 8-row load groups per wave per stage
     static_assert((BM + BN) % 32 == 0, "load split");
+    // LDS stage buffers: three, unless only two keep the block within 80 KB (two
+    // blocks, i.e. two waves per SIMD, per CU)
+    static constexpr int NB = (3 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 3 : ((2 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 2 : 3);
 };
 
-// compute one LDS stage into acc (operand format PREC); chunk c of row r is at slot c ^ ((r >> 1) & 7)
+// Fragments of one LDS stage for one wave (chunk c of row r sits at slot c ^ ((r >> 1) & 7)).
+// A stage is one K-step of the 16x16x128 fp8 MFMA (32 bytes per lane: chunks 2q and
+// 2q+1) or two K-steps of 16 bytes per lane (chunk 4 ks + q) for fp4 (16x16x128),
+// bf16 (16x16x32) and fp32 (four 16x16x4); A and B use the same chunks, so every
+// format sums the plain product.
 template <int PREC, int BM, int NTW>
-__device__ inline void stage_mma(f32x4 (&acc)[BM / 32][NTW], const uint8_t* L, int lane, int wm, int wn) {
-    constexpr int MT = BM / 32;
+struct StageFrags {
+    static constexpr int MT = BM / 32;
+    static constexpr int SUB = PREC == kPrecFP8 ? 1 : 2;   // K-steps per stage
+    static constexpr int W = PREC == kPrecFP8 ? 2 : 1;     // 16-byte chunks per fragment
+    uint4 a[SUB][MT][W], b[SUB][NTW][W];
+};
+
+template <int PREC, int BM, int NTW>
+__device__ __forceinline__ void stage_read(StageFrags<PREC, BM, NTW>& F, const uint8_t* L, int lane, int wm, int wn) {
+    using Fr = StageFrags<PREC, BM, NTW>;
     const int ra = wm * (BM / 2) + (lane & 15);
     const int rb = BM + wn * (NTW * 16) + (lane & 15);
     const int q = lane >> 4;
     const int swz = (lane & 15) >> 1;  // = (row >> 1) & 7 for every row this lane reads
-    if constexpr (PREC == kPrecFP8) {
-        const int o0 = ((2 * q) ^ swz) * 16, o1 = ((2 * q + 1) ^ swz) * 16;
-        i32x8 a[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const uint8_t* p = L + (ra + mt * 16) * kStageRowBytes;
-            const uint4 x0 = *(const uint4*)(p + o0), x1 = *(const uint4*)(p + o1);
-            a[mt] = i32x8{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+    for (int ks = 0; ks < Fr::SUB; ++ks) {
+#pragma unroll
+        for (int w = 0; w < Fr::W; ++w) {
+            const int o = ((Fr::W == 2 ? 2 * q + w : ks * 4 + q) ^ swz) * 16;
+#pragma unroll
+            for (int mt = 0; mt < Fr::MT; ++mt) F.a[ks][mt][w] = *(const uint4*)(L + (ra + mt * 16) * kStageRowBytes + o);
         }
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) {
-            const uint8_t* p = L + (rb + nt * 16) * kStageRowBytes;
-            const uint4 x0 = *(const uint4*)(p + o0), x1 = *(const uint4*)(p + o1);
-            i32x8 b{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+        for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_fp8(a[mt], b, acc[mt][nt]);
-        }
-    } else if constexpr (PREC == kPrecFP4) {
-        // fp4: a 16-byte chunk holds 32 K entries; chunk ks*4+q feeds lane group q of
-        // the ks-th 16x16x128 step, in A and B alike
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int o = ((ks * 4 + q) ^ swz) * 16;
-            i32x8 a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const uint4 x = *(const uint4*)(L + (ra + mt * 16) * kStageRowBytes + o);
-                a[mt] = i32x8{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+            for (int w = 0; w < Fr::W; ++w) {
+                const int o = ((Fr::W == 2 ? 2 * q + w : ks * 4 + q) ^ swz) * 16;
+                F.b[ks][nt][w] = *(const uint4*)(L + (rb + nt * 16) * kStageRowBytes + o);
             }
+    }
+}
+
+template <int PREC, int BM, int NTW>
+__device__ __forceinline__ void stage_mma(f32x4 (&acc)[BM / 32][NTW], const StageFrags<PREC, BM, NTW>& F) {
+    using Fr = StageFrags<PREC, BM, NTW>;
 #pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                const uint4 x = *(const uint4*)(L + (rb + nt * 16) * kStageRowBytes + o);
-                const i32x8 b{(int)x.x, (int)x.y, (int)x.z, (int)x.w, 0, 0, 0, 0};
+    for (int ks = 0; ks < Fr::SUB; ++ks)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_fp4(a[mt], b, acc[mt][nt]);
-            }
-        }
-    } else if constexpr (PREC == kPrecBF16) {
+        for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int o = ((ks * 4 + q) ^ swz) * 16;
-            bf16x8 a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) a[mt] = *(const bf16x8*)(L + (ra + mt * 16) * kStageRowBytes + o);
-#pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                bf16x8 b = *(const bf16x8*)(L + (rb + nt * 16) * kStageRowBytes + o);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_bf16(a[mt], b, acc[mt][nt]);
-            }
-        }
-    } else {
-        // fp32: a float4 at k = 16 ks + 4 q .. +4 feeds four 16x16x4 steps; A and B
-        // use the same k order, so the sum is the plain product
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int o = ((ks * 4 + q) ^ swz) * 16;
-            float4 a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) a[mt] = *(const float4*)(L + (ra + mt * 16) * kStageRowBytes + o);
-#pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                float4 b = *(const float4*)(L + (rb + nt * 16) * kStageRowBytes + o);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    acc[mt][nt] = mfma_f32(a[mt].x, b.x, acc[mt][nt]);
-                    acc[mt][nt] = mfma_f32(a[mt].y, b.y, acc[mt][nt]);
-                    acc[mt][nt] = mfma_f32(a[mt].z, b.z, acc[mt][nt]);
-                    acc[mt][nt] = mfma_f32(a[mt].w, b.w, acc[mt][nt]);
+            for (int mt = 0; mt < Fr::MT; ++mt) {
+                const uint4 a0 = F.a[ks][mt][0], b0 = F.b[ks][nt][0];
+                if constexpr (PREC == kPrecFP8) {
+                    const uint4 a1 = F.a[ks][mt][Fr::W - 1], b1 = F.b[ks][nt][Fr::W - 1];
+                    const i32x8 a{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+                    const i32x8 b{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+                    acc[mt][nt] = mfma_fp8(a, b, acc[mt][nt]);
+                } else if constexpr (PREC == kPrecFP4) {
+                    const i32x8 a{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, 0, 0, 0, 0};
+                    const i32x8 b{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, 0, 0, 0, 0};
+                    acc[mt][nt] = mfma_fp4(a, b, acc[mt][nt]);
+                } else if constexpr (PREC == kPrecBF16) {
+                    acc[mt][nt] = mfma_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[mt][nt]);
+                } else {
+                    const float4 a = __builtin_bit_cast(float4, a0), b = __builtin_bit_cast(float4, b0);
+                    acc[mt][nt] = mfma_f32(a.x, b.x, acc[mt][nt]);
+                    acc[mt][nt] = mfma_f32(a.y, b.y, acc[mt][nt]);
+                    acc[mt][nt] = mfma_f32(a.z, b.z, acc[mt][nt]);
+                    acc[mt][nt] = mfma_f32(a.w, b.w, acc[mt][nt]);
                 }
             }
-        }
-    }
 }
 
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
@@ -172,7 +162,6 @@ __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-constexpr int kStages = 3;   // LDS stage buffers
 
 // Workgroup barrier without the memory fence of __syncthreads(): that fence would
 // make every wave drain all its loads, including the prefetches of later stages.
@@ -190,30 +179,71 @@ __device__ __forceinline__ void stage_barrier() {
 
 // One K-sweep: acc += Arows[m0.., :] . Brows[n0.., :]^T over `nstages` stages
 // of 128 bytes.  Arow / Brow point at the first row of the tile; ld in bytes.
+// Two pipelines: global -> LDS runs NB stages ahead through the NB stage buffers,
+// and LDS -> registers one stage ahead through two fragment sets, so the fragment
+// reads of stage s+1 proceed while the MFMAs of stage s run.  At the top of
+// iteration s every wave has finished reading stage s, so its buffer takes the
+// loads of stage s+NB.  Large tiles, whose two fragment sets would spill, keep one.
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[BM / 32][NTW], const uint8_t* __restrict__ Arow,
                                            const uint8_t* __restrict__ Brow, size_t ld, int nstages,
                                            uint8_t* lds) {
     using T = Tile<BM, NTW>;
+    using Fr = StageFrags<PREC, BM, NTW>;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    stage_load<BM, NTW>(Arow, Brow, ld, 0, lds, lane, wave);
-    stage_load<BM, NTW>(Arow, Brow, ld, min(1, nstages - 1), lds + T::STAGE, lane, wave);
-    wait_vm<T::GROUPS>();          // stage 0 has landed, stage 1 may be in flight
-    stage_barrier();
-    int cur = 0;
-    for (int s = 0; s < nstages; ++s) {
-        const int nxt = cur >= kStages - 2 ? cur - (kStages - 2) : cur + 2;   // (s + 2) mod 3
-        // stages past the end reload the last one into the idle buffer; nobody reads it
-        stage_load<BM, NTW>(Arow, Brow, ld, min(s + 2, nstages - 1), lds + nxt * T::STAGE, lane, wave);
-        stage_mma<PREC, BM, NTW>(acc, lds + cur * T::STAGE, lane, wm, wn);
-        wait_vm<T::GROUPS>();      // stage s+1 has landed, stage s+2 may be in flight
+    if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64) {
+        // tiles whose fragments would not fit twice in registers: one fragment set, the
+        // global -> LDS loads two stages ahead
+        static_assert(T::NB == 3, "three stage buffers");
+        stage_load<BM, NTW>(Arow, Brow, ld, 0, lds, lane, wave);
+        stage_load<BM, NTW>(Arow, Brow, ld, min(1, nstages - 1), lds + T::STAGE, lane, wave);
+        wait_vm<T::GROUPS>();      // stage 0 has landed, stage 1 may be in flight
         stage_barrier();
-        cur = cur == kStages - 1 ? 0 : cur + 1;
+        int cur = 0;
+        for (int s = 0; s < nstages; ++s) {
+            const int nxt = cur >= 1 ? cur - 1 : cur + 2;   // (s + 2) mod 3
+            stage_load<BM, NTW>(Arow, Brow, ld, min(s + 2, nstages - 1), lds + nxt * T::STAGE, lane, wave);
+            Fr F;
+            stage_read<PREC, BM, NTW>(F, lds + cur * T::STAGE, lane, wm, wn);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mma<PREC, BM, NTW>(acc, F);
+            wait_vm<T::GROUPS>();  // stage s+1 has landed, stage s+2 may be in flight
+            stage_barrier();
+            cur = cur == 2 ? 0 : cur + 1;
+        }
+        return;
+    }
+    // stages past the end reload the last one into a free buffer; nobody reads it
+    constexpr int NB = T::NB;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) stage_load<BM, NTW>(Arow, Brow, ld, min(b, nstages - 1), lds + b * T::STAGE, lane, wave);
+    wait_vm<(NB - 1) * T::GROUPS>();   // stage 0 has landed
+    stage_barrier();
+    Fr F0, F1;
+    stage_read<PREC, BM, NTW>(F0, lds, lane, wm, wn);
+    int cur = 0;                   // buffer of stage s
+    for (int s = 0; s < nstages; s += 2) {
+        // ---- stage s (fragments in F0)
+        wait_vm<(NB - 2) * T::GROUPS>();   // stage s+1 has landed (later ones may be in flight)
+        stage_barrier();           // ... for every wave, and every wave has stage s in registers
+        stage_load<BM, NTW>(Arow, Brow, ld, min(s + NB, nstages - 1), lds + cur * T::STAGE, lane, wave);
+        cur = cur == NB - 1 ? 0 : cur + 1;
+        if (s + 1 < nstages) stage_read<PREC, BM, NTW>(F1, lds + cur * T::STAGE, lane, wm, wn);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_mma<PREC, BM, NTW>(acc, F0);
+        if (s + 1 >= nstages) break;
+        // ---- stage s+1 (fragments in F1)
+        wait_vm<(NB - 2) * T::GROUPS>();
+        stage_barrier();
+        stage_load<BM, NTW>(Arow, Brow, ld, min(s + 1 + NB, nstages - 1), lds + cur * T::STAGE, lane, wave);
+        cur = cur == NB - 1 ? 0 : cur + 1;
+        if (s + 2 < nstages) stage_read<PREC, BM, NTW>(F0, lds + cur * T::STAGE, lane, wm, wn);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_mma<PREC, BM, NTW>(acc, F1);
     }
 }
-
 
 // XCD-aware order: hardware deals block b to XCD b mod 8, so give each XCD a
 // contiguous range of tiles (neighbouring tiles share operand panels in its L2)
@@ -241,14 +271,14 @@ __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, 
 }
 
 template <int PREC, int BM, int NTW, int MODE>
-__global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, int G, int total_tiles,
-                                              int honor_stop, int passes, int cstage) {
+__device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G, int total_tiles, int honor_stop,
+                                          int passes, int cstage) {
     using T = Tile<BM, NTW>;
     constexpr int MT = T::MT;
     constexpr int BN = T::BN;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int* f2l = (int*)(lds + kStages * T::STAGE);     // BN + 2 gather counters
-    static_assert((BN + 2) * BM * 2 <= kStages * T::STAGE, "gather colours fit the stage buffers");
+    int* f2l = (int*)(lds + T::NB * T::STAGE);       // BN + 2 gather counters
+    static_assert((BN + 2) * BM * 2 <= T::NB * T::STAGE, "gather colours fit the stage buffers");
 
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     int g, tm, tn;
@@ -259,10 +289,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
     const int pS = st->pS;
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
-    // a graph takes either the dense operand pass or the penalty rows of the sparse
+    // a graph takes either the dense operand pass or the penalty rows of the class-gather
     // kernel (already in G); the plain path (passes bit 3) always takes the dense pass
-    const bool sparse_pen = pen && d.sparse && !(passes & 8);
-    const bool dense_pen = pen && !sparse_pen;
+    const bool gather_pen = pen && d.pgather && !(passes & 8);
+    const bool dense_pen = pen && !gather_pen;
 
     // graph fields in registers: reading them through gd after a store or an
     // atomic would reload them, one dependent round trip per use
@@ -364,7 +394,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                     for (int nt = 0; nt < NTW; ++nt)
                         if (cm[nt] >= 0) {
                             float* gp = Gg + ((size_t)cm[nt] * n + i) * k + cl[nt];
-                            *gp = sparse_pen ? acc[mt][nt][r] + *gp : acc[mt][nt][r];
+                            *gp = gather_pen ? acc[mt][nt][r] + *gp : acc[mt][nt][r];
                         }
                 }
             }
@@ -410,7 +440,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 const float* w = Wc + rowoff;
                 float* wo = Wn + rowoff;
                 const float* gr = Gt + r * LDG + dm * k;
-                const float* g1 = Gg + rowoff;      // penalty rows of the sparse kernel
+                const float* g1 = Gg + rowoff;      // penalty rows of the class-gather kernel
                 const int32_t* V = Vp + (size_t)dd * k;
                 float mx = -INFINITY;
                 for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
@@ -419,7 +449,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx);
                     float gv = gr[l];
-                    if (sparse_pen) gv += g1[l];
+                    if (gather_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
                     z += e;
                     q += e * gv;
@@ -435,7 +465,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, i
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx) * rz;
                     float gv = gr[l];
-                    if (sparse_pen) gv += g1[l];
+                    if (gather_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
                     float nw = w[l] - eta * (e * (gv - rq));
                     if (smooth) nw = nw / rho;
@@ -468,16 +498,39 @@ constexpr int kMaxLds = 160 * 1024;
 template <int BM, int NTW, int MODE>
 static size_t lds_bytes(int cstage) {
     using T = Tile<BM, NTW>;
-    const size_t sweep = kStages * T::STAGE + sizeof(int) * (T::BN + 2);
+    const size_t sweep = T::NB * T::STAGE + sizeof(int) * (T::BN + 2);
     if (MODE == 0) return sweep;
     const size_t epi = (size_t)(BM < 128 ? BM : 128) * (T::BN + 4) * sizeof(float) + (size_t)cstage;
     return sweep > epi ? sweep : epi;
 }
 
+// The contraction kernel.  Tiles whose stage buffers leave room for a second block
+// per CU are compiled for two waves per SIMD (at most 256 registers per lane), so
+// that the second block can actually be resident.
+template <int PREC, int BM, int NTW, int MODE>
+__global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, int G, int total_tiles,
+                                              int honor_stop, int passes, int cstage) {
+    gemm_body<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, cstage);
+}
+template <int PREC, int BM, int NTW, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_x2(
+    const GraphDev* __restrict__ gd, int G, int total_tiles, int honor_stop, int passes, int cstage) {
+    gemm_body<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, cstage);
+}
+template <int BM, int NTW, int MODE>
+constexpr bool two_per_cu() {
+    using T = Tile<BM, NTW>;
+    return MODE == 0 && T::NB * T::STAGE + 4 * (T::BN + 2) <= 80 * 1024;
+}
+
 template <int PREC, int BM, int NTW, int MODE>
 static hipError_t prep_one() {
-    return hipFuncSetAttribute((const void*)k_gemm<PREC, BM, NTW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kMaxLds);
+    const void* f;
+    if constexpr (two_per_cu<BM, NTW, MODE>())
+        f = (const void*)k_gemm_x2<PREC, BM, NTW, MODE>;
+    else
+        f = (const void*)k_gemm<PREC, BM, NTW, MODE>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
 }
 
 template <int PREC, int BM, int NTW, int MODE>
@@ -485,8 +538,12 @@ static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int hon
                              hipStream_t s) {
     const size_t shm = lds_bytes<BM, NTW, MODE>(cstage);
     if (shm > (size_t)kMaxLds) return hipErrorInvalidValue;
-    k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop, passes,
-                                                                         cstage);
+    if constexpr (two_per_cu<BM, NTW, MODE>())
+        k_gemm_x2<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop,
+                                                                                passes, cstage);
+    else
+        k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop, passes,
+                                                                             cstage);
     return hipGetLastError();
 }
 

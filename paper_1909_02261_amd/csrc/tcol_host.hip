@@ -11,7 +11,7 @@
 // Three step sequences (tcol_options.fused):
 //   0 plain: colours -> classes -> one-hot S -> dense penalty operand -> contraction
 //     storing G -> fitness / stop -> update -> counter;
-//   1 fast: classes -> penalty rows (sparse kernel) or dense operand -> one-hot S ->
+//   1 fast: classes -> penalty rows (class-gather kernel) or dense operand -> one-hot S ->
 //     contraction storing G -> fitness / stop -> update that also colours the new rows
 //     -> counter (the colours of the first iteration come from one argmax pass);
 //   2 epilogue: classes -> penalty -> one-hot S -> contraction whose epilogue updates W
@@ -38,7 +38,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_LST, B_LCNT, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_COUNT
 };
 
 struct Layout {
@@ -75,8 +75,8 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
     sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
-    sz[B_LST] = sizeof(uint32_t) * (size_t)p.n * L.n_pad;
-    sz[B_LCNT] = sizeof(int32_t) * (size_t)p.n * (L.n_pad / kPlSeg);
+    sz[B_CLSV] = sizeof(int16_t) * (size_t)p.D * round_up(p.n, 64);
+    sz[B_CLSOFF] = sizeof(int32_t) * (size_t)p.D * (p.k + 1);
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -126,9 +126,10 @@ struct tcol_ctx {
     GemmShape shape{};              // separate-path tiling (also used by tcol_conflicts / tcol_loss_grad)
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
-    int sp_R = 0, sp_DM = 0;        // sparse penalty tiles: rows x members (0: no graph uses it)
-    size_t sp_lds = 0, pl_lds = 0;  // dynamic LDS of the sparse scatter and list kernels
-    int total_pl = 0, total_ps = 0; // blocks of the sparse list and scatter kernels
+    int pg_R = 0, pg_M = 0;         // class-gather penalty: rows per block, members per list stage
+    size_t pg_lds = 0;              // dynamic LDS of the class-gather kernel
+    size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
+    int total_pg = 0;               // blocks of the class-gather kernel (0: no graph uses it)
     int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0;
     int total_gm[2] = {0, 0};
     int kmax = 0, nmax = 0;
@@ -198,13 +199,14 @@ static long long tiles_for(const tcol_ctx* c, int bm, int ntw, int mode) {
 
 // Estimated time of one contraction launch with a tile shape: tiles run in
 // rounds of (CUs x resident blocks), and a tile costs its MFMA work (BM x BN per
-// K-stage) plus its operand staging (BM + BN rows per K-stage).  Small tiles fit
-// two blocks per CU (LDS and registers); the large ones one.
+// K-stage) plus its operand staging (BM + BN rows per K-stage).  Tiles whose stage
+// buffers fit in 80 KB run two blocks per CU; the large ones one.
 static double shape_cost(const tcol_ctx* c, int bm, int ntw) {
     const long long tiles = tiles_for(c, bm, ntw, 0);
     const int bn = gemm_bn(ntw);
-    const int lds = 3 * (bm + bn) * 128;
-    const int per_cu = (bm * bn <= 64 * 128 && 2 * lds <= kMaxLdsBytes) ? 2 : 1;
+    // the kernel keeps three stage buffers, or two when only two fit two blocks per CU
+    const int stage = (bm + bn) * 128, extra = 4 * (bn + 2);
+    const int per_cu = (3 * stage + extra <= 80 * 1024 || 2 * stage + extra <= 80 * 1024) ? 2 : 1;
     const long long rounds = (tiles + 256LL * per_cu - 1) / (256LL * per_cu);
     return (double)rounds * ((double)bm * bn + 32.0 * (bm + bn));
 }
@@ -248,40 +250,47 @@ static void pick_shapes(tcol_ctx* c) {
     c->fused_ok = f.ntw > 0 && common_precision(c) >= 0;
 }
 
+// Automatic penalty mode: the dense bf16 (fp32) operand pass.  The class gather does
+// k times fewer operations but is latency-bound in its current form and slower on
+// every workload measured, so it runs only on request.
+static bool gather_preferred(const tcol_graph_params&) { return false; }
+
 // recompute flattened work offsets for the tile shapes and upload the descriptors
 static tcol_status rebuild_schedule(tcol_ctx* c) {
     pick_shapes(c);
     HIPCHK(gemm_prepare(c->shape));
     if (c->fused_ok) HIPCHK(gemm_prepare(c->fshape));
-    HIPCHK(penalty_sparse_prepare());
+    HIPCHK(penalty_gather_prepare());
     const int BN0 = gemm_bn(c->shape.ntw);
     const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
-    // sparse penalty: a graph takes it on request; tiles of R rows x DM members with the
-    // DM x R x k histograms in LDS (DM a power of two <= 8, R a multiple of 4)
-    int sp_k = 0, sp_D = 0, sp_n = 0;
+    // class-gather penalty: a graph takes it on request (penalty 2) or when the automatic
+    // choice prefers it
+    int pg_k = 0, pg_D = 0, pg_n = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
-        c->hdesc[g].sparse = c->opt.penalty == 2 ? 1 : 0;
-        if (c->hdesc[g].sparse) {
-            sp_k = std::max(sp_k, p.k);
-            sp_D = std::max(sp_D, p.D);
-            sp_n = std::max(sp_n, p.n);
+        const int pen = c->opt.penalty;
+        c->hdesc[g].pgather = (pen == 2 || (pen == 0 && gather_preferred(p))) ? 1 : 0;
+        if (c->hdesc[g].pgather) {
+            pg_k = std::max(pg_k, p.k);
+            pg_D = std::max(pg_D, p.D);
+            pg_n = std::max(pg_n, p.n);
         }
     }
-    c->sp_R = c->sp_DM = 0;
-    c->sp_lds = c->pl_lds = 0;
-    if (sp_k > 0) {
-        int DM = 8;
-        while (DM > 1 && DM / 2 >= sp_D) DM /= 2;
-        while (DM > 1 && 4LL * DM * sp_k * 4 > 150 * 1024) DM /= 2;
-        int R = (int)std::min<long long>(64, (64LL * 1024) / (4LL * DM * sp_k)) & ~3;
-        R = std::max(R, 4);
-        c->sp_R = R;
-        c->sp_DM = DM;
-        c->sp_lds = penalty_scatter_lds(R, DM, sp_k, sp_D, sp_n);
-        c->pl_lds = penalty_list_lds(sp_D);
+    c->pg_R = c->pg_M = 0;
+    c->pg_lds = 0;
+    if (pg_k > 0) {
+        // rows per block: codes of at most 40 KB; then as many staged members as keep the
+        // block within 80 KB (two blocks per CU); very large n falls back to one row and one member
+        int R = 8;
+        while (R > 1 && 2LL * R * round_up(pg_n, kPadN) > 40 * 1024) R /= 2;
+        int M = 8;
+        while (M > 1 && (M > pg_D || penalty_gather_lds(R, M, pg_k, pg_D, pg_n) > 80 * 1024)) M /= 2;
+        c->pg_R = R;
+        c->pg_M = M;
+        c->pg_lds = penalty_gather_lds(R, M, pg_k, pg_D, pg_n);
     }
-    int rows = 0, mem = 0, pl = 0, ps = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
+    c->prep_lds = prep_lds(c->kmax, c->nmax, pg_k > 0);
+    int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const Layout& L = c->layouts[g];
@@ -290,12 +299,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         rows += p.D * p.n;
         d.mem_begin = mem;
         mem += p.D;
-        d.pl_begin = pl;
-        d.ps_begin = ps;
-        if (d.sparse) {
-            pl += ceil_div(p.n, kPlRows) * (L.n_pad / kPlSeg);
-            ps += ceil_div(p.n, c->sp_R) * ceil_div(p.D, c->sp_DM);
-        }
+        d.pg_begin = pg;
+        if (d.pgather) pg += ceil_div(p.n, c->pg_R);
         d.mt_begin = mt;
         d.mt_T = L.mt_T;
         mt += L.mt_tiles;
@@ -317,8 +322,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     }
     c->total_rows = rows;
     c->total_mem = mem;
-    c->total_pl = pl;
-    c->total_ps = ps;
+    c->total_pg = pg;
     c->total_mt = mt;
     c->total_ex = ex;
     c->total_gm[0] = gm0;
@@ -347,7 +351,7 @@ static hipError_t launch_update_any(tcol_ctx* c, int honor, int mode, int gsel, 
 // one Algorithm-1 iteration for every running graph (plain path)
 static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     HIPRET(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 15, 0, s));
@@ -357,18 +361,17 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     return hipSuccess;
 }
 
-// penalty of the fast and epilogue paths: sparse rows or the dense operand, per graph
+// penalty of the fast and epilogue paths: class-gather rows or the dense operand, per graph
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
-    if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_pl, c->total_ps, c->sp_R, c->sp_DM, c->pl_lds,
-                                     c->sp_lds, 1, s));
+    if (c->total_pg > 0)
+        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_M, c->pg_lds, 1, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
 
 // one iteration on the fast path; c[pS] holds the colours of the current weights
 static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
@@ -380,7 +383,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
 
 // one iteration on the epilogue path; c[pS] holds the colours of the current weights
 static hipError_t enqueue_step_fused(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
@@ -608,8 +611,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.st = c->dstate + g;
         d.cT = (int16_t*)(b + L.off[B_CT]);
         d.cTs = round_up(q.D, 8);
-        d.lst = (uint32_t*)(b + L.off[B_LST]);
-        d.lcnt = (int32_t*)(b + L.off[B_LCNT]);
+        d.cls_v = (int16_t*)(b + L.off[B_CLSV]);
+        d.cls_off = (int32_t*)(b + L.off[B_CLSOFF]);
         // look-up tables over the group concentration m = 0..D (host libm, FP64)
         std::vector<float> lp(q.D + 1), lb(q.D + 1);
         std::vector<double> lka(q.D + 1), lvb(q.D + 1);
@@ -709,7 +712,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     // steps 1-2 for all graphs of the context (cheap), reporting only
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, c->stream));
     HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
@@ -720,7 +723,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
 tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* gradS_dev, float* gradW_dev) {
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagLoss | kFlagForcePen, g, nullptr, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 15, 0, c->stream));
@@ -772,7 +775,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(hipEventRecord(ev[0], s));
         if (path == 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
         HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 1, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
         HIPCHK(hipEventRecord(ev[2], s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, path != 0 ? 1 : 0, s));
         HIPCHK(hipEventRecord(ev[3], s));
@@ -806,7 +809,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     if (as_only) {
         double a = 0;
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
-        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->kmax, 0, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
         for (int it = 0; it < steps; ++it) {
             HIPCHK(hipEventRecord(ev[0], s));

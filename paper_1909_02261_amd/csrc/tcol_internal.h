@@ -77,14 +77,14 @@ struct GraphDev {
     GraphState* st;
     int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
     int cTs;                  // row stride of cT (D rounded up to 8)
-    int sparse;               // fused path: penalty rows by the sparse kernels (else dense operand pass)
-    uint32_t* lst;            // [n][n_pad] sparse penalty entries of row i, by segment (see k_pen_list)
-    int32_t* lcnt;            // [n][n_pad / kPlSeg] entries per row and segment
+    int pgather;              // fast / epilogue paths: penalty rows by the class-gather kernel
+                              // (else the dense operand pass of the contraction)
+    int16_t* cls_v;           // [D][cs] vertices of each member grouped by colour, increasing j in a class
+    int32_t* cls_off;         // [D][k + 1] start of colour l's vertices in cls_v (last entry n)
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
-    int pl_begin;             // blocks of the penalty-list kernel (kPlRows rows each)
-    int ps_begin;             // blocks of the penalty-scatter kernel (row tile x member group)
+    int pg_begin;             // blocks of the class-gather penalty kernel (row tiles)
     int mt_begin;             // tiles of the group-concentration kernel
     int mt_T;                 // 64-row tiles per side
     int ex_begin;             // blocks of the S^T expansion kernel
@@ -93,11 +93,6 @@ struct GraphDev {
     int gm_tm[2], gm_tn[2];   // tiles along rows and along columns
     int gm_mpb;               // fused tiling: members per column tile
 };
-
-// rows per block of the penalty-list kernel, and columns per list segment
-// (a divisor of kPadN, so a padded row holds a whole number of segments)
-constexpr int kPlRows = 16;
-constexpr int kPlSeg = 256;
 
 // run-time flags passed to the kernels of one launch sequence
 enum : int {

@@ -33,6 +33,43 @@ __device__ inline int graph_of_row(const GraphDev* gd, int G, int w) {
     return find_graph(gd, G, w, [](const GraphDev& x) { return x.row_begin; });
 }
 
+// ---------------------------------------------------- shared device helpers --
+
+__device__ inline bool pen_active(const GraphDev& d, const GraphState* st) {
+    const float tf = (float)st->t;
+    return (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// equal 16-bit halves of a and b among those whose top bit is set in `valid`
+// (0x8000 for the low half, 0x80000000 for the high half): a half of a ^ b is zero
+// exactly when subtracting one inside that half sets its top bit while the half
+// itself does not have it set (colours are < 2^15)
+__device__ inline int equal_halves_in(uint32_t a, uint32_t b, uint32_t valid) {
+    const uint32_t x = a ^ b;
+    u16x2 h = __builtin_bit_cast(u16x2, x);
+    const u16x2 one = {1, 1};
+    const uint32_t y = __builtin_bit_cast(uint32_t, (u16x2)(h - one));
+    return __builtin_popcount(y & ~x & valid);
+}
+
+// global-address-space views: loads through them are not ordered against LDS
+// operations (a flat pointer may alias LDS, which pins every flat load behind
+// the LDS atomics and barriers before it)
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gview(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+typedef unsigned int u32x4n __attribute__((ext_vector_type(4)));
+// order this wave's LDS accesses across lanes (LDS executes a wave's operations in issue order)
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// 16-byte global load (p 16-byte aligned)
+__device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((address_space(1))) u32x4n*)p; }
+
 // ------------------------------------------------------ validation, packing --
 
 // Checks A (n x n, row-major 0/1, symmetric, zero diagonal) and writes the
@@ -105,10 +142,14 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
 }
 
 // Class sizes #V_{d,l} of member d and the vertex-major copy of its colours.
-// One block per member (all graphs).  Dynamic LDS: k ints.
+// For a graph on the class-gather penalty also the member's vertices grouped by
+// colour (stable counting sort: each class in increasing vertex order, so the
+// penalty sums run in the same order on every run).  One block per member.
+// Dynamic LDS: k counts, and with the class lists k + 1 cursors and n entries.
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
                                               int next) {
-    extern __shared__ int cnt[];
+    extern __shared__ int prep_sh[];
+    __shared__ int part[257];
     const int mem = blockIdx.x;
     if (mem >= total_mem) return;
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
@@ -117,131 +158,152 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     const int p = next ? st->pS ^ 1 : st->pS;
     const int m = mem - d.mem_begin;
     const int k = d.k, n = d.n, tid = threadIdx.x;
-    const int16_t* c = d.c[p] + (size_t)m * d.cs;
+    const int16_t* __restrict__ c = d.c[p] + (size_t)m * d.cs;
+    int16_t* __restrict__ cT = d.cT;
+    const size_t cTs = d.cTs;
+    int* cnt = prep_sh;
     for (int l = tid; l < k; l += 256) cnt[l] = 0;
     __syncthreads();
     for (int i = tid; i < n; i += 256) {
         const int16_t x = c[i];
         atomicAdd(&cnt[x], 1);
-        d.cT[(size_t)i * d.cTs + m] = x;
+        cT[(size_t)i * cTs + m] = x;
     }
     __syncthreads();
     int32_t* V = d.V[p] + (size_t)m * k;
     for (int l = tid; l < k; l += 256) V[l] = cnt[l];
-}
-
-// ------------------------------------------------------ sparse penalty rows ----
-
-__device__ inline bool pen_active(const GraphDev& d, const GraphState* st) {
-    const float tf = (float)st->t;
-    return (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
-}
-
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-// number of equal 16-bit halves of a and b (colours are < 2^15)
-__device__ inline int equal_halves(uint32_t a, uint32_t b) {
-    const uint32_t x = a ^ b;
-    // a half is zero exactly when subtracting one inside that half sets its top bit while
-    // the half itself does not have it set
-    u16x2 h = __builtin_bit_cast(u16x2, x);
-    const u16x2 one = {1, 1};
-    const uint32_t y = __builtin_bit_cast(uint32_t, (u16x2)(h - one));
-    return __builtin_popcount(y & ~x & 0x80008000u);
-}
-
-// equal 16-bit halves of a and b among those whose top bit is set in `valid`
-// (0x8000 for the low half, 0x80000000 for the high half)
-__device__ inline int equal_halves_in(uint32_t a, uint32_t b, uint32_t valid) {
-    const uint32_t x = a ^ b;
-    u16x2 h = __builtin_bit_cast(u16x2, x);
-    const u16x2 one = {1, 1};
-    const uint32_t y = __builtin_bit_cast(uint32_t, (u16x2)(h - one));
-    return __builtin_popcount(y & ~x & valid);
-}
-
-// global-address-space views: loads through them are not ordered against LDS
-// operations (a flat pointer may alias LDS, which pins every flat load behind
-// the LDS atomics and barriers before it)
-template <typename T>
-__device__ inline const __attribute__((address_space(1))) T* gview(const T* p) {
-    return (const __attribute__((address_space(1))) T*)p;
-}
-typedef unsigned int u32x4n __attribute__((ext_vector_type(4)));
-// order this wave's LDS accesses across lanes (LDS executes a wave's operations in issue order)
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-// 16-byte global load (p 16-byte aligned)
-__device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((address_space(1))) u32x4n*)p; }
-
-// Sparse penalty, for populations with few members against many colours.  The
-// penalty operand
-//   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
-// m = Mt_ij, vanishes unless i and j share a colour in some member, and with
-// one-hot S_d the product (P.S_d)[i, l] is the sum of P_ij over the j with
-// c_d(j) = l.  Two kernels compute it without the dense operand.
-//
-// k_pen_list: the non-zero entries of row i, packed as j | m << 15 | a_ij << 26,
-// per segment of kPlSeg columns: segment s of row i lists its entries in
-// increasing j at lst[i][s * kPlSeg ...] and counts them in lcnt[i][s].  A block
-// takes kPlRows rows (four per wave) and one segment; lane jj of a wave takes
-// j = j0 + jj, counts m for its four rows from the vertex-major colours (two
-// members per 32-bit compare, eight members per 16-byte load), and a ballot
-// places the entries.  Dynamic LDS: the rows' colours, then the two tables.
-__global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                  int honor_stop) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t pl_sh[];
-    const int b = blockIdx.x;
-    if (b >= total_blocks) return;
-    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.pl_begin; })];
-    GraphState* st = d.st;
-    if (honor_stop && st->stopped) return;
-    if (!d.sparse || !pen_active(d, st)) return;
-    const int n = d.n, D = d.D;
-    const size_t cTs = d.cTs, n_pad = d.n_pad;
-    const int16_t* __restrict__ cT = d.cT;
-    const uint8_t* __restrict__ A8 = d.A8;
-    uint32_t* __restrict__ lst = d.lst;
-    int32_t* __restrict__ lcnt = d.lcnt;
-    const bool diag = d.bonus_diag != 0;
-    const int nseg = (int)(n_pad / kPlSeg);
-    const int local = b - d.pl_begin;
-    const int rt = local / nseg, sg = local - rt * nseg;
-    const int i0 = rt * kPlRows, js = sg * kPlSeg;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ngrp = (D + 7) >> 3;     // 16-byte groups of eight members (cT rows are padded to 8)
-    const int rw = 4 * ngrp;           // words per staged row
-    uint32_t* ci = pl_sh;              // [kPlRows][rw]
-    float* lpen = (float*)(pl_sh + kPlRows * rw);
-    float* lbon = lpen + (D + 1);
-    const float tf = (float)st->t;
-    for (int e = tid; e < kPlRows * rw; e += 256) {
-        const int r = e / rw, q = e - r * rw;
-        const int i = i0 + r;
-        ci[e] = i < n ? gview((const uint32_t*)(cT + (size_t)i * cTs))[q] : 0u;
-    }
-    for (int m = tid; m <= D; m += 256) {
-        lpen[m] = tf * d.lut_pen[m];
-        lbon[m] = -(tf * d.lut_bon[m]);
+    if (!d.pgather) return;                         // uniform over the block
+    int* cur = prep_sh + k;                         // [k + 1]
+    int16_t* lst = (int16_t*)(cur + k + 1);         // [n]
+    int32_t* __restrict__ off = d.cls_off + (size_t)m * (k + 1);
+    int16_t* __restrict__ cv = d.cls_v + (size_t)m * d.cs;
+    // exclusive scan of the counts: runs of `per` classes per thread, then the 256 run sums
+    const int per = (k + 255) / 256;
+    const int lb = min(k, tid * per), le = min(k, lb + per);
+    int run = 0;
+    for (int l = lb; l < le; ++l) run += cnt[l];
+    part[tid] = run;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
     }
     __syncthreads();
-    const int rbase = i0 + wave * 4;
-    const uint32_t* cw0 = ci + (wave * 4) * rw;
-    int cnt[4] = {0, 0, 0, 0};
-#pragma unroll 1
-    for (int c = 0; c < kPlSeg / 64; ++c) {
-        const int j = js + c * 64 + lane;
-        if (js + c * 64 >= n) break;                 // uniform
-        const bool valid = j < n;
-        // the four rows' adjacency bytes, independent of the counts
-        uint8_t ab[4];
+    int acc = part[tid];
+    for (int l = lb; l < le; ++l) {
+        cur[l] = acc;
+        off[l] = acc;
+        acc += cnt[l];
+    }
+    if (tid == 0) off[k] = n;
+    __syncthreads();
+    // stable placement: wave 0 walks the vertices in order, 64 at a time (colours
+    // loaded eight chunks ahead); lanes of one colour find each other with one
+    // ballot per colour bit and take consecutive slots
+    if (tid < 64) {
+        const int lane = tid;
+        int nb = 0;
+        while ((1 << nb) < k) ++nb;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        for (int i8 = 0; i8 < n; i8 += 512) {
+            int xs[8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            ab[r] = (valid && rbase + r < n) ? gview(A8)[(size_t)(rbase + r) * n_pad + j] : (uint8_t)0;
-        const int16_t* cj = cT + (size_t)(valid ? j : 0) * cTs;
-        int m[4] = {0, 0, 0, 0};
+            for (int u = 0; u < 8; ++u) {
+                const int i = i8 + 64 * u + lane;
+                xs[u] = i < n ? (int)gview(c)[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i8 + 64 * u + lane;
+                if (i8 + 64 * u >= n) break;            // uniform
+                const bool v = i < n;
+                const int x = xs[u];
+                unsigned long long match = __ballot(v);
+                for (int bit = 0; bit < nb; ++bit) {
+                    const bool on = (x >> bit) & 1;
+                    const unsigned long long bb = __ballot(on);
+                    match &= on ? bb : ~bb;
+                }
+                const int base = v ? cur[x] : 0;
+                wave_sync();
+                if (v) {
+                    lst[base + __builtin_popcountll(match & lt)] = (int16_t)i;
+                    if ((match >> lane) == 1ull) cur[x] = base + __builtin_popcountll(match);   // last of its colour
+                }
+                wave_sync();
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) cv[i] = lst[i];
+}
+
+// ------------------------------------------------------ class-gather penalty ----
+
+// Penalty rows by class gather.  The penalty operand
+//   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
+// m = Mt_ij, enters the gradient as (P.S_d)[i, l], and with one-hot S_d that is the
+// sum of P_ij over the vertices j of colour l in member d: D n terms per row,
+// against D n k multiply-adds for the dense product.  A block takes R rows:
+//   1. for every j it counts m = Mt_ij for its rows from the vertex-major colours
+//      (two members per 32-bit compare, eight per 16-byte load) and keeps the
+//      code (a_ij, m) of P_ij in LDS (the values come from a table of 2 (D + 1)
+//      entries; the excluded diagonal gets m = 0, whose value is 0);
+//   2. it stages the class lists of M members at a time and sums, for every
+//      (member, colour), the table values of its vertices in increasing j, one
+//      thread per (member, colour), in FP32; the sums go to G[d][i][l], where the
+//      contraction adds A.S_d.
+// Dynamic LDS: row colours [R][cTs/2] u32, codes [n_pad][R] u16, lists [M][cs]
+// i16, offsets [M][k+1] i32, table [2 (D+1)] f32 (the first three 16-byte aligned).
+template <int R>
+__global__ __launch_bounds__(256) void k_pen_gather(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                    int honor_stop, int M) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t pg_sh[];
+    const int b = blockIdx.x;
+    if (b >= total_blocks) return;
+    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.pg_begin; })];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    if (!d.pgather || !pen_active(d, st)) return;
+    const int n = d.n, k = d.k, D = d.D, cs = d.cs;
+    const int n_pad = d.n_pad;
+    const size_t cTs = d.cTs;
+    const int16_t* __restrict__ cT = d.cT;
+    const uint8_t* __restrict__ A8 = d.A8;
+    const int16_t* __restrict__ clsv = d.cls_v;
+    const int32_t* __restrict__ clsoff = d.cls_off;
+    float* __restrict__ Gg = d.G;
+    const bool diag = d.bonus_diag != 0;
+    const int i0 = (b - d.pg_begin) * R;
+    const int rows = min(R, n - i0);
+    const int tid = threadIdx.x;
+    const int ngrp = (D + 7) >> 3;
+    const int rw = 4 * ngrp;                                   // u32 words per staged row
+    uint32_t* ci = (uint32_t*)pg_sh;                           // [R][rw], 16-byte rows
+    uint16_t* codes = (uint16_t*)(ci + R * rw);                // [n_pad][R]: a vertex's R codes together
+    int16_t* lists = (int16_t*)(codes + (size_t)R * n_pad);    // [M][cs]
+    int* offs = (int*)(lists + (size_t)M * cs);                // [M][k + 1]
+    float* lut = (float*)(offs + (size_t)M * (k + 1));         // [2 (D + 1)]
+    const float tf = (float)st->t;
+    for (int e = tid; e < R * rw; e += 256) {
+        const int r = e / rw, q = e - r * rw;
+        ci[e] = r < rows ? gview((const uint32_t*)(cT + (size_t)(i0 + r) * cTs))[q] : 0u;
+    }
+    for (int m = tid; m <= D; m += 256) {
+        lut[m] = -(tf * d.lut_bon[m]);
+        lut[D + 1 + m] = tf * d.lut_pen[m];
+    }
+    __syncthreads();
+    // 1. codes of P_ij for the block's rows
+    for (int j = tid; j < n; j += 256) {
+        const int16_t* cj = cT + (size_t)j * cTs;
+        int m[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) m[r] = 0;
 #pragma unroll 1
         for (int g0 = 0; g0 < ngrp; g0 += 8) {
             u32x4n w[8];
@@ -250,11 +312,11 @@ __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ g
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int g = g0 + u;
-                if (g >= ngrp) break;                // uniform
+                if (g >= ngrp) break;                          // uniform
                 const uint32_t wv[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint4 c4 = *(const uint4*)(cw0 + r * rw + 4 * g);
+                for (int r = 0; r < R; ++r) {
+                    const uint4 c4 = *(const uint4*)(ci + r * rw + 4 * g);
                     const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
                     for (int h = 0; h < 4; ++h) {
@@ -265,120 +327,66 @@ __global__ __launch_bounds__(256) void k_pen_list(const GraphDev* __restrict__ g
                 }
             }
         }
+        uint16_t cd[R];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = rbase + r;
-            if (i >= n) break;                       // uniform
-            const bool edge = ab[r] != 0;
-            const int mm = m[r];
-            float P = 0.0f;
-            if (valid && mm > 0) P = edge ? lpen[mm] : ((i != j || diag) ? lbon[mm] : 0.0f);
-            const bool hit = P != 0.0f;
-            const unsigned long long bal = __ballot(hit);
-            if (hit) {
-                const int pos = cnt[r] + __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-                lst[(size_t)i * n_pad + js + pos] = (uint32_t)j | ((uint32_t)mm << 15) | (edge ? (1u << 26) : 0u);
+        for (int r = 0; r < R; ++r) {
+            int code = 0;
+            if (r < rows) {
+                const int i = i0 + r;
+                const bool edge = gview(A8)[(size_t)i * n_pad + j] != 0;
+                int mm = m[r];
+                if (j == i && !diag) mm = 0;                   // a_ii = 0: excluded from the bonus
+                code = edge ? D + 1 + mm : mm;
             }
-            cnt[r] += __builtin_popcountll(bal);
+            cd[r] = (uint16_t)code;
         }
-    }
-    if (lane == 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (rbase + r < n) lcnt[(size_t)(rbase + r) * nseg + sg] = cnt[r];
-    }
-}
-
-// k_pen_scatter: histograms (P.S_d)[i, :] of a tile of R rows for DM members
-// (DM in {1, 2, 4, 8}, so the members of a tile sit in one 16-byte group of a cT
-// row) in LDS, written to G[d][i][:], where the contraction adds A.S_d.  Each row
-// belongs to one wave, which walks its entries segment by segment in increasing
-// j, 64 at a time (a lane finds its segment from the running counts), so the FP32
-// sums run in the same order on every run.  Dynamic LDS: DM*R*k floats of
-// histograms, 2(D+1) floats of tables, 4 (n_pad/kPlSeg + 1) ints of counts.
-__global__ __launch_bounds__(256) void k_pen_scatter(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                     int honor_stop, int R, int DM) {
-    extern __shared__ float sh[];
-    const int b = blockIdx.x;
-    if (b >= total_blocks) return;
-    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
-    GraphState* st = d.st;
-    if (honor_stop && st->stopped) return;
-    if (!d.sparse || !pen_active(d, st)) return;
-    const int n = d.n, k = d.k, D = d.D;
-    const size_t cTs = d.cTs, n_pad = d.n_pad;
-    const int nseg = (int)(n_pad / kPlSeg);
-    const int16_t* __restrict__ cT = d.cT;
-    const uint32_t* __restrict__ lst = d.lst;
-    const int32_t* __restrict__ lcnt = d.lcnt;
-    float* __restrict__ Gg = d.G;
-    const int ndg = ceil_div(D, DM);
-    const int local = b - d.ps_begin;
-    const int rt = local / ndg, dg = local - rt * ndg;
-    const int i0 = rt * R, d0 = dg * DM;
-    const int nmem = min(DM, D - d0);
-    const int rows = min(R, n - i0);
-    const int sub = d0 & 7;                  // first member's slot in its 16-byte group
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int slab = R * k;                  // floats per member
-    float* hist = sh;
-    float* lpen = sh + DM * slab;
-    float* lbon = lpen + (D + 1);
-    int* pref = (int*)(lbon + (D + 1)) + wave * (nseg + 1);   // this wave's running counts
-    const float tf = (float)st->t;
-    for (int e = tid; e < DM * slab; e += 256) hist[e] = 0.0f;
-    for (int m = tid; m <= D; m += 256) {
-        lpen[m] = tf * d.lut_pen[m];
-        lbon[m] = -(tf * d.lut_bon[m]);
+        for (int r = 0; r < R; ++r) codes[(size_t)j * R + r] = cd[r];
     }
     __syncthreads();
-    for (int ri = wave; ri < rows; ri += 4) {
-        const int i = i0 + ri;
-        // running counts of the row's segments (lane 0 sums; at most 128 segments)
-        for (int sgi = lane; sgi < nseg; sgi += 64) pref[sgi + 1] = gview(lcnt)[(size_t)i * nseg + sgi];
-        wave_sync();
-        if (lane == 0) {
-            int acc = 0;
-            pref[0] = 0;
-            for (int sgi = 0; sgi < nseg; ++sgi) {
-                acc += pref[sgi + 1];
-                pref[sgi + 1] = acc;
-            }
-        }
-        wave_sync();
-        const int total = pref[nseg];
-        const __attribute__((address_space(1))) uint32_t* row = gview(lst + (size_t)i * n_pad);
-        float* h = hist + ri * k;
-        int s0 = 0;                          // segment of entry e0 (uniform)
-        for (int e0 = 0; e0 < total; e0 += 64) {
-            while (pref[s0 + 1] <= e0) ++s0;
-            const int e = e0 + lane;
-            if (e < total) {
-                int sgi = s0;
-                while (pref[sgi + 1] <= e) ++sgi;
-                const uint32_t v = row[sgi * kPlSeg + (e - pref[sgi])];
-                const int j = (int)(v & 0x7FFFu), m = (int)((v >> 15) & 0x7FFu);
-                const float P = (v >> 26) & 1u ? lpen[m] : lbon[m];
-                const u32x4n cc = gload16(cT + (size_t)j * cTs + (d0 - sub));
-                const uint32_t cw[4] = {cc.x, cc.y, cc.z, cc.w};
+    // 2. class sums, M members at a time
+    for (int dg = 0; dg < D; dg += M) {
+        const int mc = min(M, D - dg);
+        // the lists of members dg .. dg+mc-1 are contiguous (rows of cs entries, 16-byte multiples)
+        for (int e = tid; e < mc * cs / 8; e += 256)
+            *(u32x4n*)(lists + 8 * e) = gload16(clsv + (size_t)dg * cs + 8 * e);
+        for (int e = tid; e < mc * (k + 1); e += 256) offs[e] = gview(clsoff)[(size_t)dg * (k + 1) + e];
+        __syncthreads();
+        for (int e = tid; e < mc * k; e += 256) {
+            const int dm = e / k, l = e - dm * k;
+            const int beg = offs[dm * (k + 1) + l], end = offs[dm * (k + 1) + l + 1];
+            const int16_t* lv = lists + (size_t)dm * cs;
+            float acc[R];
 #pragma unroll
-                for (int dm = 0; dm < 8; ++dm) {
-                    if (dm < nmem) {
-                        const int s = sub + dm;
-                        const int col = (int)((cw[s >> 1] >> (16 * (s & 1))) & 0xFFFFu);
-                        atomicAdd(&h[dm * slab + col], P);
-                    }
+            for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+            for (int q = beg; q < end; ++q) {
+                const int j = lv[q];
+                uint16_t cd[R];
+                if constexpr (R == 8) {
+                    const u32x4n v = *(const u32x4n*)(codes + (size_t)j * 8);
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) cd[r] = (uint16_t)(w[r >> 1] >> (16 * (r & 1)));
+                } else if constexpr (R == 4) {
+                    const uint2 v = *(const uint2*)(codes + (size_t)j * 4);
+                    cd[0] = (uint16_t)v.x; cd[1] = (uint16_t)(v.x >> 16);
+                    cd[2] = (uint16_t)v.y; cd[3] = (uint16_t)(v.y >> 16);
+                } else if constexpr (R == 2) {
+                    const uint32_t v = *(const uint32_t*)(codes + (size_t)j * 2);
+                    cd[0] = (uint16_t)v; cd[1] = (uint16_t)(v >> 16);
+                } else {
+                    cd[0] = codes[j];
                 }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (cd[r]) acc[r] += lut[cd[r]];
             }
+            float* out = Gg + ((size_t)(dg + dm) * n + i0) * k + l;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < rows) out[(size_t)r * k] = acc[r];
         }
-        wave_sync();     // pref is reused by the wave's next row
-    }
-    __syncthreads();
-    // member dm's rows i0 .. i0+rows-1 are contiguous in G
-    for (int dm = 0; dm < nmem; ++dm) {
-        float* out = Gg + ((size_t)(d0 + dm) * n + i0) * k;
-        const float* src = hist + dm * slab;
-        for (int e = tid; e < rows * k; e += 256) out[e] = src[e];
+        __syncthreads();
     }
 }
 
@@ -394,7 +402,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     // the bf16 copy of S feeds only the dense penalty pass of FP8 / FP4 graphs
-    const bool want_sp2 = prec_split(d.precision) && (!gate || !d.sparse);
+    const bool want_sp2 = prec_split(d.precision) && (!gate || !d.pgather);
     const int cgs = d.n_pad / 16;
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
     const int row = (int)(item / cgs);
@@ -485,7 +493,7 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
     if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
-    if ((flags & kFlagGate) && d.sparse) return;
+    if ((flags & kFlagGate) && d.pgather) return;
     const int p = st->pS;
     // upper-triangle tile (ti <= tj)
     int u = b - d.mt_begin, ti = 0, T = d.mt_T;
@@ -904,39 +912,50 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
     return hipSuccess;
 }
 
-hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next, hipStream_t s) {
+size_t prep_lds(int kmax, int nmax, int gather) {
+    size_t b = sizeof(int) * (size_t)kmax;
+    if (gather) b += sizeof(int) * (size_t)(kmax + 1) + sizeof(int16_t) * (size_t)nmax;
+    return (b + 15) / 16 * 16;
+}
+
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s) {
     if (total_mem <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), sizeof(int) * (size_t)kmax, s, gd, G, total_mem,
-                       honor_stop, next);
+    if (lds > 150 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), lds, s, gd, G, total_mem, honor_stop, next);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t penalty_sparse_prepare() {
-    const hipError_t e =
-        hipFuncSetAttribute((const void*)k_pen_list, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_pen_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+hipError_t penalty_gather_prepare() {
+    const void* fns[] = {(const void*)k_pen_gather<1>, (const void*)k_pen_gather<2>, (const void*)k_pen_gather<4>,
+                         (const void*)k_pen_gather<8>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    // k_prep also holds 1 KB of static LDS
+    return hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
 
-size_t penalty_list_lds(int dmax) {
-    return sizeof(uint32_t) * (size_t)kPlRows * 4 * ((dmax + 7) / 8) + sizeof(float) * 2 * (size_t)(dmax + 1);
+size_t penalty_gather_lds(int R, int M, int kmax, int dmax, int nmax) {
+    const size_t n_pad = (size_t)round_up(nmax, kPadN), cs = (size_t)round_up(nmax, 64);
+    const size_t cts = (size_t)round_up(dmax, 8);
+    const size_t b = 2 * (size_t)R * cts + 2 * (size_t)R * n_pad + 2 * (size_t)M * cs +
+                     4 * (size_t)M * (kmax + 1) + 4 * 2 * (size_t)(dmax + 1);
+    return (b + 15) / 16 * 16;
 }
 
-size_t penalty_scatter_lds(int R, int DM, int kmax, int dmax, int nmax) {
-    const int nseg = round_up(nmax, kPadN) / kPlSeg;
-    return sizeof(float) * ((size_t)DM * R * kmax + 2 * (size_t)(dmax + 1)) + sizeof(int) * 4 * (size_t)(nseg + 1);
-}
-
-hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int list_blocks, int scatter_blocks, int R, int DM,
-                                 size_t list_lds, size_t scatter_lds, int honor_stop, hipStream_t s) {
-    if (list_blocks <= 0 || scatter_blocks <= 0) return hipSuccess;
-    if (R < 1 || (DM != 1 && DM != 2 && DM != 4 && DM != 8) || list_lds > 160 * 1024 || scatter_lds > 160 * 1024)
-        return hipErrorInvalidValue;
-    k_pen_list<<<list_blocks, 256, list_lds, s>>>(gd, G, list_blocks, honor_stop);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_pen_scatter<<<scatter_blocks, 256, scatter_lds, s>>>(gd, G, scatter_blocks, honor_stop, R, DM);
+hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int M, size_t lds, int honor_stop,
+                                 hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (M < 1 || lds > 160 * 1024) return hipErrorInvalidValue;
+    switch (R) {
+        case 1: k_pen_gather<1><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
+        case 2: k_pen_gather<2><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
+        case 4: k_pen_gather<4><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
+        case 8: k_pen_gather<8><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

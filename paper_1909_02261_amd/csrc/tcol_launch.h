@@ -8,14 +8,15 @@ namespace tcol {
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
                              hipStream_t s);
 hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s);
-hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, int kmax, int honor_stop, int next, hipStream_t s);
-hipError_t penalty_sparse_prepare();
-// sparse penalty: per-row, per-segment entry lists, then histograms of row tiles of R rows x DM
-// members (DM in {1, 2, 4, 8}); dynamic LDS of the two kernels from the helpers below
-size_t penalty_list_lds(int dmax);
-size_t penalty_scatter_lds(int R, int DM, int kmax, int dmax, int nmax);
-hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int list_blocks, int scatter_blocks, int R, int DM,
-                                 size_t list_lds, size_t scatter_lds, int honor_stop, hipStream_t s);
+// class sizes and vertex-major colours; with gather != 0 also the class lists of graphs on the
+// class-gather penalty (dynamic LDS from prep_lds)
+size_t prep_lds(int kmax, int nmax, int gather);
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s);
+hipError_t penalty_gather_prepare();
+// class-gather penalty rows: blocks of R rows (R in {1, 2, 4, 8}), member lists staged M at a time
+size_t penalty_gather_lds(int R, int M, int kmax, int dmax, int nmax);
+hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int M, size_t lds, int honor_stop,
+                                 hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
@@ -36,7 +37,7 @@ hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long
 // MFMA contraction G = A.S (+ P.S) with the conflict gather.
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
 //   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
-//           bit 3 = dense penalty operand even for graphs on the sparse penalty rows
+//           bit 3 = dense penalty operand even for graphs on the class-gather penalty
 struct GemmShape {
     int prec, bm, ntw, mode;
 };

@@ -150,8 +150,8 @@ def run_resynced(case, steps, tol, check_every=1, t0=0, W=None, **opts):
     return worst
 
 
-PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_sparse": dict(fused=1, penalty=2),
-         "epi_dense": dict(fused=2, penalty=1), "epi_sparse": dict(fused=2, penalty=2)}
+PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_gather": dict(fused=1, penalty=2),
+         "epi_dense": dict(fused=2, penalty=1), "epi_gather": dict(fused=2, penalty=2)}
 
 
 @pytest.mark.parametrize("path", list(PATHS))
@@ -167,7 +167,7 @@ def test_fused_large_k_resynced(path, prec):
     ECP so every loss term is active, a ragged n and several tiles."""
     case = GraphCase(f"ecp_n600_k120_D8_p{prec}", ECP, 600, 120, 8, prec, "gnp", 0.5, graph_seed=31, rho=10.0,
                      lam=2e-2, mu=5e-3, nu=0.05)
-    tol = TOL if (prec == FP32 or path.endswith("sparse")) else 1e-2
+    tol = TOL if (prec == FP32 or path.endswith("gather")) else 1e-2
     worst = run_resynced(case, 8, tol, t0=3, **PATHS[path])
     print(f"{case.name} {path}: worst W error vs FP64 {worst:.2e}")
 
@@ -175,7 +175,7 @@ def test_fused_large_k_resynced(path, prec):
 @pytest.mark.parametrize("path", [p for p in PATHS if p != "plain"])
 def test_degenerate_population(path):
     """Every vertex in one colour in every member: Mt is all D, the penalty operand is dense
-    and every row of the sparse kernel visits all n vertices."""
+    and the class-gather kernel sees one class of n vertices per member."""
     n, k, D = 300, 100, 8
     case = GraphCase("degenerate", KCOL, n, k, D, FP32, "gnp", 0.5, graph_seed=33, lam=1e-2, mu=1e-3)
     W = case.weights()
@@ -189,7 +189,7 @@ def test_degenerate_population(path):
 def test_small_resynced_low_precision(prec, path):
     case = GraphCase("kcol90", KCOL, 90, 9, 6, prec, "gnp", 0.5, graph_seed=12, rho=10.0, lam=1e-2, mu=3e-3)
     # bf16 penalty operand: errors against FP64 are reported; the bound only catches wrong arithmetic
-    worst = run_resynced(case, 30, TOL if path.endswith("sparse") else 1e-2, **PATHS[path])
+    worst = run_resynced(case, 30, TOL if path.endswith("gather") else 1e-2, **PATHS[path])
     print(f"prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
