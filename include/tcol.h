@@ -198,9 +198,11 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * 3 group concentration + penalty operand, 4 contraction A.S (+ penalty pass)
  * with fitness gather and, on the fused path, the update epilogue,
  * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
- * 7 counter advance.  When as_only is non-zero it then also times `steps`
- * launches of the contraction restricted to A.S with the gather (W unchanged)
- * into ms[8]; otherwise ms[8] = 0.  Synchronises the stream.
+ * 7 counter advance.  Phase 4 is timed separately as `steps` contraction
+ * launches back to back on the operands of the last iteration (one event pair,
+ * so launch gaps do not count).  When as_only is non-zero it then also times
+ * `steps` back-to-back launches of the contraction restricted to A.S with the
+ * gather (W unchanged) into ms[8]; otherwise ms[8] = 0.  Synchronises the stream.
  * Errors: TCOL_EINVAL, TCOL_EHIP. */
 #define TCOL_NPHASES 9
 tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *ms);

@@ -51,6 +51,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libtcol.so not found at {path}; build it with "
                           f"`python -m paper_1909_02261_amd.build` (hipcc, gfx950)")
+    # torch first: libtcol must bind to the HIP runtime that torch's tensors and streams live in
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64

@@ -889,6 +889,8 @@ __global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_on
         st->steps_done = 0; st->legal_d = -1;
     } else if (op == 3) {     // the caller's buffer holds the weights again
         st->pW = 0;
+    } else if (op == 4) {     // clear the conflict accumulators (after timing repeated contractions)
+        for (int m = 0; m < gd[g].D; ++m) gd[g].f2[m] = 0;
     }
 }
 
