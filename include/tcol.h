@@ -105,11 +105,10 @@ typedef struct {
                                pairs are (64,2) (64,4) (128,4) (128,8) (64,9) (128,9) (256,4) */
     int32_t penalty;        /* fast and epilogue paths, penalty term (A o Mt^(alpha-1) and
                                (J-A) o Mt^(beta-1) times S, eq. 17): 0 = choose (default),
-                               1 = dense operand pass on MFMA, 2 = sparse: per-row lists of the
-                               non-zero entries of the operand and FP32 histograms over the
-                               members' colours (the operand is non-zero only where two vertices
-                               share a colour in some member, so it is sparse when D is small
-                               against k) */
+                               1 = dense operand pass on MFMA, 2 = class gather in FP32: with
+                               one-hot S_d, (P.S_d)[i, l] is the sum of P_ij over the vertices of
+                               colour l in member d (D n terms per row instead of D n k
+                               multiply-adds); 0 currently takes 1 */
 } tcol_options;
 
 typedef struct tcol_ctx tcol_ctx;
@@ -209,6 +208,52 @@ tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *m
 
 /* Release the context (and the workspace it allocated).  NULL is ignored. */
 void tcol_destroy(tcol_ctx *ctx);
+
+/* Initial weights W ~ N(0, sigma0^2) (Section 3.2: sigma0 is their standard
+ * deviation, 0.01 in the parameter table), written to W_dev[0 .. count) on the
+ * device: Philox4x32-10 with key = seed and counter block b = (b mod 2^32,
+ * b / 2^32, 1, 0) gives two 53-bit uniforms u1 = ((w0 >> 5) 2^26 + (w1 >> 6) + 1)
+ * 2^-53 and u2 (from w2, w3), and Box-Muller in FP64 the normals
+ * sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2) for entries 2b and
+ * 2b + 1, times sigma0, rounded to fp32.  Asynchronous on `stream`.
+ * Errors: TCOL_EINVAL (NULL W_dev, count < 0, sigma0 not finite), TCOL_EHIP. */
+tcol_status tcol_init_weights(float *W_dev, int64_t count, uint64_t seed, double sigma0, void *stream);
+
+/* Colour-count descent (Sections 1 and 3: the GCP, and likewise the ECP, is
+ * approached by solving k-COL (or k-ECP) for decreasing k, each legal k being
+ * an upper bound).  Starting from k = k_first, each k gets up to `attempts`
+ * runs of at most max_steps iterations, attempt r from fresh weights drawn by
+ * tcol_init_weights with seed + 1000003 k + r; a run stops at its first legal
+ * member.  The descent moves to k - 1 after a legal colouring and ends at the
+ * first k none of whose attempts finds one, or below k_min. */
+typedef struct {
+    int32_t k_first;        /* first number of colours tried (1..4096) */
+    int32_t k_min;          /* smallest k tried (1..k_first) */
+    int32_t max_steps;      /* iteration budget of one attempt (>= 1) */
+    int32_t attempts;       /* runs per k (>= 1) */
+    uint64_t seed;          /* base seed of the initial weights */
+    double sigma0;          /* standard deviation of the initial weights (> 0) */
+} tcol_descent_options;
+
+typedef struct {
+    int32_t k_best;         /* smallest k with a legal colouring found, or -1 */
+    int32_t k_tried;        /* number of k values tried */
+    int32_t attempt_best;   /* attempt that found the k_best colouring */
+    int32_t steps_best;     /* iterations that attempt took (the legal one included) */
+    int64_t steps_total;    /* iterations over all attempts */
+} tcol_descent_result;
+
+/* Run the descent on one graph.  A_dev: n x n row-major 0/1 (as tcol_init);
+ * base: the graph's parameters (k and stop_on_legal are overridden; D,
+ * problem, precision and the method's parameters are kept); opt: as above.
+ * On return *result (host) holds the outcome and colors_dev (device, n int16,
+ * may be NULL) the legal colouring with k_best colours when one was found.
+ * The call allocates the weights and the workspace of each run on the device
+ * and frees them before it returns; it synchronises `stream`.
+ * Errors: TCOL_EINVAL, TCOL_ESHAPE, TCOL_EGRAPH, TCOL_ENOMEM, TCOL_EHIP and
+ * TCOL_ENONFINITE (as tcol_init / tcol_step). */
+tcol_status tcol_descent(const uint8_t *A_dev, const tcol_graph_params *base, const tcol_descent_options *opt,
+                         tcol_descent_result *result, int16_t *colors_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,8 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, ECP, FP4, FP8, FP32, KCOL, TcolError
 
-__all__ = ["Params", "Solver", "TensColLoss", "KCOL", "ECP", "FP32", "BF16", "FP8", "FP4", "TcolError"]
+__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "KCOL", "ECP", "FP32", "BF16", "FP8",
+           "FP4", "TcolError"]
 
 
 @dataclass
@@ -181,6 +182,38 @@ class Solver:
         bm, ntw = ctypes.c_int32(0), ctypes.c_int32(0)
         _lib.check(self._lib.tcol_autotune(self._ctx, ctypes.byref(bm), ctypes.byref(ntw)), "tcol_autotune")
         return bm.value, ntw.value
+
+
+def init_weights(W, seed: int, sigma0: float = 0.01, stream=None) -> None:
+    """Fill the contiguous fp32 device tensor W with N(0, sigma0^2) draws (tcol_init_weights)."""
+    torch = _torch()
+    if W.dtype != torch.float32 or not W.is_contiguous() or not W.is_cuda:
+        raise ValueError("W must be a contiguous float32 device tensor")
+    lib = _lib.load()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _lib.check(lib.tcol_init_weights(_ptr(W), W.numel(), int(seed) & (2**64 - 1), float(sigma0),
+                                     ctypes.c_void_p(st.cuda_stream)), "tcol_init_weights")
+
+
+def descent(A, params: Params, k_first: int, k_min: int = 1, max_steps: int = 10000, attempts: int = 1,
+            seed: int = 0, sigma0: float = 0.01, stream=None):
+    """Colour-count descent on graph A (uint8 n x n device tensor) with the method's parameters
+    `params` (k is overridden).  Returns (result dict, int16 device tensor of the legal colouring
+    with result["k_best"] colours, or None when none was found)."""
+    torch = _torch()
+    if A.dtype != torch.uint8 or not A.is_contiguous() or not A.is_cuda:
+        raise ValueError("A must be a contiguous uint8 device tensor")
+    lib = _lib.load()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    colors = torch.zeros(params.n, dtype=torch.int16, device=A.device)
+    opt = _lib.DescentOptions(int(k_first), int(k_min), int(max_steps), int(attempts), int(seed) & (2**64 - 1),
+                              float(sigma0))
+    res = _lib.DescentResult()
+    cp = params.c_struct()
+    _lib.check(lib.tcol_descent(_ptr(A), ctypes.byref(cp), ctypes.byref(opt), ctypes.byref(res), _ptr(colors),
+                                ctypes.c_void_p(st.cuda_stream)), "tcol_descent")
+    out = {f: getattr(res, f) for f, _ in _lib.DescentResult._fields_}
+    return out, (colors if res.k_best >= 0 else None)
 
 
 class TensColLoss:

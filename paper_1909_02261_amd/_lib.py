@@ -28,6 +28,16 @@ class Options(ctypes.Structure):
                 ("tile_bm", ctypes.c_int32), ("tile_ntw", ctypes.c_int32), ("penalty", ctypes.c_int32)]
 
 
+class DescentOptions(ctypes.Structure):
+    _fields_ = [("k_first", ctypes.c_int32), ("k_min", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("attempts", ctypes.c_int32), ("seed", ctypes.c_uint64), ("sigma0", ctypes.c_double)]
+
+
+class DescentResult(ctypes.Structure):
+    _fields_ = [("k_best", ctypes.c_int32), ("k_tried", ctypes.c_int32), ("attempt_best", ctypes.c_int32),
+                ("steps_best", ctypes.c_int32), ("steps_total", ctypes.c_int64)]
+
+
 class TcolError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -36,7 +46,8 @@ class TcolError(RuntimeError):
 
 EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_options",
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
-           "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy"]
+           "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
+           "tcol_init_weights", "tcol_descent"]
 NPHASES = 9
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only"]
 
@@ -75,6 +86,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_reset.argtypes = [P]
     lib.tcol_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tcol_profile.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_float)]
+    lib.tcol_init_weights.argtypes = [P, i64, ctypes.c_uint64, ctypes.c_double, P]
+    lib.tcol_descent.argtypes = [P, ctypes.POINTER(GraphParams), ctypes.POINTER(DescentOptions),
+                                 ctypes.POINTER(DescentResult), P, P]
     lib.tcol_destroy.argtypes = [P]
     lib.tcol_destroy.restype = None
     for name in EXPORTS:

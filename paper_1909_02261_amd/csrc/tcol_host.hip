@@ -942,3 +942,75 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- descent driver -
+
+tcol_status tcol_init_weights(float* W_dev, int64_t count, uint64_t seed, double sigma0, void* stream) {
+    if (!W_dev || count < 0 || !isfinite(sigma0)) return TCOL_EINVAL;
+    HIPCHK(launch_init_weights(W_dev, (long long)count, (unsigned long long)seed, sigma0, (hipStream_t)stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_descent(const uint8_t* A_dev, const tcol_graph_params* base, const tcol_descent_options* opt,
+                         tcol_descent_result* result, int16_t* colors_dev, void* stream) {
+    if (!A_dev || !base || !opt || !result) return TCOL_EINVAL;
+    if (opt->k_first < 1 || opt->k_first > kMaxK || opt->k_min < 1 || opt->k_min > opt->k_first ||
+        opt->max_steps < 1 || opt->attempts < 1 || !(opt->sigma0 > 0.0) || !isfinite(opt->sigma0))
+        return TCOL_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    result->k_best = -1;
+    result->k_tried = 0;
+    result->attempt_best = -1;
+    result->steps_best = 0;
+    result->steps_total = 0;
+    int16_t* found = nullptr;          // legal colouring of the current attempt
+    if (hipMalloc((void**)&found, sizeof(int16_t) * (size_t)std::max(1, base->n)) != hipSuccess) return TCOL_ENOMEM;
+    tcol_status rc = TCOL_OK;
+    for (int k = opt->k_first; k >= opt->k_min && rc == TCOL_OK; --k) {
+        tcol_graph_params p = *base;
+        p.k = k;
+        p.stop_on_legal = 1;
+        rc = check_params(p);
+        if (rc != TCOL_OK) break;
+        ++result->k_tried;
+        bool legal = false;
+        for (int r = 0; r < opt->attempts && !legal && rc == TCOL_OK; ++r) {
+            const size_t count = (size_t)p.D * p.n * p.k;
+            float* W = nullptr;
+            if (hipMalloc((void**)&W, sizeof(float) * count) != hipSuccess) {
+                rc = TCOL_ENOMEM;
+                break;
+            }
+            const uint64_t seed = opt->seed + 1000003ull * (uint64_t)k + (uint64_t)r;
+            rc = tcol_init_weights(W, (int64_t)count, seed, opt->sigma0, s);
+            tcol_ctx* c = nullptr;
+            if (rc == TCOL_OK) {
+                const uint8_t* As[1] = {A_dev};
+                float* Ws[1] = {W};
+                rc = tcol_init(&c, 1, &p, As, Ws, nullptr, 0, s);
+            }
+            if (rc == TCOL_OK) {
+                int32_t done = 0, legal_d = -1;
+                int16_t* outs[1] = {found};
+                rc = tcol_step(c, opt->max_steps, &done, &legal_d, outs);
+                result->steps_total += done;
+                if (rc == TCOL_OK && legal_d >= 0) {
+                    legal = true;
+                    result->k_best = k;
+                    result->attempt_best = r;
+                    // the iteration that found the legal member performs no update
+                    result->steps_best = done + 1;
+                    if (colors_dev &&
+                        hipMemcpyAsync(colors_dev, found, sizeof(int16_t) * p.n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                        rc = TCOL_EHIP;
+                }
+            }
+            tcol_destroy(c);
+            if (hipStreamSynchronize(s) != hipSuccess && rc == TCOL_OK) rc = TCOL_EHIP;
+            hipFree(W);
+        }
+        if (!legal) break;
+    }
+    hipFree(found);
+    return rc;
+}

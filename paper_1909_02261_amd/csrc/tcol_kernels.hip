@@ -894,9 +894,63 @@ __global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_on
     }
 }
 
+// ------------------------------------------------------------ initial weights -
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), from its published round
+// function and constants: ten rounds of two 32x32->64 multiplies, with the key
+// bumped by the Weyl constants between rounds.
+__device__ inline void philox4x32_10(uint32_t (&x)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)x[0] * 0xD2511F53ull;
+        const uint64_t p1 = (uint64_t)x[2] * 0xCD9E8D57ull;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x[3] ^ k1;
+        x[0] = n0;
+        x[1] = (uint32_t)p1;
+        x[2] = n2;
+        x[3] = (uint32_t)p0;
+    }
+}
+
+// two 32-bit words to a uniform in (0, 1] with 53 bits
+__device__ inline double uniform53(uint32_t hi, uint32_t lo) {
+    return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6) + 1.0) * (1.0 / 9007199254740992.0);
+}
+
+// W[e] ~ N(0, sigma0^2), e < count: counter block b = (b mod 2^32, b / 2^32, stream 1, 0)
+// under key = seed gives two uniforms (u1, u2) and, by Box-Muller in FP64, the normals
+// r cos(2 pi u2) and r sin(2 pi u2), r = sqrt(-2 ln u1), for entries 2b and 2b+1,
+// scaled by sigma0 and rounded to fp32.  One thread per block b.
+__global__ __launch_bounds__(256) void k_init_weights(float* __restrict__ W, long long count, uint32_t key0,
+                                                      uint32_t key1, double sigma0) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * b >= count) return;
+    uint32_t x[4] = {(uint32_t)b, (uint32_t)((unsigned long long)b >> 32), 1u, 0u};
+    philox4x32_10(x, key0, key1);
+    const double u1 = uniform53(x[0], x[1]), u2 = uniform53(x[2], x[3]);
+    const double r = sqrt(-2.0 * log(u1));
+    const double th = 6.283185307179586 * u2;
+    W[2 * b] = (float)(r * cos(th) * sigma0);
+    if (2 * b + 1 < count) W[2 * b + 1] = (float)(r * sin(th) * sigma0);
+}
+
 // ------------------------------------------------------------- launchers -----
 
 #define TCOL_LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_init_weights(float* W, long long count, unsigned long long seed, double sigma0, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const long long blocks = ((count + 1) / 2 + 255) / 256;
+    hipLaunchKernelGGL(k_init_weights, dim3((unsigned)blocks), dim3(256), 0, s, W, count, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), sigma0);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
 
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
                              hipStream_t s) {
