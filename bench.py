@@ -105,6 +105,50 @@ def cpu_baseline(case, A, W0, budget_s: float):
                       f"oracle, {el:.1f} s)"}
 
 
+def run_descent(args, torch, pk):
+    """Colour-count descent on the planted n = 1000 graph (28 hidden colours, D = 128): k from
+    --descent-k-first down while a legal colouring is found within --descent-steps iterations."""
+    prec = args.precision or "fp4"
+    case = workload("c3", prec)
+    print(f"[bench] descent on {case.name} precision {prec}", file=sys.stderr, flush=True)
+    A = case.adjacency()
+    At = torch.from_numpy(A).cuda()
+    prm = pk.Params.from_dict(case.params())
+    pk.descent(At, prm, args.descent_k_first, args.descent_k_first, max_steps=5, attempts=1, seed=99)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, col = pk.descent(At, prm, args.descent_k_first, 1, max_steps=args.descent_steps, attempts=1, seed=0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    legal = None
+    if col is not None:
+        import oracle
+        legal = int(oracle.fcolor(A, col.cpu().numpy()[None, :])[0]) == 0
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        p = oracle.Params.from_dict(dict(case.params(), k=args.descent_k_first))
+        W = tcolgen.weights0(case.D, case.n, args.descent_k_first, 1000003 * args.descent_k_first)
+        t1 = time.perf_counter()
+        steps = 0
+        t = 0
+        while time.perf_counter() - t1 < args.cpu_seconds and steps < 200:
+            r = oracle.iteration(p, t, A, W, want_grads=False)
+            W, t = r.W, r.t
+            steps += 1
+        e1 = time.perf_counter() - t1
+        cpu = {"value": case.D * steps / e1, "unit": "population-iterations/s", "cores": 1, "kind": "oracle",
+               "sample": f"{steps} iterations at k = {args.descent_k_first} from the descent's first weights "
+                         f"(single-threaded FP64 C oracle, {e1:.1f} s)"}
+    out = {"metric": "population-iterations/s (descent)", "value": case.D * res["steps_total"] / el,
+           "unit": "population-iterations/s", "n_gpus": 1, "wall_s": el, "higher_is_better": True,
+           "dtype": prec, "data": "synthetic (seeded planted 28-partite graph, n = 1000)",
+           "config": {"workload": case.name + "_descent", "k_first": args.descent_k_first,
+                      "max_steps": args.descent_steps, "attempts": 1, "D": case.D},
+           "result": dict(res, colouring_legal=legal), "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +165,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--tile-bm", type=int, default=0)
     ap.add_argument("--tile-ntw", type=int, default=0)
+    ap.add_argument("--descent", action="store_true",
+                    help="time the colour-count descent driver instead of the step (planted n=1000, 28 colours)")
+    ap.add_argument("--descent-k-first", type=int, default=34)
+    ap.add_argument("--descent-steps", type=int, default=2000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -132,6 +180,10 @@ def main():
 
     import torch
     import paper_1909_02261_amd as pk
+
+    if args.descent:
+        run_descent(args, torch, pk)
+        return
 
     prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp4", "c4": "bf16", "c5": "fp4"}[args.workload]
     case = workload(args.workload, prec)
