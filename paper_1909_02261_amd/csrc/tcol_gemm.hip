@@ -8,8 +8,9 @@
 // into 2 f_color(S_d) (the gradient's first term is the TabuCol gamma matrix,
 // whose entry at the vertex's own colour counts its conflicts).
 //
-// Layout: 256 threads = 4 waves as 2 (rows) x 2 (columns); block tile BM x BN
-// with BN = 32 * NTW; each wave owns (BM/2) x (16 NTW) as 16x16 MFMA subtiles.
+// Layout: 4 waves as 2 (rows) x 2 (columns), or 8 as 4 x 2 for 256-row tiles; block
+// tile BM x BN with BN = 32 * NTW; each wave owns (BM/WM) x (16 NTW) as 16x16 MFMA
+// subtiles.
 // Both operands are K-contiguous; a K-stage moves 128 bytes of every operand
 // row straight from global memory into LDS (global_load_lds, 16 bytes per
 // lane, no registers on the way) through two or three stage buffers, and the
@@ -51,16 +52,31 @@ __device__ inline f32x4 mfma_f32(float a, float b, const f32x4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// 16-row MFMA subtiles per wave of a BM-row tile (4 waves of BM/2 rows, or 8 of 64 rows at BM = 256)
+constexpr int tile_mt(int bm) { return bm == 256 ? 4 : bm / 32; }
+constexpr int tile_threads(int bm) { return bm == 256 ? 512 : 256; }
+
 template <int BM, int NTW>
 struct Tile {
     static constexpr int BN = 32 * NTW;
-    static constexpr int MT = BM / 32;                       // 16-row subtiles per wave
+    // 256-row tiles run 8 waves (4 x 2, 64 x 64 each, two per SIMD); the others 4 (2 x 2)
+    static constexpr int WAVES = BM == 256 ? 8 : 4;
+    static constexpr int THREADS = 64 * WAVES;
+    static_assert(THREADS == tile_threads(BM), "threads per block");
+    static constexpr int WM = WAVES / 2;                     // waves along the rows
+    static constexpr int RW = BM / WM;                       // rows per wave
+    static constexpr int MT = RW / 16;                       // 16-row subtiles per wave
+    static_assert(MT == tile_mt(BM), "subtiles per wave");
     static constexpr int STAGE = (BM + BN) * kStageRowBytes; // bytes per LDS stage
-    static constexpr int GROUPS = (BM + BN) / 32;            // 8-row load groups per wave per stage
-    static_assert((BM + BN) % 32 == 0, "load split");
-    // LDS stage buffers: three, unless only two keep the block within 80 KB (two
-    // blocks, i.e. two waves per SIMD, per CU)
-    static constexpr int NB = (3 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 3 : ((2 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 2 : 3);
+    static constexpr int GROUPS = (BM + BN) / (8 * WAVES);   // 8-row load groups per wave per stage
+    static_assert((BM + BN) % (8 * WAVES) == 0, "load split");
+    // LDS stage buffers: three, unless only two keep a 4-wave block within 80 KB (two
+    // blocks, i.e. two waves per SIMD, per CU); an 8-wave block takes two
+    static constexpr int NB = WAVES == 8 ? 2
+                              : ((3 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 3
+                                                                         : ((2 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 2 : 3));
+    // compiled for two waves per SIMD (at most 256 registers per lane)
+    static constexpr bool TWO_PER_SIMD = WAVES == 8 || 2 * (NB * STAGE + 4 * (BN + 2)) <= 160 * 1024;
 };
 
 // Fragments of one LDS stage for one wave (chunk c of row r sits at slot c ^ ((r >> 1) & 7)).
@@ -70,7 +86,7 @@ struct Tile {
 // format sums the plain product.
 template <int PREC, int BM, int NTW>
 struct StageFrags {
-    static constexpr int MT = BM / 32;
+    static constexpr int MT = Tile<BM, NTW>::MT;
     static constexpr int SUB = PREC == kPrecFP8 ? 1 : 2;   // K-steps per stage
     static constexpr int W = PREC == kPrecFP8 ? 2 : 1;     // 16-byte chunks per fragment
     uint4 a[SUB][MT][W], b[SUB][NTW][W];
@@ -79,7 +95,7 @@ struct StageFrags {
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void stage_read(StageFrags<PREC, BM, NTW>& F, const uint8_t* L, int lane, int wm, int wn) {
     using Fr = StageFrags<PREC, BM, NTW>;
-    const int ra = wm * (BM / 2) + (lane & 15);
+    const int ra = wm * Tile<BM, NTW>::RW + (lane & 15);
     const int rb = BM + wn * (NTW * 16) + (lane & 15);
     const int q = lane >> 4;
     const int swz = (lane & 15) >> 1;  // = (row >> 1) & 7 for every row this lane reads
@@ -102,7 +118,7 @@ __device__ __forceinline__ void stage_read(StageFrags<PREC, BM, NTW>& F, const u
 }
 
 template <int PREC, int BM, int NTW>
-__device__ __forceinline__ void stage_mma(f32x4 (&acc)[BM / 32][NTW], const StageFrags<PREC, BM, NTW>& F) {
+__device__ __forceinline__ void stage_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const StageFrags<PREC, BM, NTW>& F) {
     using Fr = StageFrags<PREC, BM, NTW>;
 #pragma unroll
     for (int ks = 0; ks < Fr::SUB; ++ks)
@@ -145,7 +161,7 @@ __device__ __forceinline__ void stage_load(const uint8_t* __restrict__ Arow, con
     const int rsub = lane >> 3, slot = lane & 7;
 #pragma unroll
     for (int gi = 0; gi < T::GROUPS; ++gi) {
-        const int grp = wave + 4 * gi;
+        const int grp = wave + T::WAVES * gi;
         const int r = grp * 8 + rsub;
         const int c = slot ^ ((r >> 1) & 7);
         const uint8_t* src = (r < BM ? Arow + (size_t)r * ld : Brow + (size_t)(r - BM) * ld) +
@@ -185,7 +201,7 @@ __device__ __forceinline__ void stage_barrier() {
 // iteration s every wave has finished reading stage s, so its buffer takes the
 // loads of stage s+NB.  Large tiles, whose two fragment sets would spill, keep one.
 template <int PREC, int BM, int NTW>
-__device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[BM / 32][NTW], const uint8_t* __restrict__ Arow,
+__device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const uint8_t* __restrict__ Arow,
                                            const uint8_t* __restrict__ Brow, size_t ld, int nstages,
                                            uint8_t* lds) {
     using T = Tile<BM, NTW>;
@@ -348,17 +364,17 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
         const int dlast = (ncol_end - 1) / k;
         const int nm = dlast - dfirst + 1;
         int16_t* ct = (int16_t*)lds;   // [nm][BM]
-        for (int e = tid; e < nm * BM; e += 256) {
+        for (int e = tid; e < nm * BM; e += T::THREADS) {
             const int dm = e / BM, r = e - dm * BM;
             ct[e] = m0 + r < n ? colr[(size_t)(dfirst + dm) * cs + m0 + r] : (int16_t)-1;
         }
-        for (int e = tid; e < nm; e += 256) f2l[e] = 0;
+        for (int e = tid; e < nm; e += T::THREADS) f2l[e] = 0;
         __syncthreads();
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int ri = wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
+                const int ri = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
 #pragma unroll
                 for (int nt = 0; nt < NTW; ++nt) {
                     if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
@@ -366,7 +382,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 }
             }
         __syncthreads();
-        for (int e = tid; e < nm; e += 256)
+        for (int e = tid; e < nm; e += T::THREADS)
             if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);
     }
     if ((passes & 2) && dense_pen) {
@@ -388,7 +404,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = m0 + wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
+                const int i = m0 + wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
                 if (i < n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
@@ -424,14 +440,14 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int row = wm * (BM / 2) + mt * 16 + (lane >> 4) * 4 + r;
+                        const int row = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
                         const int col = wn * (NTW * 16) + nt * 16 + (lane & 15);
                         if (row / EPI == h) Gt[(row - h * EPI) * LDG + col] = acc[mt][nt][r];
                     }
             __syncthreads();
             // rows (member, vertex): softmax along k, straight-through gradient, update,
             // smoothing, and the argmax colouring of the updated weights
-            for (int rr = g16; rr < EPI * nmem; rr += 16) {
+            for (int rr = g16; rr < EPI * nmem; rr += T::THREADS / 16) {
                 const int r = rr % EPI, dm = rr / EPI;
                 const int i = m0 + h * EPI + r;
                 if (i >= n) continue;
@@ -504,29 +520,29 @@ static size_t lds_bytes(int cstage) {
     return sweep > epi ? sweep : epi;
 }
 
-// The contraction kernel.  Tiles whose stage buffers leave room for a second block
-// per CU are compiled for two waves per SIMD (at most 256 registers per lane), so
-// that the second block can actually be resident.
+// The contraction kernel.  Tiles that run two waves per SIMD (a second 4-wave block
+// per CU, or one 8-wave block) are compiled for at most 256 registers per lane, so
+// that the second wave can actually be resident.
 template <int PREC, int BM, int NTW, int MODE>
-__global__ __launch_bounds__(256) void k_gemm(const GraphDev* __restrict__ gd, int G, int total_tiles,
-                                              int honor_stop, int passes, int cstage) {
+__global__ __launch_bounds__(tile_threads(BM)) void k_gemm(const GraphDev* __restrict__ gd, int G,
+                                                                 int total_tiles, int honor_stop, int passes,
+                                                                 int cstage) {
     gemm_body<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, cstage);
 }
 template <int PREC, int BM, int NTW, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_x2(
+__global__ __launch_bounds__(tile_threads(BM)) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_x2(
     const GraphDev* __restrict__ gd, int G, int total_tiles, int honor_stop, int passes, int cstage) {
     gemm_body<PREC, BM, NTW, MODE>(gd, G, total_tiles, honor_stop, passes, cstage);
 }
 template <int BM, int NTW, int MODE>
-constexpr bool two_per_cu() {
-    using T = Tile<BM, NTW>;
-    return MODE == 0 && T::NB * T::STAGE + 4 * (T::BN + 2) <= 80 * 1024;
+constexpr bool two_per_simd() {
+    return MODE == 0 && Tile<BM, NTW>::TWO_PER_SIMD;
 }
 
 template <int PREC, int BM, int NTW, int MODE>
 static hipError_t prep_one() {
     const void* f;
-    if constexpr (two_per_cu<BM, NTW, MODE>())
+    if constexpr (two_per_simd<BM, NTW, MODE>())
         f = (const void*)k_gemm_x2<PREC, BM, NTW, MODE>;
     else
         f = (const void*)k_gemm<PREC, BM, NTW, MODE>;
@@ -538,12 +554,13 @@ static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int hon
                              hipStream_t s) {
     const size_t shm = lds_bytes<BM, NTW, MODE>(cstage);
     if (shm > (size_t)kMaxLds) return hipErrorInvalidValue;
-    if constexpr (two_per_cu<BM, NTW, MODE>())
-        k_gemm_x2<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop,
-                                                                                passes, cstage);
+    constexpr int threads = Tile<BM, NTW>::THREADS;
+    if constexpr (two_per_simd<BM, NTW, MODE>())
+        k_gemm_x2<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(threads), shm, s>>>(gd, G, total_tiles, honor_stop,
+                                                                                    passes, cstage);
     else
-        k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(256), shm, s>>>(gd, G, total_tiles, honor_stop, passes,
-                                                                             cstage);
+        k_gemm<PREC, BM, NTW, MODE><<<dim3(total_tiles), dim3(threads), shm, s>>>(gd, G, total_tiles, honor_stop,
+                                                                                 passes, cstage);
     return hipGetLastError();
 }
 

@@ -199,15 +199,18 @@ static long long tiles_for(const tcol_ctx* c, int bm, int ntw, int mode) {
 
 // Estimated time of one contraction launch with a tile shape: tiles run in
 // rounds of (CUs x resident blocks), and a tile costs its MFMA work (BM x BN per
-// K-stage) plus its operand staging (BM + BN rows per K-stage).  Tiles whose stage
-// buffers fit in 80 KB run two blocks per CU; the large ones one.
+// K-stage) plus its operand staging (BM + BN rows per K-stage).
 static double shape_cost(const tcol_ctx* c, int bm, int ntw) {
     const long long tiles = tiles_for(c, bm, ntw, 0);
     const int bn = gemm_bn(ntw);
-    // the kernel keeps three stage buffers, or two when only two fit two blocks per CU
+    // 256-row tiles run one 8-wave block per CU; the others keep three stage buffers, or
+    // two when only two fit two 4-wave blocks per CU
+    const int waves = bm == 256 ? 8 : 4;
     const int stage = (bm + bn) * 128, extra = 4 * (bn + 2);
-    const int per_cu = (3 * stage + extra <= 80 * 1024 || 2 * stage + extra <= 80 * 1024) ? 2 : 1;
+    const int per_cu = waves == 8 ? 1 : ((3 * stage + extra <= 80 * 1024 || 2 * stage + extra <= 80 * 1024) ? 2 : 1);
     const long long rounds = (tiles + 256LL * per_cu - 1) / (256LL * per_cu);
+    // an 8-wave block measured slower than two independent 4-wave blocks of half its
+    // size (their barriers do not align), so it gets no credit for its extra waves
     return (double)rounds * ((double)bm * bn + 32.0 * (bm + bn));
 }
 
