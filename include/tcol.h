@@ -102,7 +102,8 @@ typedef struct {
     int32_t unroll;         /* steps per captured graph (1..64, default 8) */
     int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */
     int32_t tile_ntw;       /* GEMM 16-column subtiles per wave; the instantiated (tile_bm, tile_ntw)
-                               pairs are (64,2) (64,4) (128,4) (128,8) (64,9) (128,9) (256,4) */
+                               pairs are (64,2) (64,4) (128,4) (128,6) (128,8) (64,9) (128,9)
+                               (256,4; 8 waves) */
     int32_t penalty;        /* fast and epilogue paths, penalty term (A o Mt^(alpha-1) and
                                (J-A) o Mt^(beta-1) times S, eq. 17): 0 = choose (default),
                                1 = dense operand pass on MFMA, 2 = class gather in FP32: with

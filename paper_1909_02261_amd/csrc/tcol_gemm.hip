@@ -73,10 +73,13 @@ struct Tile {
     // LDS stage buffers: three, unless only two keep a 4-wave block within 80 KB (two
     // blocks, i.e. two waves per SIMD, per CU); an 8-wave block takes two
     static constexpr int NB = WAVES == 8 ? 2
-                              : ((3 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 3
-                                                                         : ((2 * STAGE + 4 * (BN + 2) <= 80 * 1024) ? 2 : 3));
+                              : ((3 * STAGE <= 80 * 1024) ? 3 : ((2 * STAGE <= 80 * 1024) ? 2 : 3));
     // compiled for two waves per SIMD (at most 256 registers per lane)
-    static constexpr bool TWO_PER_SIMD = WAVES == 8 || 2 * (NB * STAGE + 4 * (BN + 2)) <= 160 * 1024;
+    static constexpr bool TWO_PER_SIMD = WAVES == 8 || 2 * NB * STAGE <= 160 * 1024;
+    // after the K-sweep the stage buffers hold the gather: the colours of the tile's
+    // rows for its members, then the per-member conflict counters
+    static constexpr int CT_BYTES = ((BN + 2) * BM * 2 + 15) / 16 * 16;
+    static_assert(CT_BYTES + 4 * (BN + 2) <= NB * STAGE, "gather fits the stage buffers");
 };
 
 // Fragments of one LDS stage for one wave (chunk c of row r sits at slot c ^ ((r >> 1) & 7)).
@@ -211,23 +214,24 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const
     const int wm = wave >> 1, wn = wave & 1;
     if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64) {
         // tiles whose fragments would not fit twice in registers: one fragment set, the
-        // global -> LDS loads two stages ahead
-        static_assert(T::NB == 3, "three stage buffers");
-        stage_load<BM, NTW>(Arow, Brow, ld, 0, lds, lane, wave);
-        stage_load<BM, NTW>(Arow, Brow, ld, min(1, nstages - 1), lds + T::STAGE, lane, wave);
-        wait_vm<T::GROUPS>();      // stage 0 has landed, stage 1 may be in flight
+        // global -> LDS loads NB - 1 stages ahead
+        constexpr int NB = T::NB;
+#pragma unroll
+        for (int b = 0; b < NB - 1; ++b)
+            stage_load<BM, NTW>(Arow, Brow, ld, min(b, nstages - 1), lds + b * T::STAGE, lane, wave);
+        wait_vm<(NB - 2) * T::GROUPS>();   // stage 0 has landed
         stage_barrier();
         int cur = 0;
         for (int s = 0; s < nstages; ++s) {
-            const int nxt = cur >= 1 ? cur - 1 : cur + 2;   // (s + 2) mod 3
-            stage_load<BM, NTW>(Arow, Brow, ld, min(s + 2, nstages - 1), lds + nxt * T::STAGE, lane, wave);
+            const int nxt = cur == 0 ? NB - 1 : cur - 1;   // (s + NB - 1) mod NB
+            stage_load<BM, NTW>(Arow, Brow, ld, min(s + NB - 1, nstages - 1), lds + nxt * T::STAGE, lane, wave);
             Fr F;
             stage_read<PREC, BM, NTW>(F, lds + cur * T::STAGE, lane, wm, wn);
             __builtin_amdgcn_sched_barrier(0);
             stage_mma<PREC, BM, NTW>(acc, F);
-            wait_vm<T::GROUPS>();  // stage s+1 has landed, stage s+2 may be in flight
+            wait_vm<(NB - 2) * T::GROUPS>();  // stage s+1 has landed
             stage_barrier();
-            cur = cur == 2 ? 0 : cur + 1;
+            cur = cur == NB - 1 ? 0 : cur + 1;
         }
         return;
     }
@@ -293,8 +297,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     constexpr int MT = T::MT;
     constexpr int BN = T::BN;
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int* f2l = (int*)(lds + T::NB * T::STAGE);       // BN + 2 gather counters
-    static_assert((BN + 2) * BM * 2 <= T::NB * T::STAGE, "gather colours fit the stage buffers");
+    int* f2l = (int*)(lds + T::CT_BYTES);            // BN + 2 gather counters (after the colours)
 
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     int g, tm, tn;
@@ -514,7 +517,7 @@ constexpr int kMaxLds = 160 * 1024;
 template <int BM, int NTW, int MODE>
 static size_t lds_bytes(int cstage) {
     using T = Tile<BM, NTW>;
-    const size_t sweep = T::NB * T::STAGE + sizeof(int) * (T::BN + 2);
+    const size_t sweep = T::NB * T::STAGE;
     if (MODE == 0) return sweep;
     const size_t epi = (size_t)(BM < 128 ? BM : 128) * (T::BN + 4) * sizeof(float) + (size_t)cstage;
     return sweep > epi ? sweep : epi;
@@ -566,8 +569,8 @@ static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int hon
 
 // instantiated tile shapes: (BM, NTW)
 #define TCOL_GEMM_SHAPES(X, PREC, MODE) \
-    X(PREC, 64, 2, MODE) X(PREC, 64, 4, MODE) X(PREC, 128, 4, MODE) X(PREC, 128, 8, MODE) X(PREC, 64, 9, MODE) \
-    X(PREC, 128, 9, MODE) X(PREC, 256, 4, MODE)
+    X(PREC, 64, 2, MODE) X(PREC, 64, 4, MODE) X(PREC, 128, 4, MODE) X(PREC, 128, 6, MODE) X(PREC, 128, 8, MODE) \
+    X(PREC, 64, 9, MODE) X(PREC, 128, 9, MODE) X(PREC, 256, 4, MODE)
 
 #define TCOL_GEMM_CASE(PREC, BM, NTW, MODE)                                                             \
     if (s.prec == PREC && s.bm == BM && s.ntw == NTW && s.mode == MODE) {                               \

@@ -105,7 +105,7 @@ tcol_status check_params(const tcol_graph_params& p) {
 double pow0(double x, double p) { return x == 0.0 ? 0.0 : pow(x, p); }
 
 // shapes the contraction kernel is instantiated for: (rows per block, 16-column subtiles per wave)
-const int kShapes[][2] = {{64, 2}, {64, 4}, {128, 4}, {128, 8}, {64, 9}, {128, 9}, {256, 4}};
+const int kShapes[][2] = {{64, 2}, {64, 4}, {128, 4}, {128, 6}, {128, 8}, {64, 9}, {128, 9}, {256, 4}};
 
 }  // namespace
 
@@ -206,8 +206,8 @@ static double shape_cost(const tcol_ctx* c, int bm, int ntw) {
     // 256-row tiles run one 8-wave block per CU; the others keep three stage buffers, or
     // two when only two fit two 4-wave blocks per CU
     const int waves = bm == 256 ? 8 : 4;
-    const int stage = (bm + bn) * 128, extra = 4 * (bn + 2);
-    const int per_cu = waves == 8 ? 1 : ((3 * stage + extra <= 80 * 1024 || 2 * stage + extra <= 80 * 1024) ? 2 : 1);
+    const int stage = (bm + bn) * 128;
+    const int per_cu = waves == 8 ? 1 : ((3 * stage <= 80 * 1024 || 2 * stage <= 80 * 1024) ? 2 : 1);
     const long long rounds = (tiles + 256LL * per_cu - 1) / (256LL * per_cu);
     // an 8-wave block measured slower than two independent 4-wave blocks of half its
     // size (their barriers do not align), so it gets no credit for its extra waves
