@@ -28,7 +28,7 @@ import tcolgen
 
 PEAK = {"fp4": 10.1e15, "fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
 GEMM_SRC = os.path.join(ROOT, "paper_1909_02261_amd", "csrc", "tcol_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_fp8_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_hbm_traffic.txt")
 HBM_PEAK = 8.0e12
 PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8, "fp4": tcolgen.FP4}
 
@@ -78,7 +78,7 @@ def measured_traffic(config: dict):
         sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
         if fields.get("source_sha256") != sha:
             return None
-        for key in ("workload", "tile_bm", "tile_ntw", "penalty", "path"):
+        for key in ("workload", "tile_bm", "tile_ntw", "penalty", "path", "precision"):
             if fields.get(key) != str(config[key]):
                 return None
         return float(fields["traffic_bytes_per_launch"])

@@ -92,9 +92,9 @@ typedef struct {
 typedef struct {
     int32_t fused;          /* step schedule: 0 = plain path (argmax, dense penalty operand,
                                contraction, update as separate kernels every iteration);
-                               1 = fast path (default): penalty rows from the sparse kernel when
-                               chosen, the update kernel also colours the updated rows, no
-                               separate argmax pass (k <= 288, else the plain order);
+                               1 = fast path (default): the update kernel also colours the
+                               updated rows, no separate argmax pass (k <= 288, else the plain
+                               order); the penalty term as `penalty` selects;
                                2 = epilogue path: the contraction kernel itself applies softmax,
                                gradient, update and the next argmax, into a second weight
                                buffer (k <= 288) */
