@@ -195,7 +195,9 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * captured graph) with HIP events around each kernel on the context's stream
  * and writes the average milliseconds per iteration of each phase to
  * ms[TCOL_NPHASES]: 0 argmax colours, 1 class sizes, 2 one-hot S expansion,
- * 3 group concentration + penalty operand, 4 contraction A.S (+ penalty pass)
+ * 3 penalty (group concentration + dense operand, or the class gather, which on
+ * the fast path runs after the contraction and adds its rows to G),
+ * 4 contraction A.S (+ dense penalty pass)
  * with fitness gather and, on the fused path, the update epilogue,
  * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
  * 7 counter advance.  Phase 4 is timed separately as `steps` contraction

@@ -309,7 +309,8 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
     // a graph takes either the dense operand pass or the penalty rows of the class-gather
-    // kernel (already in G); the plain path (passes bit 3) always takes the dense pass
+    // kernel (in G for the fused epilogue, in Gp for the row update); the plain path
+    // (passes bit 3) always takes the dense pass
     const bool gather_pen = pen && d.pgather && !(passes & 8);
     const bool dense_pen = pen && !gather_pen;
 
@@ -402,7 +403,8 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     }
     if (!(passes & 4)) return;
     if constexpr (MODE == 0) {
-        // G[d][i][l] = acc
+        // G[d][i][l] = acc (class-gather penalty rows, when present, are in Gp and the
+        // row update adds them)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -411,10 +413,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 if (i < n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
-                        if (cm[nt] >= 0) {
-                            float* gp = Gg + ((size_t)cm[nt] * n + i) * k + cl[nt];
-                            *gp = gather_pen ? acc[mt][nt][r] + *gp : acc[mt][nt][r];
-                        }
+                        if (cm[nt] >= 0) Gg[((size_t)cm[nt] * n + i) * k + cl[nt]] = acc[mt][nt][r];
                 }
             }
     } else {

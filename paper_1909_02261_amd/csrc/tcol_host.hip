@@ -126,7 +126,7 @@ struct tcol_ctx {
     GemmShape shape{};              // separate-path tiling (also used by tcol_conflicts / tcol_loss_grad)
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
-    int pg_R = 0, pg_M = 0;         // class-gather penalty: rows per block, members per list stage
+    int pg_R = 0, pg_PM = 0;        // class-gather penalty: rows per block, members per list group
     size_t pg_lds = 0;              // dynamic LDS of the class-gather kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
     int total_pg = 0;               // blocks of the class-gather kernel (0: no graph uses it)
@@ -258,6 +258,25 @@ static void pick_shapes(tcol_ctx* c) {
 // every workload measured, so it runs only on request.
 static bool gather_preferred(const tcol_graph_params&) { return false; }
 
+// Rows per block R and members per list group PM of the class-gather kernel: the largest
+// R <= 4 that keeps at least 500 blocks, with the largest PM <= min(D, 16) whose LDS fits
+// two blocks per CU (80 KB), else one block per CU (160 KB); R is lowered when neither
+// fits.  Returns false when nothing fits.
+static bool pick_gather(int kmax, int dmax, int nmax, int rows_total, int& R, int& PM) {
+    int r = 4;
+    while (r > 1 && rows_total / r < 500) r /= 2;
+    for (; r >= 1; r /= 2)
+        for (size_t budget : {(size_t)80 * 1024, (size_t)160 * 1024})
+            for (int pm = std::min(dmax, 16); pm >= 1; --pm)
+                if (penalty_gather_group_fits(pm, kmax, nmax) &&
+                    penalty_gather_lds(r, pm, kmax, dmax, nmax) <= budget) {
+                    R = r;
+                    PM = pm;
+                    return true;
+                }
+    return false;
+}
+
 // recompute flattened work offsets for the tile shapes and upload the descriptors
 static tcol_status rebuild_schedule(tcol_ctx* c) {
     pick_shapes(c);
@@ -268,7 +287,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
     // class-gather penalty: a graph takes it on request (penalty 2) or when the automatic
     // choice prefers it
-    int pg_k = 0, pg_D = 0, pg_n = 0;
+    int pg_k = 0, pg_D = 0, pg_n = 0, pg_rows = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const int pen = c->opt.penalty;
@@ -277,20 +296,22 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
             pg_k = std::max(pg_k, p.k);
             pg_D = std::max(pg_D, p.D);
             pg_n = std::max(pg_n, p.n);
+            pg_rows += p.n;
         }
     }
-    c->pg_R = c->pg_M = 0;
+    c->pg_R = c->pg_PM = 0;
     c->pg_lds = 0;
     if (pg_k > 0) {
-        // rows per block: codes of at most 40 KB; then as many staged members as keep the
-        // block within 80 KB (two blocks per CU); very large n falls back to one row and one member
-        int R = 8;
-        while (R > 1 && 2LL * R * round_up(pg_n, kPadN) > 40 * 1024) R /= 2;
-        int M = 8;
-        while (M > 1 && (M > pg_D || penalty_gather_lds(R, M, pg_k, pg_D, pg_n) > 80 * 1024)) M /= 2;
-        c->pg_R = R;
-        c->pg_M = M;
-        c->pg_lds = penalty_gather_lds(R, M, pg_k, pg_D, pg_n);
+        // graphs too large for the kernel's LDS take the dense pass
+        int R = 0, PM = 0;
+        if (pick_gather(pg_k, pg_D, pg_n, pg_rows, R, PM)) {
+            c->pg_R = R;
+            c->pg_PM = PM;
+            c->pg_lds = penalty_gather_lds(R, PM, pg_k, pg_D, pg_n);
+        } else {
+            for (int g = 0; g < c->G; ++g) c->hdesc[g].pgather = 0;
+            pg_k = 0;
+        }
     }
     c->prep_lds = prep_lds(c->kmax, c->nmax, pg_k > 0);
     int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
@@ -365,10 +386,19 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 }
 
 // penalty of the fast and epilogue paths: class-gather rows or the dense operand, per graph
+// (the epilogue path takes the class-gather rows in G before the contraction, whose
+// epilogue adds them; the fast path adds them to the contraction's G afterwards,
+// enqueue_gather_add)
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
-    if (c->total_pg > 0)
-        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_M, c->pg_lds, 1, s));
+    if (c->total_pg > 0 && path_of(c) == 2)
+        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_PM, c->pg_lds, 1, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
+    return hipSuccess;
+}
+
+static hipError_t enqueue_gather_add(tcol_ctx* c, hipStream_t s) {
+    if (c->total_pg > 0)
+        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_PM, c->pg_lds, 1, 1, s));
     return hipSuccess;
 }
 
@@ -378,6 +408,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
+    HIPRET(enqueue_gather_add(c, s));
     HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
     HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, 1, 0, -1, nullptr, nullptr, s));
     HIPRET(launch_advance(c->ddesc, c->G, s));
@@ -776,8 +807,9 @@ tcol_status tcol_reset(tcol_ctx* c) {
 tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms) {
     if (!c || steps < 1 || !ms) return TCOL_EINVAL;
     constexpr int NP = TCOL_NPHASES;
-    hipEvent_t ev[NP];
-    for (int i = 0; i < NP; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    constexpr int NE = 10;
+    hipEvent_t ev[NE];
+    for (int i = 0; i < NE; ++i) HIPCHK(hipEventCreate(&ev[i]));
     double acc[NP] = {0};
     hipStream_t s = c->stream;
     const int path = path_of(c);
@@ -801,18 +833,27 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         else
             HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
-        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
+        if (path == 1) HIPCHK(enqueue_gather_add(c, s));
         HIPCHK(hipEventRecord(ev[6], s));
-        if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
+        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
         HIPCHK(hipEventRecord(ev[7], s));
-        if (path != 2) HIPCHK(launch_advance(c->ddesc, c->G, s));
+        if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
         HIPCHK(hipEventRecord(ev[8], s));
-        HIPCHK(hipEventSynchronize(ev[8]));
-        for (int i = 0; i < 8; ++i) {
-            float x = 0;
-            HIPCHK(hipEventElapsedTime(&x, ev[i], ev[i + 1]));
-            acc[i] += x;
-        }
+        if (path != 2) HIPCHK(launch_advance(c->ddesc, c->G, s));
+        HIPCHK(hipEventRecord(ev[9], s));
+        HIPCHK(hipEventSynchronize(ev[9]));
+        float x[NE - 1];
+        for (int i = 0; i + 1 < NE; ++i) HIPCHK(hipEventElapsedTime(&x[i], ev[i], ev[i + 1]));
+        // phases: colours, class sizes, expansion, penalty (operand or class gather),
+        // contraction, fitness, update, advance
+        acc[0] += x[0];
+        acc[1] += x[1];
+        acc[2] += x[2];
+        acc[3] += x[3] + x[5];
+        acc[4] += x[4];
+        acc[5] += x[6];
+        acc[6] += x[7];
+        acc[7] += x[8];
     }
     for (int i = 0; i < 8; ++i) ms[i] = (float)(acc[i] / steps);
     // the contraction again, `steps` launches back to back on the operands of the last
@@ -848,7 +889,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
         ms[8] = x / steps;
     }
-    for (int i = 0; i < NP; ++i) hipEventDestroy(ev[i]);
+    for (int i = 0; i < NE; ++i) hipEventDestroy(ev[i]);
     return TCOL_OK;
 }
 

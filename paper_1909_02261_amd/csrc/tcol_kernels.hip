@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
 // For a graph on the class-gather penalty also the member's vertices grouped by
 // colour (stable counting sort: each class in increasing vertex order, so the
 // penalty sums run in the same order on every run).  One block per member.
-// Dynamic LDS: k counts, and with the class lists k + 1 cursors and n entries.
+// Dynamic LDS: k counts, and with the class lists 4 k per-wave cursors and n entries.
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
                                               int next) {
     extern __shared__ int prep_sh[];
@@ -162,65 +162,98 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     int16_t* __restrict__ cT = d.cT;
     const size_t cTs = d.cTs;
     int* cnt = prep_sh;
+    const bool lists = d.pgather != 0;              // uniform over the block
+    // with the class lists each wave counts its own quarter of the vertices
+    constexpr int NW = 4;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int Q = ((n + NW - 1) / NW + 63) & ~63;
+    int* cw = prep_sh + k;                          // [NW][k]
     for (int l = tid; l < k; l += 256) cnt[l] = 0;
+    if (lists)
+        for (int l = tid; l < NW * k; l += 256) cw[l] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += 256) {
-        const int16_t x = c[i];
-        atomicAdd(&cnt[x], 1);
-        cT[(size_t)i * cTs + m] = x;
+    if (lists) {
+        const int e = min(n, (wv + 1) * Q);
+        for (int i = wv * Q + lane; i < e; i += 64) {
+            const int16_t x = gview(c)[i];
+            atomicAdd(&cnt[x], 1);
+            atomicAdd(&cw[wv * k + x], 1);
+            cT[(size_t)i * cTs + m] = x;
+        }
+    } else {
+        for (int i = tid; i < n; i += 256) {
+            const int16_t x = gview(c)[i];
+            atomicAdd(&cnt[x], 1);
+            cT[(size_t)i * cTs + m] = x;
+        }
     }
     __syncthreads();
     int32_t* V = d.V[p] + (size_t)m * k;
     for (int l = tid; l < k; l += 256) V[l] = cnt[l];
-    if (!d.pgather) return;                         // uniform over the block
-    int* cur = prep_sh + k;                         // [k + 1]
-    int16_t* lst = (int16_t*)(cur + k + 1);         // [n]
+    if (!lists) return;
+    int16_t* lst = (int16_t*)(cw + NW * k);         // [n]
     int32_t* __restrict__ off = d.cls_off + (size_t)m * (k + 1);
     int16_t* __restrict__ cv = d.cls_v + (size_t)m * d.cs;
-    // exclusive scan of the counts: runs of `per` classes per thread, then the 256 run sums
+    // exclusive scan of the counts: runs of `per` classes per thread, the 256 run sums
+    // scanned by wave 0 (four per lane, then across lanes)
     const int per = (k + 255) / 256;
     const int lb = min(k, tid * per), le = min(k, lb + per);
     int run = 0;
     for (int l = lb; l < le; ++l) run += cnt[l];
     part[tid] = run;
     __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < 256; ++t) {
-            const int v = part[t];
-            part[t] = acc;
-            acc += v;
+    if (tid < 64) {
+        const int v0 = part[4 * tid], v1 = part[4 * tid + 1], v2 = part[4 * tid + 2], v3 = part[4 * tid + 3];
+        const int sum = v0 + v1 + v2 + v3;
+        int incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (tid >= o) incl += y;
         }
+        const int ex = incl - sum;
+        part[4 * tid] = ex;
+        part[4 * tid + 1] = ex + v0;
+        part[4 * tid + 2] = ex + v0 + v1;
+        part[4 * tid + 3] = ex + v0 + v1 + v2;
     }
     __syncthreads();
+    // class l starts at its offset; within it the quarters follow in order, so each
+    // wave's cursor for l starts after the earlier quarters' vertices of colour l
     int acc = part[tid];
     for (int l = lb; l < le; ++l) {
-        cur[l] = acc;
         off[l] = acc;
+        int q = acc;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int x = cw[w * k + l];
+            cw[w * k + l] = q;
+            q += x;
+        }
         acc += cnt[l];
     }
     if (tid == 0) off[k] = n;
     __syncthreads();
-    // stable placement: wave 0 walks the vertices in order, 64 at a time (colours
-    // loaded eight chunks ahead); lanes of one colour find each other with one
-    // ballot per colour bit and take consecutive slots
-    if (tid < 64) {
-        const int lane = tid;
+    // stable placement: each wave walks its quarter in order, 64 vertices at a time
+    // (colours loaded eight chunks ahead); lanes of one colour find each other with
+    // one ballot per colour bit and take consecutive slots
+    {
         int nb = 0;
         while ((1 << nb) < k) ++nb;
         const unsigned long long lt = (1ull << lane) - 1ull;
-        for (int i8 = 0; i8 < n; i8 += 512) {
+        int* cur = cw + wv * k;
+        const int qb = wv * Q, qe = min(n, (wv + 1) * Q);
+        for (int i8 = qb; i8 < qe; i8 += 512) {
             int xs[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = i8 + 64 * u + lane;
-                xs[u] = i < n ? (int)gview(c)[i] : 0;
+                xs[u] = i < qe ? (int)gview(c)[i] : 0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = i8 + 64 * u + lane;
-                if (i8 + 64 * u >= n) break;            // uniform
-                const bool v = i < n;
+                if (i8 + 64 * u >= qe) break;           // uniform over the wave
+                const bool v = i < qe;
                 const int x = xs[u];
                 unsigned long long match = __ballot(v);
                 for (int bit = 0; bit < nb; ++bit) {
@@ -248,20 +281,30 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 //   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
 // m = Mt_ij, enters the gradient as (P.S_d)[i, l], and with one-hot S_d that is the
 // sum of P_ij over the vertices j of colour l in member d: D n terms per row,
-// against D n k multiply-adds for the dense product.  A block takes R rows:
-//   1. for every j it counts m = Mt_ij for its rows from the vertex-major colours
-//      (two members per 32-bit compare, eight per 16-byte load) and keeps the
-//      code (a_ij, m) of P_ij in LDS (the values come from a table of 2 (D + 1)
-//      entries; the excluded diagonal gets m = 0, whose value is 0);
-//   2. it stages the class lists of M members at a time and sums, for every
-//      (member, colour), the table values of its vertices in increasing j, one
-//      thread per (member, colour), in FP32; the sums go to G[d][i][l], where the
-//      contraction adds A.S_d.
-// Dynamic LDS: row colours [R][cTs/2] u32, codes [n_pad][R] u16, lists [M][cs]
-// i16, offsets [M][k+1] i32, table [2 (D+1)] f32 (the first three 16-byte aligned).
-template <int R>
-__global__ __launch_bounds__(256) void k_pen_gather(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                    int honor_stop, int M) {
+// against D n k multiply-adds for the dense product.  A block of NT threads (1024
+// when it has a CU's LDS to itself, else 512) takes R rows:
+//   1. Mt_ij for its rows from the class lists: j shares row i's colour in member d
+//      exactly when j is in the class of c_d(i) in d, so each member adds one to the
+//      count of every vertex of that class (D |class| increments per row, against
+//      n D comparisons for the whole row);
+//   2. the counts become the values P_ij, FP32, kept in LDS as [j][R];
+//   3. the class lists go to LDS PM members at a time (two buffers: the next group
+//      is loaded while the current one is summed); for every (member, colour) one
+//      thread walks the class (increasing j) and sums the values of its vertices
+//      for the R rows in FP32; the sums are added to G[d][i][l] = (A.S_d)[i, l] after
+//      the contraction (accumulate 1), or written there for the contraction's
+//      epilogue to add A.S_d (accumulate 0).
+// Dynamic LDS (penalty_gather_lds): values [n_pad + 1][R] f32 (the last row stays
+// zero: list slots outside a class read it, so a chunk's eight reads issue without
+// branches), table [2 (D + 1)] f32, lists [2][PM][cs] i16, offsets [2][PM][k + 1] i32.
+constexpr int kPgMaxL = 8;      // 16-byte list units per thread per group (512 threads)
+constexpr int kPgMaxO = 9;      // offsets per thread per group (512 threads)
+
+__host__ __device__ inline size_t pg_off_words(int PM, int k) { return ((size_t)PM * (k + 1) + 3) & ~(size_t)3; }
+
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                           int honor_stop, int PM, int accumulate) {
     extern __shared__ __attribute__((aligned(16))) uint8_t pg_sh[];
     const int b = blockIdx.x;
     if (b >= total_blocks) return;
@@ -281,111 +324,193 @@ __global__ __launch_bounds__(256) void k_pen_gather(const GraphDev* __restrict__
     const int i0 = (b - d.pg_begin) * R;
     const int rows = min(R, n - i0);
     const int tid = threadIdx.x;
-    const int ngrp = (D + 7) >> 3;
-    const int rw = 4 * ngrp;                                   // u32 words per staged row
-    uint32_t* ci = (uint32_t*)pg_sh;                           // [R][rw], 16-byte rows
-    uint16_t* codes = (uint16_t*)(ci + R * rw);                // [n_pad][R]: a vertex's R codes together
-    int16_t* lists = (int16_t*)(codes + (size_t)R * n_pad);    // [M][cs]
-    int* offs = (int*)(lists + (size_t)M * cs);                // [M][k + 1]
-    float* lut = (float*)(offs + (size_t)M * (k + 1));         // [2 (D + 1)]
+    float* vals = (float*)pg_sh;                               // [n_pad + 1][R]
+    uint32_t* cnt = (uint32_t*)pg_sh;                          // the same words, phase 1
+    const int vrows = n_pad + (R >= 4 ? 1 : 4 / R);            // whole 16-byte units
+    float* lut = vals + (size_t)vrows * R;                     // [2 (D + 1)]
+    int16_t* lists = (int16_t*)(lut + ((2 * (D + 1) + 3) & ~3));   // [2][PM][cs]
+    const size_t lst_stage = (size_t)PM * cs;
+    const size_t off_stage = pg_off_words(PM, k);
+    int32_t* offs = (int32_t*)(lists + 2 * lst_stage);         // [2][off_stage]
+    const int ngroups = (D + PM - 1) / PM;
+
+    // group loads go through registers: issued early, written to LDS after the
+    // work that hides them
+    constexpr int ML = kPgMaxL * 512 / NT, MO = (kPgMaxO * 512 + NT - 1) / NT;
+    u32x4n lr[ML];
+    int32_t orr[MO];
+    auto fetch = [&](int grp) {
+        const int dg = grp * PM, mc = min(PM, D - dg);
+        const int nu = mc * cs / 8;
+        const int16_t* src = clsv + (size_t)dg * cs;
+#pragma unroll
+        for (int u = 0; u < ML; ++u) {
+            const int e = tid + u * NT;
+            if (e < nu) lr[u] = gload16(src + 8 * e);
+        }
+        const int no = mc * (k + 1);
+        const int32_t* so = clsoff + (size_t)dg * (k + 1);
+#pragma unroll
+        for (int u = 0; u < MO; ++u) {
+            const int e = tid + u * NT;
+            if (e < no) orr[u] = gview(so)[e];
+        }
+    };
+    auto put = [&](int grp, int buf) {
+        const int dg = grp * PM, mc = min(PM, D - dg);
+        const int nu = mc * cs / 8;
+        int16_t* dl = lists + buf * lst_stage;
+#pragma unroll
+        for (int u = 0; u < ML; ++u) {
+            const int e = tid + u * NT;
+            if (e < nu) *(u32x4n*)(dl + 8 * e) = lr[u];
+        }
+        const int no = mc * (k + 1);
+        int32_t* dof = offs + buf * off_stage;
+#pragma unroll
+        for (int u = 0; u < MO; ++u) {
+            const int e = tid + u * NT;
+            if (e < no) dof[e] = orr[u];
+        }
+    };
+
+    fetch(0);
     const float tf = (float)st->t;
-    for (int e = tid; e < R * rw; e += 256) {
-        const int r = e / rw, q = e - r * rw;
-        ci[e] = r < rows ? gview((const uint32_t*)(cT + (size_t)(i0 + r) * cTs))[q] : 0u;
-    }
-    for (int m = tid; m <= D; m += 256) {
-        lut[m] = -(tf * d.lut_bon[m]);
+    for (int e = tid; e < vrows * R / 4; e += NT) ((u32x4n*)cnt)[e] = u32x4n{0u, 0u, 0u, 0u};
+    for (int m = tid; m <= D; m += NT) {
+        // entry 0 is an exact zero: m = 0, and the excluded diagonal
+        lut[m] = m == 0 ? 0.0f : -(tf * d.lut_bon[m]);
         lut[D + 1 + m] = tf * d.lut_pen[m];
     }
     __syncthreads();
-    // 1. codes of P_ij for the block's rows
-    for (int j = tid; j < n; j += 256) {
-        const int16_t* cj = cT + (size_t)j * cTs;
-        int m[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) m[r] = 0;
-#pragma unroll 1
-        for (int g0 = 0; g0 < ngrp; g0 += 8) {
-            u32x4n w[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = g0 + u < ngrp ? gload16(cj + 8 * (g0 + u)) : u32x4n{0u, 0u, 0u, 0u};
+    // 1. Mt_ij: one thread per (row, member) adds one for each vertex of the row's class
+    for (int e = tid; e < rows * D; e += NT) {
+        const int r = e / D, dm = e - r * D;
+        const int col = gview(cT)[(size_t)(i0 + r) * cTs + dm];
+        const int32_t* o = clsoff + (size_t)dm * (k + 1) + col;
+        const int beg = gview(o)[0], end = gview(o)[1];
+        const int16_t* lv = clsv + (size_t)dm * cs;
+        for (int q0 = beg & ~7; q0 < end; q0 += 8) {
+            const u32x4n w = gload16(lv + q0);
+            const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int g = g0 + u;
-                if (g >= ngrp) break;                          // uniform
-                const uint32_t wv[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const uint4 c4 = *(const uint4*)(ci + r * rw + 4 * g);
-                    const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        const int q = 4 * g + h;
-                        const uint32_t vm = (2 * q < D ? 0x8000u : 0u) | (2 * q + 1 < D ? 0x80000000u : 0u);
-                        m[r] += equal_halves_in(cv[h], wv[h], vm);
-                    }
+                const int q = q0 + u;
+                if (q >= beg && q < end) {
+                    const int j = (int)((wv[u >> 1] >> (16 * (u & 1))) & 0xFFFFu);
+                    atomicAdd(&cnt[j * R + r], 1u);
                 }
             }
         }
-        uint16_t cd[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            int code = 0;
-            if (r < rows) {
-                const int i = i0 + r;
-                const bool edge = gview(A8)[(size_t)i * n_pad + j] != 0;
-                int mm = m[r];
-                if (j == i && !diag) mm = 0;                   // a_ii = 0: excluded from the bonus
-                code = edge ? D + 1 + mm : mm;
-            }
-            cd[r] = (uint16_t)code;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) codes[(size_t)j * R + r] = cd[r];
     }
     __syncthreads();
-    // 2. class sums, M members at a time
-    for (int dg = 0; dg < D; dg += M) {
-        const int mc = min(M, D - dg);
-        // the lists of members dg .. dg+mc-1 are contiguous (rows of cs entries, 16-byte multiples)
-        for (int e = tid; e < mc * cs / 8; e += 256)
-            *(u32x4n*)(lists + 8 * e) = gload16(clsv + (size_t)dg * cs + 8 * e);
-        for (int e = tid; e < mc * (k + 1); e += 256) offs[e] = gview(clsoff)[(size_t)dg * (k + 1) + e];
-        __syncthreads();
-        for (int e = tid; e < mc * k; e += 256) {
+    // 2. counts -> P_ij, 16 vertices per thread (the diagonal, m = D, is excluded
+    // from the bonus unless bonus_diag)
+    for (int j0 = 16 * tid; j0 < n; j0 += 16 * NT) {
+        // a_ij of the 16 vertices for each row as a bit mask (A8 bytes are 0 or 1)
+        uint32_t em[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const u32x4n a = r < rows ? gload16(A8 + (size_t)(i0 + r) * n_pad + j0) : u32x4n{0u, 0u, 0u, 0u};
+            const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+            uint32_t m = 0;
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                m |= ((aw[h] & 1u) | ((aw[h] >> 7) & 2u) | ((aw[h] >> 14) & 4u) | ((aw[h] >> 21) & 8u)) << (4 * h);
+            em[r] = m;
+        }
+#pragma unroll 2
+        for (int u = 0; u < 16; ++u) {
+            const int j = j0 + u;
+            uint32_t cw[R];
+            uint32_t* cp = cnt + (size_t)j * R;
+            if constexpr (R >= 4) {
+#pragma unroll
+                for (int h = 0; h < R; h += 4) {
+                    const u32x4n x = *(const u32x4n*)(cp + h);
+                    cw[h] = x.x; cw[h + 1] = x.y; cw[h + 2] = x.z; cw[h + 3] = x.w;
+                }
+            } else if constexpr (R == 2) {
+                const uint2 x = *(const uint2*)cp;
+                cw[0] = x.x; cw[1] = x.y;
+            } else {
+                cw[0] = cp[0];
+            }
+            float fv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int m = (int)cw[r];
+                const bool edge = (em[r] >> u) & 1u;
+                const bool excl = !edge && !diag && j == i0 + r;
+                fv[r] = lut[(m == 0 || excl) ? 0 : (edge ? D + 1 + m : m)];
+            }
+            if constexpr (R >= 4) {
+#pragma unroll
+                for (int h = 0; h < R; h += 4)
+                    *(u32x4n*)(cp + h) = u32x4n{__float_as_uint(fv[h]), __float_as_uint(fv[h + 1]),
+                                                __float_as_uint(fv[h + 2]), __float_as_uint(fv[h + 3])};
+            } else if constexpr (R == 2) {
+                *(uint2*)cp = uint2{__float_as_uint(fv[0]), __float_as_uint(fv[1])};
+            } else {
+                cp[0] = __float_as_uint(fv[0]);
+            }
+        }
+    }
+    put(0, 0);
+    __syncthreads();
+    // 3. class sums, one thread per (member, colour) of the staged group
+    for (int grp = 0; grp < ngroups; ++grp) {
+        const int buf = grp & 1;
+        if (grp + 1 < ngroups) fetch(grp + 1);
+        const int dg = grp * PM, mc = min(PM, D - dg);
+        const int16_t* gl = lists + buf * lst_stage;
+        const int32_t* go = offs + buf * off_stage;
+        for (int e = tid; e < mc * k; e += NT) {
             const int dm = e / k, l = e - dm * k;
-            const int beg = offs[dm * (k + 1) + l], end = offs[dm * (k + 1) + l + 1];
-            const int16_t* lv = lists + (size_t)dm * cs;
+            const int beg = go[dm * (k + 1) + l], end = go[dm * (k + 1) + l + 1];
+            const int16_t* lv = gl + (size_t)dm * cs;
+            float* out = Gg + ((size_t)(dg + dm) * n + i0) * k + l;
+            // the contraction's values, loaded before the sums that hide their latency
+            float prev[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) prev[r] = (accumulate && r < rows) ? out[(size_t)r * k] : 0.0f;
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] = 0.0f;
-            for (int q = beg; q < end; ++q) {
-                const int j = lv[q];
-                uint16_t cd[R];
-                if constexpr (R == 8) {
-                    const u32x4n v = *(const u32x4n*)(codes + (size_t)j * 8);
-                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            for (int q0 = beg & ~7; q0 < end; q0 += 8) {
+                const u32x4n w = *(const u32x4n*)(lv + q0);
+                const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+                // all eight reads first (slots outside the class read the zero row), then
+                // the additions in list order
+                float v[8][R];
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) cd[r] = (uint16_t)(w[r >> 1] >> (16 * (r & 1)));
-                } else if constexpr (R == 4) {
-                    const uint2 v = *(const uint2*)(codes + (size_t)j * 4);
-                    cd[0] = (uint16_t)v.x; cd[1] = (uint16_t)(v.x >> 16);
-                    cd[2] = (uint16_t)v.y; cd[3] = (uint16_t)(v.y >> 16);
-                } else if constexpr (R == 2) {
-                    const uint32_t v = *(const uint32_t*)(codes + (size_t)j * 2);
-                    cd[0] = (uint16_t)v; cd[1] = (uint16_t)(v >> 16);
-                } else {
-                    cd[0] = codes[j];
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + u;
+                    const int j = (q >= beg && q < end) ? (int)((wv[u >> 1] >> (16 * (u & 1))) & 0xFFFFu) : n_pad;
+                    const float* vj = vals + j * R;
+                    if constexpr (R >= 4) {
+#pragma unroll
+                        for (int h = 0; h < R; h += 4) {
+                            const float4 x = *(const float4*)(vj + h);
+                            v[u][h] = x.x; v[u][h + 1] = x.y; v[u][h + 2] = x.z; v[u][h + 3] = x.w;
+                        }
+                    } else if constexpr (R == 2) {
+                        const float2 x = *(const float2*)vj;
+                        v[u][0] = x.x; v[u][1] = x.y;
+                    } else {
+                        v[u][0] = vj[0];
+                    }
                 }
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (cd[r]) acc[r] += lut[cd[r]];
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += v[u][r];
             }
-            float* out = Gg + ((size_t)(dg + dm) * n + i0) * k + l;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < rows) out[(size_t)r * k] = acc[r];
+                if (r < rows) out[(size_t)r * k] = accumulate ? prev[r] + acc[r] : acc[r];
         }
+        if (grp + 1 < ngroups) put(grp + 1, buf ^ 1);
         __syncthreads();
     }
 }
@@ -970,7 +1095,7 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
 
 size_t prep_lds(int kmax, int nmax, int gather) {
     size_t b = sizeof(int) * (size_t)kmax;
-    if (gather) b += sizeof(int) * (size_t)(kmax + 1) + sizeof(int16_t) * (size_t)nmax;
+    if (gather) b += sizeof(int) * 4 * (size_t)kmax + sizeof(int16_t) * (size_t)nmax;
     return (b + 15) / 16 * 16;
 }
 
@@ -983,8 +1108,10 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int
 }
 
 hipError_t penalty_gather_prepare() {
-    const void* fns[] = {(const void*)k_pen_gather<1>, (const void*)k_pen_gather<2>, (const void*)k_pen_gather<4>,
-                         (const void*)k_pen_gather<8>};
+    const void* fns[] = {(const void*)k_pen_gather<1, 512>,  (const void*)k_pen_gather<2, 512>,
+                         (const void*)k_pen_gather<4, 512>,  (const void*)k_pen_gather<8, 512>,
+                         (const void*)k_pen_gather<1, 1024>, (const void*)k_pen_gather<2, 1024>,
+                         (const void*)k_pen_gather<4, 1024>, (const void*)k_pen_gather<8, 1024>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -993,25 +1120,38 @@ hipError_t penalty_gather_prepare() {
     return hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
 
-size_t penalty_gather_lds(int R, int M, int kmax, int dmax, int nmax) {
+size_t penalty_gather_lds(int R, int PM, int kmax, int dmax, int nmax) {
     const size_t n_pad = (size_t)round_up(nmax, kPadN), cs = (size_t)round_up(nmax, 64);
-    const size_t cts = (size_t)round_up(dmax, 8);
-    const size_t b = 2 * (size_t)R * cts + 2 * (size_t)R * n_pad + 2 * (size_t)M * cs +
-                     4 * (size_t)M * (kmax + 1) + 4 * 2 * (size_t)(dmax + 1);
+    const size_t vrows = n_pad + (R >= 4 ? 1 : 4 / R);
+    const size_t b = 4 * (size_t)R * vrows + 4 * (size_t)((2 * (dmax + 1) + 3) & ~3) + 2 * 2 * (size_t)PM * cs +
+                     4 * 2 * pg_off_words(PM, kmax);
     return (b + 15) / 16 * 16;
 }
 
-hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int M, size_t lds, int honor_stop,
-                                 hipStream_t s) {
+bool penalty_gather_group_fits(int PM, int kmax, int nmax) {
+    const long long cs = round_up(nmax, 64);
+    return (long long)PM * cs / 8 <= (long long)kPgMaxL * 512 &&
+           (long long)PM * (kmax + 1) <= (long long)kPgMaxO * 512;
+}
+
+hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int PM, size_t lds, int honor_stop,
+                                 int accumulate, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    if (M < 1 || lds > 160 * 1024) return hipErrorInvalidValue;
+    if (PM < 1 || lds > 160 * 1024) return hipErrorInvalidValue;
+    const bool wide = lds > 80 * 1024;     // one block per CU: 1024 threads
+#define TCOL_PG(RR)                                                                                     \
+    if (wide)                                                                                           \
+        k_pen_gather<RR, 1024><<<blocks, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate);    \
+    else                                                                                                \
+        k_pen_gather<RR, 512><<<blocks, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate);
     switch (R) {
-        case 1: k_pen_gather<1><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
-        case 2: k_pen_gather<2><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
-        case 4: k_pen_gather<4><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
-        case 8: k_pen_gather<8><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, M); break;
+        case 1: TCOL_PG(1) break;
+        case 2: TCOL_PG(2) break;
+        case 4: TCOL_PG(4) break;
+        case 8: TCOL_PG(8) break;
         default: return hipErrorInvalidValue;
     }
+#undef TCOL_PG
     return hipGetLastError();
 }
 

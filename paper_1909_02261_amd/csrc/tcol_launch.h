@@ -15,10 +15,14 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
 size_t prep_lds(int kmax, int nmax, int gather);
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s);
 hipError_t penalty_gather_prepare();
-// class-gather penalty rows: blocks of R rows (R in {1, 2, 4, 8}), member lists staged M at a time
-size_t penalty_gather_lds(int R, int M, int kmax, int dmax, int nmax);
-hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int M, size_t lds, int honor_stop,
-                                 hipStream_t s);
+// class-gather penalty rows: blocks of R rows (R in {1, 2, 4, 8}), class lists staged PM members at a time
+size_t penalty_gather_lds(int R, int PM, int kmax, int dmax, int nmax);
+// a group of PM members fits the kernel's per-thread staging registers
+bool penalty_gather_group_fits(int PM, int kmax, int nmax);
+// accumulate 0: rows written to G before the contraction (epilogue path); 1: added to the
+// contraction's G (fast path)
+hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int PM, size_t lds, int honor_stop,
+                                 int accumulate, hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
