@@ -30,7 +30,7 @@ class OrcParams(ctypes.Structure):
                 ("nb_iter", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("lam", ctypes.c_double), ("beta", ctypes.c_double), ("mu", ctypes.c_double),
                 ("nu", ctypes.c_double), ("bonus_diag", ctypes.c_int32),
-                ("stop_on_legal", ctypes.c_int32)]
+                ("stop_on_legal", ctypes.c_int32), ("momentum", ctypes.c_double)]
 
 
 def lib():
@@ -49,12 +49,15 @@ def lib():
         _lib.orc_fcolor.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
         _lib.orc_equity_bounds.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
         _lib.orc_feq.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.orc_fcut.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib.orc_fmscp.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
+        _lib.orc_fitness.argtypes = [P, P, P, P, P, P, P]
         _lib.orc_mtilde.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
         _lib.orc_grad_s.argtypes = [P, i64, P, P, P, P, P]
         _lib.orc_grad_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
-        _lib.orc_update.argtypes = [P, i64, P, P]
+        _lib.orc_update.argtypes = [P, i64, P, P, P]
         _lib.orc_loss.argtypes = [P, i64, P, P, P, P, P]
-        _lib.orc_iteration.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        _lib.orc_iteration.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         _lib.orc_iteration.restype = ctypes.c_int
         _lib.orc_run.argtypes = [P, P, P, P, ctypes.c_int, P, P]
         _lib.orc_run.restype = ctypes.c_int
@@ -85,6 +88,7 @@ class Params:
     nu: float = 0.0
     bonus_diag: int = 1
     stop_on_legal: int = 1
+    momentum: float = 0.0
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
@@ -94,7 +98,7 @@ class Params:
     def c_struct(self) -> OrcParams:
         return OrcParams(self.problem, self.n, self.k, self.D, self.eta, self.rho, self.nb_iter,
                          self.alpha, self.lam, self.beta, self.mu, self.nu, self.bonus_diag,
-                         self.stop_on_legal)
+                         self.stop_on_legal, self.momentum)
 
 
 def colors(W: np.ndarray) -> np.ndarray:
@@ -123,6 +127,36 @@ def fcolor(A: np.ndarray, c: np.ndarray) -> np.ndarray:
     f = np.zeros(D, dtype=np.int64)
     lib().orc_fcolor(D, n, _ptr(A), _ptr(c), _ptr(f))
     return f
+
+
+def fcut(A: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """Cut edges of each member's partition."""
+    A = _c(A, np.uint8)
+    c = _c(c, np.int16)
+    D, n = c.shape
+    f = np.zeros(D, dtype=np.int64)
+    lib().orc_fcut(D, n, _ptr(A), _ptr(c), _ptr(f))
+    return f
+
+
+def fmscp(V: np.ndarray) -> np.ndarray:
+    """Colour cost sum_l (l + 1) #V_dl of minimum sum colouring."""
+    V = _c(V, np.int32)
+    D, k = V.shape
+    f = np.zeros(D, dtype=np.int64)
+    lib().orc_fmscp(D, k, _ptr(V), _ptr(f))
+    return f
+
+
+def fitness(p: "Params", A: np.ndarray, c: np.ndarray):
+    """(fmain, fsec, f) of each member for the problem of p."""
+    A = _c(A, np.uint8)
+    c = _c(c, np.int16)
+    V = class_sizes(c, p.k)
+    fm = np.zeros(p.D, np.int64); fs = np.zeros(p.D, np.int64); f = np.zeros(p.D, np.int64)
+    ps = p.c_struct()
+    lib().orc_fitness(ctypes.byref(ps), _ptr(A), _ptr(c), _ptr(V), _ptr(fm), _ptr(fs), _ptr(f))
+    return fm, fs, f
 
 
 def equity_bounds(n: int, k: int):
@@ -164,16 +198,17 @@ def grad_w(W: np.ndarray, gS: np.ndarray) -> np.ndarray:
     return g
 
 
-def update(p: Params, t: int, W: np.ndarray, gW: np.ndarray) -> np.ndarray:
+def update(p: Params, t: int, W: np.ndarray, gW: np.ndarray, vel: Optional[np.ndarray] = None) -> np.ndarray:
+    """Step 4 on a copy of W; vel (FP64, updated in place) is the momentum state."""
     W = np.array(W, dtype=np.float64, copy=True)
     gW = _c(gW, np.float64)
     ps = p.c_struct()
-    lib().orc_update(ctypes.byref(ps), int(t), _ptr(W), _ptr(gW))
+    lib().orc_update(ctypes.byref(ps), int(t), _ptr(W), _ptr(gW), _ptr(vel))
     return W
 
 
 def loss(p: Params, t: int, A, Mt, fc, fe) -> np.ndarray:
-    """[L, sum f_color, sum f_eq, kappa, varpi]"""
+    """[L, sum fmain, sum fsec, kappa, varpi]; fc / fe are fmain / fsec of `fitness`."""
     A = _c(A, np.uint8); Mt = _c(Mt, np.int32)
     fc = _c(fc, np.int64); fe = _c(fe, np.int64)
     out = np.zeros(5, dtype=np.float64)
@@ -189,15 +224,17 @@ class IterResult:
     t: int
     colors: np.ndarray
     f: np.ndarray
-    f_color: np.ndarray
-    f_eq: np.ndarray
+    f_color: np.ndarray         # fmain: f_color, or f_cut for partitioning
+    f_eq: np.ndarray            # fsec: f_eq, f_mscp or 0
     gS: Optional[np.ndarray]
     gW: Optional[np.ndarray]
     legal_d: int
 
 
-def iteration(p: Params, t: int, A: np.ndarray, W: np.ndarray, want_grads: bool = True) -> IterResult:
-    """One iteration (steps 1-4) from weights W (any float dtype, upcast to FP64)."""
+def iteration(p: Params, t: int, A: np.ndarray, W: np.ndarray, want_grads: bool = True,
+              vel: Optional[np.ndarray] = None) -> IterResult:
+    """One iteration (steps 1-4) from weights W (any float dtype, upcast to FP64).  With
+    momentum, vel (FP64 [D, n, k], updated in place) is the velocity; zeros when omitted."""
     A = _c(A, np.uint8)
     Wd = np.array(W, dtype=np.float64, copy=True)
     D, n, k = Wd.shape
@@ -207,8 +244,12 @@ def iteration(p: Params, t: int, A: np.ndarray, W: np.ndarray, want_grads: bool 
     gS = np.zeros((D, n, k)) if want_grads else None
     gW = np.zeros((D, n, k)) if want_grads else None
     ld = np.zeros(1, np.int32)
+    if p.momentum != 0.0 and vel is None:
+        vel = np.zeros((D, n, k))
+    if vel is not None:
+        assert vel.dtype == np.float64 and vel.flags.c_contiguous and vel.shape == (D, n, k)
     ps = p.c_struct()
-    rc = lib().orc_iteration(ctypes.byref(ps), _ptr(tt), _ptr(A), _ptr(Wd), _ptr(c), _ptr(f),
+    rc = lib().orc_iteration(ctypes.byref(ps), _ptr(tt), _ptr(A), _ptr(Wd), _ptr(vel), _ptr(c), _ptr(f),
                              _ptr(fc), _ptr(fe), _ptr(gS), _ptr(gW), _ptr(ld))
     if rc < 0:
         raise RuntimeError(f"oracle iteration failed: {rc}")

@@ -24,6 +24,15 @@
  *    (t+1) mod nb_iter == 0;
  *  - an iteration whose population holds a legal member stops before its
  *    update, and the lowest such member is returned.
+ *
+ * Problems (Sections 3 and 6): 0 k-colouring (GCP step), 1 equitable colouring
+ * (ECP), 2 k-partitioning, 3 balanced k-partitioning, 4 minimum sum colouring.
+ * For partitioning every association matrix M is replaced by J - M, so the
+ * fitness is the number of cut edges and the group concentration enters the
+ * penalty and bonus as D - mt; the balanced variant adds the equity fitness.
+ * For minimum sum colouring the equity fitness is replaced by the colour cost
+ * sum_i z_{c(i)} with z_l = l + 1.  With momentum gamma > 0 the update is the
+ * heavy-ball step v <- gamma v + gW, W <- W - eta v (v starts at zero).
  */
 #include <math.h>
 #include <stdint.h>
@@ -31,14 +40,18 @@
 #include <string.h>
 
 typedef struct {
-    int32_t problem;   /* 0 = k-COL (GCP), 1 = equitable colouring (ECP) */
+    int32_t problem;   /* 0 k-COL, 1 ECP, 2 k-partitioning, 3 balanced k-partitioning, 4 min-sum colouring */
     int32_t n, k, D;
     double eta, rho;
     int32_t nb_iter;
     double alpha, lambda, beta, mu, nu;
     int32_t bonus_diag;
     int32_t stop_on_legal;
+    double momentum;   /* heavy-ball coefficient gamma in [0, 1); 0 = plain gradient step */
 } orc_params;
+
+static int is_partition(const orc_params *p) { return p->problem == 2 || p->problem == 3; }
+static int has_equity(const orc_params *p) { return p->problem == 1 || p->problem == 3; }
 
 /* Step 1 (vertex to colour assignment): c_d(i) = argmax_l W[d,i,l].
  * Returns 0, or -5 if some row holds a non-finite weight. */
@@ -107,6 +120,53 @@ void orc_feq(int D, int n, int k, const int32_t *V, int64_t *feq)
     }
 }
 
+/* Cut of a partition: f_cut(S_d) = 1/2 sum_ij a_ij (1 - m_dij), the number of
+ * edges {i, j} whose ends lie in different groups of member d. */
+void orc_fcut(int D, int n, const uint8_t *A, const int16_t *c, int64_t *fcut)
+{
+    for (int d = 0; d < D; ++d) {
+        const int16_t *cd = c + (size_t)d * n;
+        int64_t f = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (A[(size_t)i * n + j] && cd[i] != cd[j])
+                    f += 1;
+        fcut[d] = f;
+    }
+}
+
+/* Colour cost of minimum sum colouring: f_mscp(S_d) = sum_i z_{c_d(i)} with
+ * z_l = l + 1, i.e. sum_l (l + 1) #V_dl. */
+void orc_fmscp(int D, int k, const int32_t *V, int64_t *fsum)
+{
+    for (int d = 0; d < D; ++d) {
+        int64_t f = 0;
+        for (int l = 0; l < k; ++l)
+            f += (int64_t)(l + 1) * V[(size_t)d * k + l];
+        fsum[d] = f;
+    }
+}
+
+/* Fitness of each member for the problem: fmain is f_color (colouring) or
+ * f_cut (partitioning), fsec the added term (f_eq, f_mscp or 0), f their sum. */
+void orc_fitness(const orc_params *p, const uint8_t *A, const int16_t *c, const int32_t *V,
+                 int64_t *fmain, int64_t *fsec, int64_t *f)
+{
+    const int n = p->n, k = p->k, D = p->D;
+    if (is_partition(p))
+        orc_fcut(D, n, A, c, fmain);
+    else
+        orc_fcolor(D, n, A, c, fmain);
+    if (has_equity(p))
+        orc_feq(D, n, k, V, fsec);
+    else if (p->problem == 4)
+        orc_fmscp(D, k, V, fsec);
+    else
+        memset(fsec, 0, sizeof(int64_t) * D);
+    for (int d = 0; d < D; ++d)
+        f[d] = fmain[d] + fsec[d];
+}
+
 /* Group concentration matrix: mt_ij = sum_d m_dij = #{d : c_d(i) = c_d(j)}. */
 void orc_mtilde(int D, int n, const int16_t *c, int32_t *Mt)
 {
@@ -137,9 +197,13 @@ static double dfeq(int32_t v, int32_t c1, int32_t c2)
     return 0.0;
 }
 
-/* Gradient of the global loss with respect to the one-hot tensor S:
- *   gS = A.S + nu t grad f_eq + 2 alpha lambda t (A o Mt^(alpha-1)).S
- *        - 2 beta mu t ((J - A) o Mt^(beta-1)).S
+/* Gradient of the global loss with respect to the one-hot tensor S,
+ * colouring problems:
+ *   gS = A.S + 2 alpha lambda t (A o Mt^(alpha-1)).S
+ *        - 2 beta mu t ((J - A) o Mt^(beta-1)).S + nu t (grad f_eq or z)
+ * partitioning (M -> J - M, so mt -> D - mt and the fitness is the cut):
+ *   gS = -A.S - 2 alpha lambda t (A o (D - Mt)^(alpha-1)).S
+ *        + 2 beta mu t ((J - A) o (D - Mt)^(beta-1)).S [+ nu t grad f_eq]
  * evaluated at the hard assignment of step 1.  The two element-wise powered
  * n x n matrices are formed once, then each product with S_d is the sum over
  * the vertices j that member d colours l.  gS is [D][n][k]. */
@@ -151,15 +215,17 @@ void orc_grad_s(const orc_params *p, int64_t t, const uint8_t *A, const int16_t 
     const double cpen = 2.0 * p->alpha * p->lambda * tt;
     const double cbon = 2.0 * p->beta * p->mu * tt;
     const double ceq = p->nu * tt;
+    const int part = is_partition(p);
+    const double sgn = part ? -1.0 : 1.0;
     int32_t c1, c2;
     orc_equity_bounds(n, k, &c1, &c2);
-    /* P = A o Mt^(alpha-1), Q = (J - A) o Mt^(beta-1) */
+    /* P = A o X^(alpha-1), Q = (J - A) o X^(beta-1), X = Mt or D - Mt */
     double *P = (double *)calloc((size_t)n * n, sizeof(double));
     double *Q = (double *)calloc((size_t)n * n, sizeof(double));
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             const size_t e = (size_t)i * n + j;
-            const double m = (double)Mt[e];
+            const double m = part ? (double)(D - Mt[e]) : (double)Mt[e];
             if (A[e])
                 P[e] = pow0(m, p->alpha - 1.0);
             else if (j != i || p->bonus_diag)
@@ -175,13 +241,16 @@ void orc_grad_s(const orc_params *p, int64_t t, const uint8_t *A, const int16_t 
             const double *Qi = Q + (size_t)i * n;
             for (int j = 0; j < n; ++j) {
                 const int l = cd[j];
-                g[l] += (double)Ai[j];          /* gamma matrix term */
-                g[l] += cpen * Pi[j];           /* shared-conflict penalisation */
-                g[l] -= cbon * Qi[j];           /* shared-assignment bonus */
+                g[l] += sgn * (double)Ai[j];    /* gamma matrix term */
+                g[l] += sgn * cpen * Pi[j];     /* shared-conflict (shared-cut) penalisation */
+                g[l] -= sgn * cbon * Qi[j];     /* shared-assignment (shared-split) bonus */
             }
-            if (p->problem == 1)
+            if (has_equity(p))
                 for (int l = 0; l < k; ++l)
                     g[l] += ceq * dfeq(V[(size_t)d * k + l], c1, c2);
+            else if (p->problem == 4)
+                for (int l = 0; l < k; ++l)
+                    g[l] += ceq * (double)(l + 1);
         }
     }
     free(P);
@@ -218,45 +287,55 @@ void orc_grad_w(int D, int n, int k, const double *W, const double *gS, double *
     free(sh);
 }
 
-/* Step 4 iii-iv: W <- W - eta gW, then W <- W / rho after the update of
- * iteration t when (t+1) mod nb_iter == 0. */
-void orc_update(const orc_params *p, int64_t t, double *W, const double *gW)
+/* Step 4 iii-iv: W <- W - eta gW (or, with momentum gamma > 0, v <- gamma v +
+ * gW and W <- W - eta v), then W <- W / rho after the update of iteration t
+ * when (t+1) mod nb_iter == 0.  vel [D*n*k] is the velocity (unused when
+ * gamma = 0). */
+void orc_update(const orc_params *p, int64_t t, double *W, const double *gW, double *vel)
 {
     const size_t cnt = (size_t)p->D * p->n * p->k;
     const int smooth = p->nb_iter > 0 && ((t + 1) % p->nb_iter) == 0;
     for (size_t e = 0; e < cnt; ++e) {
-        double w = W[e] - p->eta * gW[e];
+        double step = gW[e];
+        if (p->momentum != 0.0) {
+            vel[e] = p->momentum * vel[e] + gW[e];
+            step = vel[e];
+        }
+        double w = W[e] - p->eta * step;
         if (smooth)
             w = w / p->rho;
         W[e] = w;
     }
 }
 
-/* Global loss L(t) = f_color + nu t f_eq + lambda t kappa - mu t varpi with
- * kappa = sum_ij a_ij mt_ij^alpha and varpi = sum_ij (1 - a_ij) mt_ij^beta.
- * out = {L, sum f_color, sum f_eq, kappa, varpi}. */
+/* Global loss L(t) = sum fmain + nu t sum fsec + lambda t kappa - mu t varpi,
+ * with kappa = sum_ij a_ij x_ij^alpha and varpi = sum_ij (1 - a_ij) x_ij^beta
+ * (the diagonal in varpi only with bonus_diag), x = mt (colouring) or D - mt
+ * (partitioning); fmain is f_color or f_cut, fsec f_eq, f_mscp or 0 (k-COL,
+ * where the nu term is absent).  out = {L, sum fmain, sum fsec, kappa, varpi}. */
 void orc_loss(const orc_params *p, int64_t t, const uint8_t *A, const int32_t *Mt,
-              const int64_t *fcol, const int64_t *feq, double *out)
+              const int64_t *fmain, const int64_t *fsec, double *out)
 {
     const int n = p->n, D = p->D;
+    const int part = is_partition(p);
     double sf = 0.0, se = 0.0, kappa = 0.0, varpi = 0.0;
     for (int d = 0; d < D; ++d) {
-        sf += (double)fcol[d];
-        se += (double)feq[d];
+        sf += (double)fmain[d];
+        se += (double)fsec[d];
     }
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
-            const double m = (double)Mt[(size_t)i * n + j];
+            const int32_t mt = Mt[(size_t)i * n + j];
+            const double m = part ? (double)(D - mt) : (double)mt;
             if (A[(size_t)i * n + j])
                 kappa += pow0(m, p->alpha);
             else if (j != i || p->bonus_diag)
                 varpi += pow0(m, p->beta);
         }
     const double tt = (double)t;
-    const double eq = p->problem == 1 ? se : 0.0;
-    out[0] = sf + p->nu * tt * eq + p->lambda * tt * kappa - p->mu * tt * varpi;
+    out[0] = sf + p->nu * tt * se + p->lambda * tt * kappa - p->mu * tt * varpi;
     out[1] = sf;
-    out[2] = eq;
+    out[2] = se;
     out[3] = kappa;
     out[4] = varpi;
 }
@@ -289,41 +368,46 @@ static void work_free(orc_work *w)
 }
 
 /* One iteration of the algorithm on member weights W (updated in place).
- * Outputs (any may be NULL): colours c [D*n], fitness f = f_color + f_eq [D],
- * f_color [D], f_eq [D], the gradients gS and gW [D*n*k] of this iteration.
- * Returns 1 if the population held a legal member (no update; *legal_d set to
- * the lowest such member when stop_on_legal), 0 after an update, or a
- * negative error (-5 non-finite weight, -6 out of memory). */
-int orc_iteration(const orc_params *p, int64_t *t, const uint8_t *A, double *W,
-                  int16_t *c_out, int64_t *f_out, int64_t *fcol_out, int64_t *feq_out,
+ * Outputs (any may be NULL): colours c [D*n], fitness f = fmain + fsec [D],
+ * fmain (f_color or f_cut) [D], fsec (f_eq, f_mscp or 0) [D], the gradients gS
+ * and gW [D*n*k] of this iteration.  vel [D*n*k] is the momentum state (may be
+ * NULL when momentum = 0).  Returns 1 if the population held a member with
+ * f = 0 (no update; *legal_d set to the lowest such member when
+ * stop_on_legal), 0 after an update, or a negative error (-5 non-finite
+ * weight, -6 out of memory). */
+int orc_iteration(const orc_params *p, int64_t *t, const uint8_t *A, double *W, double *vel,
+                  int16_t *c_out, int64_t *f_out, int64_t *fmain_out, int64_t *fsec_out,
                   double *gS_out, double *gW_out, int32_t *legal_d)
 {
     const int n = p->n, k = p->k, D = p->D;
+    if (p->momentum != 0.0 && !vel)
+        return -1;
     orc_work w;
     if (work_alloc(p, &w)) {
         work_free(&w);
         return -6;
     }
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * D);
+    if (!f) {
+        work_free(&w);
+        return -6;
+    }
     int rc = orc_colors(D, n, k, W, w.c);
     if (rc) {
+        free(f);
         work_free(&w);
         return rc;
     }
     orc_class_sizes(D, n, k, w.c, w.V);
-    orc_fcolor(D, n, A, w.c, w.fcol);
-    if (p->problem == 1)
-        orc_feq(D, n, k, w.V, w.feq);
-    else
-        memset(w.feq, 0, sizeof(int64_t) * D);
+    orc_fitness(p, A, w.c, w.V, w.fcol, w.feq, f);
     int best = -1;
-    for (int d = 0; d < D; ++d) {
-        const int64_t f = w.fcol[d] + w.feq[d];
-        if (f_out) f_out[d] = f;
-        if (f == 0 && best < 0) best = d;
-    }
+    for (int d = 0; d < D; ++d)
+        if (f[d] == 0 && best < 0) best = d;
+    if (f_out) memcpy(f_out, f, sizeof(int64_t) * D);
+    free(f);
     if (c_out) memcpy(c_out, w.c, sizeof(int16_t) * (size_t)D * n);
-    if (fcol_out) memcpy(fcol_out, w.fcol, sizeof(int64_t) * D);
-    if (feq_out) memcpy(feq_out, w.feq, sizeof(int64_t) * D);
+    if (fmain_out) memcpy(fmain_out, w.fcol, sizeof(int64_t) * D);
+    if (fsec_out) memcpy(fsec_out, w.feq, sizeof(int64_t) * D);
     if (legal_d) *legal_d = best;
     if (best >= 0 && p->stop_on_legal) {
         work_free(&w);
@@ -334,27 +418,29 @@ int orc_iteration(const orc_params *p, int64_t *t, const uint8_t *A, double *W,
     orc_grad_w(D, n, k, W, w.gS, w.gW);
     if (gS_out) memcpy(gS_out, w.gS, sizeof(double) * (size_t)D * n * k);
     if (gW_out) memcpy(gW_out, w.gW, sizeof(double) * (size_t)D * n * k);
-    orc_update(p, *t, W, w.gW);
+    orc_update(p, *t, W, w.gW, vel);
     *t += 1;
     work_free(&w);
     return 0;
 }
 
-/* Algorithm loop: up to max_steps iterations.  Returns the number of updates
- * performed; *legal_d is the returned member (or -1) and colors_out [n] its
- * colouring when one was found. */
+/* Algorithm loop: up to max_steps iterations (momentum state from zero).
+ * Returns the number of updates performed; *legal_d is the returned member (or
+ * -1) and colors_out [n] its colouring when one was found. */
 int orc_run(const orc_params *p, int64_t *t, const uint8_t *A, double *W, int max_steps,
             int32_t *legal_d, int16_t *colors_out)
 {
     const int n = p->n, D = p->D;
     int16_t *c = (int16_t *)malloc(sizeof(int16_t) * (size_t)D * n);
+    double *vel = p->momentum != 0.0 ? (double *)calloc((size_t)D * n * p->k, sizeof(double)) : NULL;
     int done = 0;
     *legal_d = -1;
     for (int s = 0; s < max_steps; ++s) {
         int32_t ld = -1;
-        int rc = orc_iteration(p, t, A, W, c, NULL, NULL, NULL, NULL, NULL, &ld);
+        int rc = orc_iteration(p, t, A, W, vel, c, NULL, NULL, NULL, NULL, NULL, &ld);
         if (rc < 0) {
             free(c);
+            free(vel);
             return rc;
         }
         if (rc == 1) {
@@ -366,5 +452,6 @@ int orc_run(const orc_params *p, int64_t *t, const uint8_t *A, double *W, int ma
         done += 1;
     }
     free(c);
+    free(vel);
     return done;
 }

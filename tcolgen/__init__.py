@@ -241,7 +241,7 @@ def fd_entries(count: int, D: int, n: int, k: int, seed: int) -> np.ndarray:
 # on, as synthetic stand-ins (DIMACS-like G(n, p), flat planted graphs)
 # ----------------------------------------------------------------------------
 
-KCOL, ECP = 0, 1
+KCOL, ECP, KPART, BKPART, MSCP = 0, 1, 2, 3, 4
 FP32, BF16, FP8, FP4 = 0, 1, 2, 3
 
 
@@ -267,6 +267,7 @@ class GraphCase:
     nu: float = 0.0
     bonus_diag: int = 1
     stop_on_legal: int = 1
+    momentum: float = 0.0
 
     def adjacency(self) -> np.ndarray:
         if self.graph == "gnp":
@@ -289,7 +290,7 @@ class GraphCase:
         return dict(problem=self.problem, precision=self.precision, n=self.n, k=self.k, D=self.D,
                     eta=self.eta, rho=self.rho, nb_iter=self.nb_iter, alpha=self.alpha,
                     lam=self.lam, beta=self.beta, mu=self.mu, nu=self.nu,
-                    bonus_diag=self.bonus_diag, stop_on_legal=self.stop_on_legal)
+                    bonus_diag=self.bonus_diag, stop_on_legal=self.stop_on_legal, momentum=self.momentum)
 
 
 def paper_gcp(**kw) -> dict:

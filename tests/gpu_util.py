@@ -20,7 +20,7 @@ def lib_params(case_params: dict):
 def orc_params(case_params: dict) -> oracle.Params:
     """Oracle parameters with the real-valued ones rounded to fp32, as the C ABI carries them."""
     d = dict(case_params)
-    for key in ("eta", "rho", "alpha", "lam", "beta", "mu", "nu"):
+    for key in ("eta", "rho", "alpha", "lam", "beta", "mu", "nu", "momentum"):
         d[key] = float(np.float32(d[key]))
     return oracle.Params.from_dict(d)
 

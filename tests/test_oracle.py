@@ -231,7 +231,7 @@ def test_gamma_matrix_term():
         assert gS[d, np.arange(n), c[d]].sum() == 2 * f[d]
 
 
-@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0), (1, 0)])
+@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0), (1, 0), (2, 1), (3, 1), (3, 0), (4, 1)])
 def test_grad_s_matches_literal(problem, diag):
     rng = np.random.default_rng(10 + problem + 2 * diag)
     D, n, k = 4, 23, 5
@@ -245,7 +245,7 @@ def test_grad_s_matches_literal(problem, diag):
     np.testing.assert_allclose(gS, lit, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0)])
+@pytest.mark.parametrize("problem,diag", [(0, 1), (1, 1), (0, 0), (2, 1), (3, 1), (3, 0), (4, 1)])
 def test_grad_s_finite_differences(problem, diag):
     """Central differences (h = 1e-3) of the paper's loss, as a polynomial in S, at the hard S."""
     rng = np.random.default_rng(20 + problem)
@@ -316,14 +316,13 @@ def test_update_and_smoothing_schedule():
 
 def test_loss_matches_literal():
     rng = np.random.default_rng(12)
-    for problem in (0, 1):
+    for problem in (0, 1, 2, 3, 4):
         D, n, k = 4, 20, 4
         A = tcolgen.gnp(n, 0.5, 51)
         c = rng.integers(0, k, size=(D, n)).astype(np.int16)
         p = rand_params(problem, n, k, D)
         Mt = oracle.mtilde(c)
-        fc = oracle.fcolor(A, c)
-        fe = oracle.feq(oracle.class_sizes(c, k), n)
+        fc, fe, _ = oracle.fitness(p, A, c)
         out = oracle.loss(p, 6, A, Mt, fc, fe)
         lit = literal.global_loss(A.astype(float), onehot(c, k), 6, p.alpha, p.lam, p.beta, p.mu,
                                   p.nu, problem)
@@ -369,7 +368,7 @@ def test_invariances():
 
 def test_iteration_composes_steps_and_matches_literal():
     rng = np.random.default_rng(14)
-    for problem in (0, 1):
+    for problem in (0, 1, 2, 3, 4):
         D, n, k = 3, 18, 4
         A = tcolgen.gnp(n, 0.5, 71)
         W = rng.standard_normal((D, n, k)) * 0.01
@@ -429,3 +428,128 @@ def test_mycielski_toy_reaches_legal():
     Wf, t, done, ld, col = oracle.run(p, 0, A, W, 20000)
     assert ld == 0
     assert oracle.fcolor(A, col[None, :])[0] == 0
+
+
+# ------------------------------------------------- other problems (Section 6) --
+
+@pytest.mark.parametrize("n,k,seed", [(5, 2, 0), (6, 3, 1), (6, 2, 2)])
+def test_cut_exhaustive_all_partitions(n, k, seed):
+    """f_cut by brute force over edges for every k-partition of small graphs, against the
+    literal 1/2 sum(A o (J - M)) and |E| - f_color."""
+    A = tcolgen.gnp(n, 0.6, 200 + seed)
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if A[i, j]]
+    cols = np.array(list(itertools.product(range(k), repeat=n)), dtype=np.int16)
+    got = oracle.fcut(A, cols)
+    want = np.array([sum(1 for i, j in edges if c[i] != c[j]) for c in cols], dtype=np.int64)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, len(edges) - oracle.fcolor(A, cols))
+    lit = literal.fitness_cut(A.astype(float), onehot(cols, k))
+    assert np.array_equal(got, lit.astype(np.int64))
+
+
+def test_partition_single_member_identities():
+    """D = 1, partitioning: D - mt is 1 across groups and 0 inside, so kappa = 2 f_cut and
+    varpi counts the ordered non-adjacent pairs split across groups."""
+    rng = np.random.default_rng(31)
+    for trial in range(8):
+        n, k = int(rng.integers(5, 30)), int(rng.integers(2, 6))
+        A = tcolgen.gnp(n, 0.4, 300 + trial)
+        c = rng.integers(0, k, size=(1, n)).astype(np.int16)
+        p = oracle.Params(problem=2, n=n, k=k, D=1, alpha=2.5, beta=1.2, lam=1, mu=1)
+        fm, fs, f = oracle.fitness(p, A, c)
+        out = oracle.loss(p, 0, A, oracle.mtilde(c), fm, fs)
+        split = sum(1 for i in range(n) for j in range(n) if i != j and not A[i, j] and c[0, i] != c[0, j])
+        assert out[3] == pytest.approx(2 * fm[0], abs=1e-12)
+        assert out[4] == pytest.approx(split, abs=1e-12)
+        assert fs[0] == 0 and f[0] == fm[0]
+
+
+def test_balanced_partition_fitness_adds_equity():
+    rng = np.random.default_rng(32)
+    n, k, D = 23, 4, 5
+    A = tcolgen.gnp(n, 0.5, 33)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    p = oracle.Params(problem=3, n=n, k=k, D=D)
+    fm, fs, f = oracle.fitness(p, A, c)
+    assert np.array_equal(fm, oracle.fcut(A, c))
+    assert np.array_equal(fs, literal.equity_fitness(onehot(c, k)).astype(np.int64))
+    assert np.array_equal(f, fm + fs)
+
+
+def test_mscp_fitness_closed_forms():
+    """f_mscp = sum_i (c(i) + 1): n with every vertex in colour 0, and sum_l (l + 1) #V_l."""
+    n, k = 17, 5
+    A = tcolgen.gnp(n, 0.5, 34)
+    p = oracle.Params(problem=4, n=n, k=k, D=2)
+    c = np.zeros((2, n), np.int16)
+    c[1] = np.arange(n) % k
+    fm, fs, f = oracle.fitness(p, A, c)
+    assert fs[0] == n
+    assert fs[1] == sum((i % k) + 1 for i in range(n))
+    assert np.array_equal(fm, oracle.fcolor(A, c)) and np.array_equal(f, fm + fs)
+    assert np.array_equal(fs, literal.fitness_mscp(onehot(c, k)).astype(np.int64))
+
+
+def test_partition_invariances():
+    """Relabelling the groups of a member leaves the cut and D - Mt unchanged, and permutes
+    the gradient's group axis."""
+    rng = np.random.default_rng(35)
+    D, n, k = 3, 21, 4
+    A = tcolgen.gnp(n, 0.5, 36)
+    c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+    p = rand_params(3, n, k, D)
+    gS = oracle.grad_s(p, 4, A, c, oracle.mtilde(c), oracle.class_sizes(c, k))
+    perm = rng.permutation(k)
+    c2 = c.copy(); c2[0] = perm[c[0]]
+    assert np.array_equal(oracle.fcut(A, c2), oracle.fcut(A, c))
+    gS2 = oracle.grad_s(p, 4, A, c2, oracle.mtilde(c2), oracle.class_sizes(c2, k))
+    np.testing.assert_allclose(gS2[0][:, perm], gS[0], rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------- momentum (Section 7) --
+
+@pytest.mark.parametrize("gamma", [0.5, 0.9])
+def test_momentum_matches_torch_sgd(gamma):
+    """Heavy-ball steps: the oracle's iterations with momentum gamma equal torch.optim.SGD
+    (momentum=gamma, dampening 0) fed the oracle's straight-through gradient each step
+    (smoothing off: nb_iter beyond the run)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(40)
+    D, n, k = 3, 16, 4
+    A = tcolgen.gnp(n, 0.5, 41)
+    W0 = rng.standard_normal((D, n, k)) * 0.05
+    p = rand_params(1, n, k, D, eta=0.05, nb_iter=1000, stop_on_legal=0, momentum=gamma)
+    vel = np.zeros((D, n, k))
+    Wo, t = W0.copy(), 0
+    Wt = torch.tensor(W0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.SGD([Wt], lr=p.eta, momentum=gamma, dampening=0.0)
+    for step in range(6):
+        W_np = Wt.detach().numpy()
+        c = oracle.colors(W_np)
+        gS = oracle.grad_s(p, step, A, c, oracle.mtilde(c), oracle.class_sizes(c, k))
+        opt.zero_grad()
+        Wt.grad = torch.tensor(oracle.grad_w(W_np, gS))
+        opt.step()
+        r = oracle.iteration(p, t, A, Wo, vel=vel)
+        Wo, t = r.W, r.t
+        np.testing.assert_allclose(Wo, Wt.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_momentum_zero_is_plain_and_row_sums_kept():
+    """gamma = 0 is the plain step; with momentum the velocity rows sum to zero like gW, so
+    the weight row sums stay put between smoothings."""
+    rng = np.random.default_rng(42)
+    D, n, k = 2, 12, 5
+    A = tcolgen.gnp(n, 0.5, 43)
+    W = rng.standard_normal((D, n, k)) * 0.05
+    p0 = rand_params(0, n, k, D, stop_on_legal=0, nb_iter=1000)
+    pm = rand_params(0, n, k, D, stop_on_legal=0, nb_iter=1000, momentum=0.0)
+    np.testing.assert_array_equal(oracle.iteration(p0, 2, A, W).W, oracle.iteration(pm, 2, A, W).W)
+    pg = rand_params(0, n, k, D, stop_on_legal=0, nb_iter=1000, momentum=0.8, eta=0.1)
+    vel = np.zeros((D, n, k))
+    Wi, t = W.copy(), 0
+    for _ in range(5):
+        r = oracle.iteration(pg, t, A, Wi, vel=vel)
+        Wi, t = r.W, r.t
+    assert np.abs(vel.sum(axis=2)).max() < 1e-12
+    np.testing.assert_allclose(Wi.sum(axis=2), W.sum(axis=2), atol=1e-12)
