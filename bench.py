@@ -31,6 +31,9 @@ GEMM_SRC = os.path.join(ROOT, "paper_1909_02261_amd", "csrc", "tcol_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_hbm_traffic.txt")
 HBM_PEAK = 8.0e12
 PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8, "fp4": tcolgen.FP4}
+PROBLEMS = {"kcol": tcolgen.KCOL, "ecp": tcolgen.ECP, "kpart": tcolgen.KPART, "bkpart": tcolgen.BKPART,
+            "mscp": tcolgen.MSCP}
+PROBLEM_NAMES = {0: "k-COL", 1: "ECP", 2: "k-partitioning", 3: "balanced k-partitioning", 4: "min-sum colouring"}
 
 
 def workload(name: str, prec: str):
@@ -90,11 +93,12 @@ def cpu_baseline(case, A, W0, budget_s: float):
     import oracle
     p = oracle.Params.from_dict(case.params())
     W = W0.astype(np.float64)
+    vel = np.zeros_like(W) if p.momentum else None
     t = 0
     steps = 0
     t0 = time.perf_counter()
     while True:
-        r = oracle.iteration(p, t, A, W, want_grads=False)
+        r = oracle.iteration(p, t, A, W, want_grads=False, vel=vel)
         W, t = r.W, r.t
         steps += 1
         el = time.perf_counter() - t0
@@ -158,6 +162,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
     ap.add_argument("--penalty", default="dense", choices=["auto", "dense", "gather"])
+    ap.add_argument("--problem", default=None, choices=list(PROBLEMS),
+                    help="run the workload's graph and sizes as another problem (default: its own)")
+    ap.add_argument("--momentum", type=float, default=0.0, help="heavy-ball coefficient (0: plain step)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -187,6 +194,15 @@ def main():
 
     prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp4", "c4": "bf16", "c5": "fp4"}[args.workload]
     case = workload(args.workload, prec)
+    if args.problem is not None and PROBLEMS[args.problem] != case.problem:
+        # same graph and sizes, another problem; the added term (equity or colour cost) takes
+        # the ECP's nu of the paper's parameter table
+        case.problem = PROBLEMS[args.problem]
+        case.nu = 1e-5 if case.problem in (tcolgen.ECP, tcolgen.BKPART, tcolgen.MSCP) else 0.0
+        case.name = args.problem + "_" + case.name.split("_", 1)[1]
+    if args.momentum:
+        case.momentum = args.momentum
+        case.name += f"_mom{args.momentum:g}"
     print(f"[bench] workload {case.name} precision {prec}: generating inputs", file=sys.stderr, flush=True)
     A = case.adjacency()
     W0 = case.weights()
@@ -220,13 +236,15 @@ def main():
     ph = s.profile(args.profile_steps, as_only=True)
     t_now = s.get_t()
     f_as, f_pen = gemm_flops(case, t_now)
+    if opts["penalty"] == 2:
+        f_pen = 0.0          # the class gather, not the contraction, computes the penalty term
     gemm_s = ph["gemm"] / 1e3
     achieved = (f_as + f_pen) / gemm_s
     peak = mixed_peak(prec, f_as, f_pen)
     as_s = ph["gemm_as_only"] / 1e3
     roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": None,
-            "kernel": "k_gemm (A.S pass + penalty pass + fitness gather)",
+            "kernel": "k_gemm (A.S pass + penalty pass + fitness gather)" if f_pen else "k_gemm (A.S pass + fitness gather)",
             "flops_per_launch": f_as + f_pen, "ms_per_launch": ph["gemm"]}
     roof_as = {"bound": "mfma", "achieved": f_as / as_s / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
                "frac": f_as / as_s / PEAK[prec], "ms_per_launch": ph["gemm_as_only"]}
@@ -246,10 +264,12 @@ def main():
         print(f"[bench] oracle baseline ({args.cpu_seconds:.0f} s budget)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(case, A, W0, args.cpu_seconds)
 
-    config = {"workload": case.name, "problem": "k-COL" if case.problem == 0 else "ECP", "n": case.n,
+    config = {"workload": case.name, "problem": PROBLEM_NAMES[case.problem], "n": case.n,
               "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
               "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
               "penalty": {0: "auto", 1: "dense", 2: "gather"}[opts["penalty"]], "fused": opts["fused"]}
+    if case.momentum:
+        config["momentum"] = case.momentum
     roof["traffic"] = measured_traffic(config)
     out = {
         "metric": "population-iterations/s (D*steps/s)",

@@ -60,9 +60,18 @@ enum {
     TCOL_ESTATE = -7       /* call not valid in the current state */
 };
 
-/* Problem statement (Sections 3.1-3.2): k-COL is one step of the GCP (fitness =
- * conflicts); the ECP adds the equity fitness to the fitness and the loss. */
-enum { TCOL_KCOL = 0, TCOL_ECP = 1 };
+/* Problem statement.  k-COL is one step of the GCP (Sections 3.1-3.2: fitness =
+ * conflicting edges f_color); the ECP adds the equity fitness f_eq to the
+ * fitness and nu t f_eq to the loss.  Section 6: k-partitioning replaces every
+ * association matrix M by J - M, so the fitness is the number of cut edges
+ * |E| - f_color, the group concentration enters the penalty and bonus as
+ * D - Mt, and the gradient of the fitness term is -A.S; balanced k-partitioning
+ * adds the equity fitness as the ECP does; minimum sum colouring replaces the
+ * equity fitness by the colour cost sum_i z_{c(i)} with z_l = l + 1 (colours
+ * counted from 0), whose gradient is nu t z_l.  "Main" fitness below means
+ * f_color (colouring problems) or the cut (partitioning), "added" fitness f_eq,
+ * the colour cost or 0; a member is legal when their sum is 0. */
+enum { TCOL_KCOL = 0, TCOL_ECP = 1, TCOL_KPART = 2, TCOL_BKPART = 3, TCOL_MSCP = 4 };
 
 /* Operand precision of the contractions A.S and (penalty).S.  The 0/1
  * operands A and S are exact in every format and accumulate in FP32, so the
@@ -86,6 +95,10 @@ typedef struct {
     float nu;               /* equity weight >= 0 (ECP) */
     int32_t bonus_diag;     /* 1: bonus matrix J - A includes i = j (literal); 0: excludes it */
     int32_t stop_on_legal;  /* 1: Algorithm 1 stop rule; 0: never stop (timing) */
+    float momentum;         /* heavy-ball coefficient gamma in [0, 1) (Section 7: optimiser
+                               variants): v <- gamma v + gW, W <- W - eta v, v from zero;
+                               0 = the paper's plain step.  With gamma > 0 the epilogue
+                               step schedule is not used (the fast one runs instead) */
 } tcol_graph_params;
 
 /* Execution options of a context. */
@@ -155,17 +168,21 @@ tcol_status tcol_step(tcol_ctx *ctx, int32_t max_steps, int32_t *steps_done, int
                       int16_t *const *colors_out_dev);
 
 /* Steps 1-2 only, on the current W of graph g (W unchanged, t unchanged):
- *   colors_dev  (D*n int16, may be NULL) argmax colours c_d(i);
- *   f_color_dev (D int64, may be NULL) conflicts per member, computed from the
- *               contraction A.S as 1/2 sum_i (A.S_d)[i, c_d(i)];
- *   f_eq_dev    (D int64, may be NULL) equity fitness per member (0 for k-COL).
+ *   colors_dev (D*n int16, may be NULL) argmax colours c_d(i);
+ *   f_main_dev (D int64, may be NULL) main fitness per member: f_color, computed
+ *              from the contraction A.S as 1/2 sum_i (A.S_d)[i, c_d(i)], or for
+ *              partitioning the cut |E| - f_color;
+ *   f_sec_dev  (D int64, may be NULL) added fitness per member: f_eq (ECP,
+ *              balanced partitioning), the colour cost (minimum sum colouring)
+ *              or 0.
  * Asynchronous.  Errors: TCOL_EINVAL. */
-tcol_status tcol_conflicts(tcol_ctx *ctx, int32_t g, int16_t *colors_dev, int64_t *f_color_dev,
-                           int64_t *f_eq_dev);
+tcol_status tcol_conflicts(tcol_ctx *ctx, int32_t g, int16_t *colors_dev, int64_t *f_main_dev,
+                           int64_t *f_sec_dev);
 
 /* Loss and gradients of graph g at its current W and t (no update):
- *   loss_dev  (5 doubles, may be NULL): L, sum f_color, sum f_eq, kappa, varpi
- *             (eq. global loss; FP64 reduction on the GPU);
+ *   loss_dev  (5 doubles, may be NULL): L, sum of the main fitness, sum of the
+ *             added fitness, kappa, varpi (eq. global loss, with Mt -> D - Mt
+ *             in kappa and varpi for partitioning; FP64 reduction on the GPU);
  *   gradS_dev (D*n*k fp32, may be NULL): gradient of L with respect to S;
  *   gradW_dev (D*n*k fp32, may be NULL): straight-through gradient with respect to W.
  * Asynchronous.  Errors: TCOL_EINVAL. */
@@ -177,7 +194,8 @@ tcol_status tcol_loss_grad(tcol_ctx *ctx, int32_t g, double *loss_dev, float *gr
 tcol_status tcol_mtilde(tcol_ctx *ctx, int32_t g, int32_t *mt_dev);
 
 /* Iteration counter of graph g (checkpoint / resume: the state is W and t).
- * tcol_get_t synchronises the stream. */
+ * tcol_set_t also clears the graph's momentum velocity (a resumed run restarts
+ * the heavy-ball state from zero).  tcol_get_t synchronises the stream. */
 tcol_status tcol_get_t(tcol_ctx *ctx, int32_t g, int64_t *t);
 tcol_status tcol_set_t(tcol_ctx *ctx, int32_t g, int64_t t);
 
@@ -246,7 +264,8 @@ typedef struct {
     int64_t steps_total;    /* iterations over all attempts */
 } tcol_descent_result;
 
-/* Run the descent on one graph.  A_dev: n x n row-major 0/1 (as tcol_init);
+/* Run the descent on one graph (problems TCOL_KCOL and TCOL_ECP).  A_dev: n x n
+ * row-major 0/1 (as tcol_init);
  * base: the graph's parameters (k and stop_on_legal are overridden; D,
  * problem, precision and the method's parameters are kept); opt: as above.
  * On return *result (host) holds the outcome and colors_dev (device, n int16,

@@ -12,10 +12,10 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 from . import _lib
-from ._lib import BF16, ECP, FP4, FP8, FP32, KCOL, TcolError
+from ._lib import BF16, BKPART, ECP, FP4, FP8, FP32, KCOL, KPART, MSCP, TcolError
 
-__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "KCOL", "ECP", "FP32", "BF16", "FP8",
-           "FP4", "TcolError"]
+__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "KCOL", "ECP", "KPART", "BKPART", "MSCP",
+           "FP32", "BF16", "FP8", "FP4", "TcolError"]
 
 
 @dataclass
@@ -36,11 +36,12 @@ class Params:
     nu: float = 0.0
     bonus_diag: int = 1
     stop_on_legal: int = 1
+    momentum: float = 0.0
 
     def c_struct(self) -> _lib.GraphParams:
         return _lib.GraphParams(self.problem, self.precision, self.n, self.k, self.D, self.eta, self.rho,
                                 self.nb_iter, self.alpha, self.lam, self.beta, self.mu, self.nu,
-                                self.bonus_diag, self.stop_on_legal)
+                                self.bonus_diag, self.stop_on_legal, self.momentum)
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
@@ -133,7 +134,9 @@ class Solver:
         return done.value, list(legal)
 
     def conflicts(self, g: int = 0):
-        """(colours int16 [D, n], f_color int64 [D], f_eq int64 [D]) of the current W."""
+        """(colours int16 [D, n], main fitness int64 [D], added fitness int64 [D]) of the current W:
+        f_color (the cut for partitioning) and f_eq (the colour cost for minimum sum colouring,
+        0 for k-COL and plain partitioning)."""
         torch = _torch()
         p = self.params[g]
         dev = self.W[g].device
@@ -144,7 +147,7 @@ class Solver:
         return c, fc, fe
 
     def loss_grad(self, g: int = 0, want_loss=True, want_gs=True, want_gw=True):
-        """(loss float64 [5] = L, sum f_color, sum f_eq, kappa, varpi; grad_S; grad_W)."""
+        """(loss float64 [5] = L, sum main fitness, sum added fitness, kappa, varpi; grad_S; grad_W)."""
         torch = _torch()
         p = self.params[g]
         dev = self.W[g].device

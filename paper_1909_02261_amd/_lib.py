@@ -11,7 +11,7 @@ TCOL_OK = 0
 STATUS = {0: "TCOL_OK", -1: "TCOL_EINVAL", -2: "TCOL_ESHAPE", -3: "TCOL_EGRAPH", -4: "TCOL_EHIP",
           -5: "TCOL_ENONFINITE", -6: "TCOL_ENOMEM", -7: "TCOL_ESTATE"}
 
-KCOL, ECP = 0, 1
+KCOL, ECP, KPART, BKPART, MSCP = 0, 1, 2, 3, 4
 FP32, BF16, FP8, FP4 = 0, 1, 2, 3
 
 
@@ -20,7 +20,8 @@ class GraphParams(ctypes.Structure):
                 ("k", ctypes.c_int32), ("D", ctypes.c_int32), ("eta", ctypes.c_float),
                 ("rho", ctypes.c_float), ("nb_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("lambda_", ctypes.c_float), ("beta", ctypes.c_float), ("mu", ctypes.c_float),
-                ("nu", ctypes.c_float), ("bonus_diag", ctypes.c_int32), ("stop_on_legal", ctypes.c_int32)]
+                ("nu", ctypes.c_float), ("bonus_diag", ctypes.c_int32), ("stop_on_legal", ctypes.c_int32),
+                ("momentum", ctypes.c_float)]
 
 
 class Options(ctypes.Structure):

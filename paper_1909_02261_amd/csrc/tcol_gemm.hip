@@ -313,6 +313,9 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     // (passes bit 3) always takes the dense pass
     const bool gather_pen = pen && d.pgather && !(passes & 8);
     const bool dense_pen = pen && !gather_pen;
+    // partitioning: the fitness term is -A.S, and with the operand built over D - Mt the
+    // penalty product is negated as well
+    const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;
 
     // graph fields in registers: reading them through gd after a store or an
     // atomic would reload them, one dependent round trip per use
@@ -413,7 +416,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 if (i < n) {
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
-                        if (cm[nt] >= 0) Gg[((size_t)cm[nt] * n + i) * k + cl[nt]] = acc[mt][nt][r];
+                        if (cm[nt] >= 0) Gg[((size_t)cm[nt] * n + i) * k + cl[nt]] = sgn * acc[mt][nt][r];
                 }
             }
     } else {
@@ -424,7 +427,8 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
         const int nmem = min(d.gm_mpb, d.D - d0);
         const int g16 = tid >> 4, l16 = tid & 15;
         const long long t = st->t;
-        const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+        const float nut = prob_added(d.problem) ? d.nu * (float)t : 0.0f;
+        const int prob = d.problem;
         const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
         const int pW = st->pW;
         const float* __restrict__ Wc = d.W[pW];
@@ -466,9 +470,9 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 float z = 0.0f, q = 0.0f;
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx);
-                    float gv = gr[l];
+                    float gv = sgn * gr[l];
                     if (gather_pen) gv += g1[l];
-                    if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
+                    if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
                     z += e;
                     q += e * gv;
                 }
@@ -482,9 +486,9 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 int bi = 0x7FFFFFFF, bad = 0;
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx) * rz;
-                    float gv = gr[l];
+                    float gv = sgn * gr[l];
                     if (gather_pen) gv += g1[l];
-                    if (nut != 0.0f) gv += nut * (float)((V[l] > c2) - (V[l] < c1));
+                    if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
                     float nw = w[l] - eta * (e * (gv - rq));
                     if (smooth) nw = nw / rho;
                     wo[l] = nw;

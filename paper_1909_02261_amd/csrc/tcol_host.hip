@@ -38,7 +38,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_VEL, B_COUNT
 };
 
 struct Layout {
@@ -77,6 +77,7 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     sz[B_CLSV] = sizeof(int16_t) * (size_t)p.D * round_up(p.n, 64);
     sz[B_CLSOFF] = sizeof(int32_t) * (size_t)p.D * (p.k + 1);
+    sz[B_VEL] = p.momentum != 0.0f ? sizeof(float) * dnk : 0;
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
         L.off[b] = o;
@@ -91,7 +92,8 @@ size_t head_bytes(int G) { return align_up(sizeof(GraphDev) * G) + align_up(size
 tcol_status check_params(const tcol_graph_params& p) {
     if (p.n < 1 || p.n > kMaxN || p.k < 1 || p.k > kMaxK || p.D < 1 || p.D > kMaxD) return TCOL_ESHAPE;
     if ((long long)p.D * p.k > (1LL << 26)) return TCOL_ESHAPE;
-    if (p.problem != TCOL_KCOL && p.problem != TCOL_ECP) return TCOL_EINVAL;
+    if (p.problem < TCOL_KCOL || p.problem > TCOL_MSCP) return TCOL_EINVAL;
+    if (!(p.momentum >= 0.0f && p.momentum < 1.0f)) return TCOL_EINVAL;
     if (p.precision < TCOL_FP32 || p.precision > TCOL_FP4) return TCOL_EINVAL;
     if (!(p.eta > 0.0f) || !(p.rho >= 1.0f) || p.nb_iter < 1) return TCOL_EINVAL;
     if (!(p.lambda >= 0.0f) || !(p.mu >= 0.0f) || !(p.nu >= 0.0f)) return TCOL_EINVAL;
@@ -126,6 +128,7 @@ struct tcol_ctx {
     GemmShape shape{};              // separate-path tiling (also used by tcol_conflicts / tcol_loss_grad)
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
+    bool any_momentum = false;      // some graph takes heavy-ball steps (no epilogue path)
     int pg_R = 0, pg_PM = 0;        // class-gather penalty: rows per block, members per list group
     size_t pg_lds = 0;              // dynamic LDS of the class-gather kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
@@ -358,7 +361,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
 
 // step schedule actually used: 2 needs the epilogue tiling, 1 needs the row-update kernel
 static int path_of(const tcol_ctx* c) {
-    if (c->opt.fused == 2 && c->fused_ok) return 2;
+    if (c->opt.fused == 2 && c->fused_ok && !c->any_momentum) return 2;
     if (c->opt.fused >= 1 && update_rows_kpl(c->kmax)) return 1;
     return 0;
 }
@@ -558,6 +561,7 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
     for (auto& q : c->params) {
         c->kmax = std::max(c->kmax, q.k);
         c->nmax = std::max(c->nmax, q.n);
+        if (q.momentum != 0.0f) c->any_momentum = true;
     }
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
         fprintf(stderr, "libtcol: capture stream creation failed\n");
@@ -591,9 +595,11 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
     size_t off = head_bytes(G);
     c->hdesc.resize(G);
     c->layouts.resize(G);
+    // graph check flag, then (8-byte aligned) one count of A's ones per graph
     int* dbad = nullptr;
-    if (hipMalloc((void**)&dbad, sizeof(int)) != hipSuccess ||
-        hipMemsetAsync(dbad, 0, sizeof(int), c->stream) != hipSuccess) {
+    const size_t chk_bytes = 8 + sizeof(unsigned long long) * G;
+    if (hipMalloc((void**)&dbad, chk_bytes) != hipSuccess ||
+        hipMemsetAsync(dbad, 0, chk_bytes, c->stream) != hipSuccess) {
         fprintf(stderr, "libtcol: graph check flag allocation failed\n");
         if (dbad) hipFree(dbad);
         tcol_destroy(c);
@@ -624,7 +630,9 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.c2 = (q.n % q.k == 0) ? q.n / q.k : q.n / q.k + 1;
         d.eta = q.eta;
         d.rho = q.rho;
-        d.nu = q.problem == TCOL_ECP ? q.nu : 0.0f;
+        d.nu = prob_added(q.problem) ? q.nu : 0.0f;
+        d.momentum = q.momentum;
+        d.vel = q.momentum != 0.0f ? (float*)(b + L.off[B_VEL]) : nullptr;
         d.lambda = q.lambda;
         d.mu = q.mu;
         d.lut_pen = (const float*)(b + L.off[B_LUT_PEN]);
@@ -656,14 +664,16 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.cTs = round_up(q.D, 8);
         d.cls_v = (int16_t*)(b + L.off[B_CLSV]);
         d.cls_off = (int32_t*)(b + L.off[B_CLSOFF]);
-        // look-up tables over the group concentration m = 0..D (host libm, FP64)
+        // look-up tables over the group concentration m = 0..D (host libm, FP64); for
+        // partitioning the powers are of D - m (M replaced by J - M)
         std::vector<float> lp(q.D + 1), lb(q.D + 1);
         std::vector<double> lka(q.D + 1), lvb(q.D + 1);
         for (int m = 0; m <= q.D; ++m) {
-            lp[m] = (float)(2.0 * q.alpha * q.lambda * pow0(m, (double)q.alpha - 1.0));
-            lb[m] = (float)(2.0 * q.beta * q.mu * pow0(m, (double)q.beta - 1.0));
-            lka[m] = pow0(m, q.alpha);
-            lvb[m] = pow0(m, q.beta);
+            const double x = prob_partition(q.problem) ? (double)(q.D - m) : (double)m;
+            lp[m] = (float)(2.0 * q.alpha * q.lambda * pow0(x, (double)q.alpha - 1.0));
+            lb[m] = (float)(2.0 * q.beta * q.mu * pow0(x, (double)q.beta - 1.0));
+            lka[m] = pow0(x, q.alpha);
+            lvb[m] = pow0(x, q.beta);
         }
         if (hipMemcpy(b + L.off[B_LUT_PEN], lp.data(), sizeof(float) * lp.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(b + L.off[B_LUT_BON], lb.data(), sizeof(float) * lb.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -671,16 +681,22 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
             hipMemcpy(b + L.off[B_LUT_VB], lvb.data(), sizeof(double) * lvb.size(), hipMemcpyHostToDevice) != hipSuccess)
             rc = init_fail("look-up table upload");
         if (rc == TCOL_OK &&
-            launch_pack_graph(A_dev[g], q.n, L.n_pad, q.precision, (uint8_t*)d.A8, d.Aop, dbad, c->stream) != hipSuccess)
+            launch_pack_graph(A_dev[g], q.n, L.n_pad, q.precision, (uint8_t*)d.A8, d.Aop, dbad,
+                              (unsigned long long*)(dbad + 2) + g, c->stream) != hipSuccess)
             rc = init_fail("graph packing launch");
     }
     int bad = 0;
+    std::vector<unsigned long long> ones(G, 0);
     if (rc == TCOL_OK) {
         if (hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(ones.data(), dbad + 2, sizeof(unsigned long long) * G, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess)
             rc = init_fail("graph check");
     }
     hipFree(dbad);
+    // |E|: every edge is counted from both ends
+    for (int g = 0; g < G && rc == TCOL_OK; ++g) c->hdesc[g].edges = (long long)(ones[g] / 2);
     if (rc == TCOL_OK && bad) rc = TCOL_EGRAPH;
     if (rc == TCOL_OK) {
         std::vector<GraphState> st(G);
@@ -795,6 +811,9 @@ tcol_status tcol_get_t(tcol_ctx* c, int32_t g, int64_t* t) {
 tcol_status tcol_set_t(tcol_ctx* c, int32_t g, int64_t t) {
     if (!c || g < 0 || g >= c->G || t < 0) return TCOL_EINVAL;
     HIPCHK(launch_state(c->ddesc, c->G, 1, g, t, c->stream));
+    const tcol_graph_params& p = c->params[g];
+    if (c->hdesc[g].vel)
+        HIPCHK(hipMemsetAsync(c->hdesc[g].vel, 0, sizeof(float) * (size_t)p.D * p.n * p.k, c->stream));
     return TCOL_OK;
 }
 
@@ -998,6 +1017,7 @@ tcol_status tcol_init_weights(float* W_dev, int64_t count, uint64_t seed, double
 tcol_status tcol_descent(const uint8_t* A_dev, const tcol_graph_params* base, const tcol_descent_options* opt,
                          tcol_descent_result* result, int16_t* colors_dev, void* stream) {
     if (!A_dev || !base || !opt || !result) return TCOL_EINVAL;
+    if (base->problem != TCOL_KCOL && base->problem != TCOL_ECP) return TCOL_EINVAL;
     if (opt->k_first < 1 || opt->k_first > kMaxK || opt->k_min < 1 || opt->k_min > opt->k_first ||
         opt->max_steps < 1 || opt->attempts < 1 || !(opt->sigma0 > 0.0) || !isfinite(opt->sigma0))
         return TCOL_EINVAL;

@@ -11,6 +11,22 @@ constexpr int kPrecBF16 = 1;
 constexpr int kPrecFP8 = 2;
 constexpr int kPrecFP4 = 3;
 
+// problems (the public enum's values)
+constexpr int kProbKCOL = 0, kProbECP = 1, kProbKPART = 2, kProbBKPART = 3, kProbMSCP = 4;
+// partitioning: the fitness term is -A.S and the group concentration enters as D - Mt
+__host__ __device__ inline bool prob_partition(int p) { return p == kProbKPART || p == kProbBKPART; }
+// problems whose fitness and loss carry an added term (equity or colour cost)
+__host__ __device__ inline bool prob_added(int p) { return p == kProbECP || p == kProbBKPART || p == kProbMSCP; }
+// the added term is the equity fitness
+__host__ __device__ inline bool prob_equity(int p) { return p == kProbECP || p == kProbBKPART; }
+// derivative of the added fitness with respect to s_{d,i,l} (times nu t in the
+// gradient): the equity term (+1 above c2, -1 below c1, else 0) or the colour
+// cost z_l = l + 1 of minimum sum colouring
+__device__ inline float added_grad(int problem, int32_t v, int l, int c1, int c2) {
+    if (problem == kProbMSCP) return (float)(l + 1);
+    return (float)((v > c2) - (v < c1));
+}
+
 // A.S in fp8 or fp4: the penalty pass then runs on bf16 copies of the operands
 __host__ __device__ inline bool prec_split(int prec) { return prec == kPrecFP8 || prec == kPrecFP4; }
 // bytes of one operand row of n_pad elements (n_pad a multiple of 256)
@@ -53,11 +69,13 @@ struct GraphDev {
     int problem, precision, bonus_diag, stop_on_legal, nb_iter;
     int c1, c2;         // equity bounds
     float eta, rho, nu, lambda, mu;
-    // look-up tables over m = 0..D
-    const float* lut_pen;     // 2 alpha lambda m^(alpha-1)   (0 at m = 0)
-    const float* lut_bon;     // 2 beta mu m^(beta-1)         (0 at m = 0)
-    const double* lut_ka;     // m^alpha
-    const double* lut_vb;     // m^beta
+    float momentum;           // heavy-ball coefficient (0: plain step)
+    long long edges;          // |E|
+    // look-up tables over m = 0..D, with x = m (colouring) or D - m (partitioning)
+    const float* lut_pen;     // 2 alpha lambda x^(alpha-1)   (0 at x = 0)
+    const float* lut_bon;     // 2 beta mu x^(beta-1)         (0 at x = 0)
+    const double* lut_ka;     // x^alpha
+    const double* lut_vb;     // x^beta
     // buffers
     float* W[2];              // [0] caller's weights, [1] fused-path ping-pong buffer
     const uint8_t* A8;        // [n_pad][n_pad] 0/1 bytes (zero padded)
@@ -68,10 +86,11 @@ struct GraphDev {
     int16_t* c[2];            // colours [D][cs] (member-major; entries n..cs-1 unused)
     int32_t* V[2];            // class sizes [D][k]
     float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)
+    float* vel;               // [D][n][k] momentum velocity (null when momentum is 0)
     int32_t* f2;              // [D] 2 * f_color accumulated by the GEMM
-    int64_t* fcol;            // [D]
-    int64_t* feq;             // [D]
-    int64_t* f;               // [D]
+    int64_t* fcol;            // [D] main fitness: f_color, or the cut for partitioning
+    int64_t* feq;             // [D] added fitness: f_eq, the colour cost, or 0
+    int64_t* f;               // [D] fcol + feq
     double* part;             // [mt_tiles][2] kappa / varpi partial sums
     int16_t* snap;            // [n] colouring of the legal member
     GraphState* st;

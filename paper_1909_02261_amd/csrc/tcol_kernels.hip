@@ -76,18 +76,26 @@ __device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((
 // zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]; in fp4 two
 // entries per byte, the lower column in the low nibble, 1.0 = 0x2).
 __global__ void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
-                             uint8_t* __restrict__ A8, void* __restrict__ Aop, int* __restrict__ bad) {
+                             uint8_t* __restrict__ A8, void* __restrict__ Aop, int* __restrict__ bad,
+                             unsigned long long* __restrict__ ones) {
     long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long total = (long long)n_pad * n_pad;
-    if (e >= total) return;
-    int i = (int)(e / n_pad), j = (int)(e - (long long)i * n_pad);
+    int i = 0, j = 0;
     uint8_t a = 0;
-    if (i < n && j < n) {
-        a = A[(size_t)i * n + j];
-        uint8_t b = A[(size_t)j * n + i];
-        if (a > 1 || a != b || (i == j && a != 0)) atomicOr(bad, 1);
-        a = a ? 1 : 0;
+    if (e < total) {
+        i = (int)(e / n_pad);
+        j = (int)(e - (long long)i * n_pad);
+        if (i < n && j < n) {
+            a = A[(size_t)i * n + j];
+            uint8_t b = A[(size_t)j * n + i];
+            if (a > 1 || a != b || (i == j && a != 0)) atomicOr(bad, 1);
+            a = a ? 1 : 0;
+        }
     }
+    // count of ones (2 |E| for a valid graph): one atomic per wave
+    const unsigned long long wb = __ballot(a != 0);
+    if ((threadIdx.x & 63) == 0 && wb) atomicAdd(ones, (unsigned long long)__builtin_popcountll(wb));
+    if (e >= total) return;
     A8[e] = a;
     if (prec == kPrecFP32)
         ((float*)Aop)[e] = a ? 1.0f : 0.0f;
@@ -327,8 +335,12 @@ __global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ 
     float* vals = (float*)pg_sh;                               // [n_pad + 1][R]
     uint32_t* cnt = (uint32_t*)pg_sh;                          // the same words, phase 1
     const int vrows = n_pad + (R >= 4 ? 1 : 4 / R);            // whole 16-byte units
-    float* lut = vals + (size_t)vrows * R;                     // [2 (D + 1)]
-    int16_t* lists = (int16_t*)(lut + ((2 * (D + 1) + 3) & ~3));   // [2][PM][cs]
+    float* lut = vals + (size_t)vrows * R;                     // [2 (D + 1) + 1], last entry 0
+    int16_t* lists = (int16_t*)(lut + ((2 * (D + 1) + 1 + 3) & ~3));   // [2][PM][cs]
+    const int zslot = 2 * (D + 1);
+    // partitioning: the values are those of the dense operand, whose product the
+    // contraction negates along with A.S
+    const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;
     const size_t lst_stage = (size_t)PM * cs;
     const size_t off_stage = pg_off_words(PM, k);
     int32_t* offs = (int32_t*)(lists + 2 * lst_stage);         // [2][off_stage]
@@ -378,10 +390,10 @@ __global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ 
     const float tf = (float)st->t;
     for (int e = tid; e < vrows * R / 4; e += NT) ((u32x4n*)cnt)[e] = u32x4n{0u, 0u, 0u, 0u};
     for (int m = tid; m <= D; m += NT) {
-        // entry 0 is an exact zero: m = 0, and the excluded diagonal
-        lut[m] = m == 0 ? 0.0f : -(tf * d.lut_bon[m]);
+        lut[m] = -(tf * d.lut_bon[m]);
         lut[D + 1 + m] = tf * d.lut_pen[m];
     }
+    if (tid == 0) lut[zslot] = 0.0f;                           // the excluded diagonal
     __syncthreads();
     // 1. Mt_ij: one thread per (row, member) adds one for each vertex of the row's class
     for (int e = tid; e < rows * D; e += NT) {
@@ -442,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ 
                 const int m = (int)cw[r];
                 const bool edge = (em[r] >> u) & 1u;
                 const bool excl = !edge && !diag && j == i0 + r;
-                fv[r] = lut[(m == 0 || excl) ? 0 : (edge ? D + 1 + m : m)];
+                fv[r] = lut[excl ? zslot : (edge ? D + 1 + m : m)];
             }
             if constexpr (R >= 4) {
 #pragma unroll
@@ -508,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ 
             }
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < rows) out[(size_t)r * k] = accumulate ? prev[r] + acc[r] : acc[r];
+                if (r < rows) out[(size_t)r * k] = accumulate ? prev[r] + sgn * acc[r] : sgn * acc[r];
         }
         if (grp + 1 < ngroups) put(grp + 1, buf ^ 1);
         __syncthreads();
@@ -721,9 +733,11 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
 
 // ------------------------------------------------------- step 2, stop rule -----
 
-// One block per graph: f_color = f2 / 2 (f2 gathered from A.S), f_eq from the
-// class sizes, f = f_color + f_eq (ECP); lowest legal member; stop rule.
-// Clears f2.  With kFlagReport only the fitness arrays are written.
+// One block per graph: f_color = f2 / 2 (f2 gathered from A.S); the main
+// fitness f_color, or |E| - f_color for partitioning; the added fitness from the
+// class sizes (f_eq, or the colour cost sum_l (l + 1) #V_l); f = main + added;
+// lowest legal member; stop rule.  Clears f2.  With kFlagReport only the fitness
+// arrays are written.
 __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd, int G, int honor_stop,
                                                  int flags, int gsel) {
     __shared__ int best;
@@ -736,9 +750,10 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
     if (threadIdx.x == 0) best = 0x7FFFFFFF;
     __syncthreads();
     for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
-        const long long fc = d.f2[m] / 2;
+        long long fc = d.f2[m] / 2;
+        if (prob_partition(d.problem)) fc = d.edges - fc;
         long long fe = 0;
-        if (d.problem == 1) {
+        if (prob_equity(d.problem)) {
             const int32_t* V = d.V[p] + (size_t)m * d.k;
             for (int l = 0; l < d.k; ++l) {
                 // min(|#V - c1|, |#V - c2|)
@@ -747,6 +762,9 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
                 long long y = v > d.c2 ? v - d.c2 : d.c2 - v;
                 fe += x < y ? x : y;
             }
+        } else if (d.problem == kProbMSCP) {
+            const int32_t* V = d.V[p] + (size_t)m * d.k;
+            for (int l = 0; l < d.k; ++l) fe += (long long)(l + 1) * V[l];
         }
         d.fcol[m] = fc;
         d.feq[m] = fe;
@@ -799,8 +817,11 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
     float* w = d.W[0] + (size_t)r * k;
     const float* gs = d.G + (size_t)r * k;
     const long long t = st->t;
-    const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+    const float nut = prob_added(d.problem) ? d.nu * (float)t : 0.0f;
+    const int prob = d.problem;
     const int32_t* V = d.V[st->pS] + (size_t)m * k;
+    const float gam = d.momentum;
+    float* vel = d.vel ? d.vel + (size_t)r * k : nullptr;
     float mx = -INFINITY;
     for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
     for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
@@ -808,7 +829,7 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
     for (int l = l16; l < k; l += 16) {
         float e = expf(w[l] - mx);
         float gv = gs[l];
-        if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+        if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, d.c1, d.c2);
         z += e;
         q += e * gv;
     }
@@ -822,10 +843,15 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
     for (int l = l16; l < k; l += 16) {
         float e = expf(w[l] - mx) * rz;
         float gv = gs[l];
-        if (nut != 0.0f) gv += nut * (float)((V[l] > d.c2) - (V[l] < d.c1));
+        if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, d.c1, d.c2);
         float gw = e * (gv - rr);
         if (mode == 0) {
-            float nw = w[l] - d.eta * gw;
+            float step = gw;
+            if (vel) {
+                step = gam * vel[l] + gw;       // heavy-ball velocity
+                vel[l] = step;
+            }
+            float nw = w[l] - d.eta * step;
             if (smooth) nw = nw / d.rho;
             w[l] = nw;
         } else {
@@ -858,11 +884,14 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     float* w = d.W[0] + (size_t)r * k;
     const float* gs = d.G + (size_t)r * k;
     const long long t = st->t;
-    const float nut = d.problem == 1 ? d.nu * (float)t : 0.0f;
+    const float nut = prob_added(d.problem) ? d.nu * (float)t : 0.0f;
+    const int prob = d.problem;
     const int32_t* V = d.V[st->pS] + (size_t)m * k;
     // fields used after the stores below stay in registers (no reload through gd)
     const int c1 = d.c1, c2 = d.c2;
     const float eta = d.eta, rho = d.rho;
+    const float gam = d.momentum;
+    float* __restrict__ vel = d.vel ? d.vel + (size_t)r * k : nullptr;
     int16_t* __restrict__ cnext = d.c[st->pS] + (size_t)m * d.cs;
     float wv[KPL], gv[KPL];
 #pragma unroll
@@ -871,7 +900,7 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
         if (l < k) {
             wv[q] = w[l];
             float x = gs[l];
-            if (nut != 0.0f) x += nut * (float)((V[l] > c2) - (V[l] < c1));
+            if (nut != 0.0f) x += nut * added_grad(prob, V[l], l, c1, c2);
             gv[q] = x;
         } else {
             wv[q] = -INFINITY;
@@ -914,7 +943,12 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     for (int q = 0; q < KPL; ++q) {
         const int l = l16 + 16 * q;
         if (l < k) {
-            float nw = wv[q] - eta * (ev[q] * rz * (gv[q] - rq));
+            float step = ev[q] * rz * (gv[q] - rq);
+            if (vel) {
+                step = gam * vel[l] + step;     // heavy-ball velocity
+                vel[l] = step;
+            }
+            float nw = wv[q] - eta * step;
             if (smooth) nw = nw / rho;
             w[l] = nw;
             if (!finite_f(nw)) bad = 1;
@@ -951,7 +985,8 @@ __global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
     }
 }
 
-// FP64 loss of one graph: L = sum f_color + nu t sum f_eq + lambda t kappa - mu t varpi.
+// FP64 loss of one graph: L = sum main fitness + nu t sum added fitness + lambda t kappa
+// - mu t varpi (kappa, varpi from the group-concentration kernel's partials).
 __global__ __launch_bounds__(256) void k_loss(const GraphDev* __restrict__ gd, int g, int ntiles,
                                               double* __restrict__ out) {
     __shared__ double red[4][256];
@@ -975,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_loss(const GraphDev* __restrict__ gd, i
     }
     if (threadIdx.x == 0) {
         const double t = (double)d.st->t;
-        const double eq = d.problem == 1 ? red[3][0] : 0.0;
+        const double eq = prob_added(d.problem) ? red[3][0] : 0.0;
         out[0] = red[2][0] + (double)d.nu * t * eq + (double)d.lambda * t * red[0][0] - (double)d.mu * t * red[1][0];
         out[1] = red[2][0];
         out[2] = eq;
@@ -1078,10 +1113,10 @@ hipError_t launch_init_weights(float* W, long long count, unsigned long long see
 }
 
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
-                             hipStream_t s) {
+                             unsigned long long* ones, hipStream_t s) {
     long long total = (long long)n_pad * n_pad;
     int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_pack_graph, dim3(blocks), dim3(256), 0, s, A, n, n_pad, prec, A8, Aop, bad);
+    hipLaunchKernelGGL(k_pack_graph, dim3(blocks), dim3(256), 0, s, A, n, n_pad, prec, A8, Aop, bad, ones);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1123,7 +1158,7 @@ hipError_t penalty_gather_prepare() {
 size_t penalty_gather_lds(int R, int PM, int kmax, int dmax, int nmax) {
     const size_t n_pad = (size_t)round_up(nmax, kPadN), cs = (size_t)round_up(nmax, 64);
     const size_t vrows = n_pad + (R >= 4 ? 1 : 4 / R);
-    const size_t b = 4 * (size_t)R * vrows + 4 * (size_t)((2 * (dmax + 1) + 3) & ~3) + 2 * 2 * (size_t)PM * cs +
+    const size_t b = 4 * (size_t)R * vrows + 4 * (size_t)((2 * (dmax + 1) + 1 + 3) & ~3) + 2 * 2 * (size_t)PM * cs +
                      4 * 2 * pg_off_words(PM, kmax);
     return (b + 15) / 16 * 16;
 }

@@ -7,8 +7,9 @@ namespace tcol {
 
 // initial weights N(0, sigma0^2) from Philox4x32-10 (stream 1) and Box-Muller
 hipError_t launch_init_weights(float* W, long long count, unsigned long long seed, double sigma0, hipStream_t s);
+// validates A, writes A8 and the operand copy, adds the number of ones of A to *ones
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
-                             hipStream_t s);
+                             unsigned long long* ones, hipStream_t s);
 hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s);
 // class sizes and vertex-major colours; with gather != 0 also the class lists of graphs on the
 // class-gather penalty (dynamic LDS from prep_lds)

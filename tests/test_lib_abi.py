@@ -64,7 +64,14 @@ def test_workspace_size_and_validation(lib):
     assert ws(lib, params(D=5000))[0] == -2
     assert ws(lib, params(n=40000))[0] == -2
     assert ws(lib, params(precision=7))[0] == -1
-    assert ws(lib, params(problem=3))[0] == -1
+    for prob in (1, 2, 3, 4):                           # ECP, (balanced) k-partitioning, min-sum colouring
+        assert ws(lib, params(problem=prob))[0] == 0
+    assert ws(lib, params(problem=5))[0] == -1
+    assert ws(lib, params(problem=-1))[0] == -1
+    assert ws(lib, params(momentum=1.0))[0] == -1       # heavy-ball coefficient in [0, 1)
+    assert ws(lib, params(momentum=-0.1))[0] == -1
+    st, bm = ws(lib, params(momentum=0.9))              # the velocity lives in the workspace
+    assert st == 0 and bm >= b1 + 4 * 4 * 100 * 10
     assert ws(lib, params(alpha=1.0))[0] == -1          # lambda > 0 needs alpha > 1
     assert ws(lib, params(alpha=1.0, lambda_=0.0))[0] == 0
     assert ws(lib, params(beta=0.5))[0] == -1           # mu > 0 needs beta > 1
@@ -97,6 +104,13 @@ def test_init_rejects_bad_arguments_without_gpu(lib):
     assert lib.tcol_set_t(None, 0, 0) == -1
     assert lib.tcol_reset(None) == -1
     lib.tcol_destroy(None)
+    # the colour-count descent is for colouring problems only (checked before any device work)
+    dopt = _lib.DescentOptions(10, 1, 100, 1, 0, 0.01)
+    dres = _lib.DescentResult()
+    for prob in (2, 3, 4):
+        bp = params(problem=prob)
+        assert lib.tcol_descent(ctypes.c_void_p(1), ctypes.byref(bp), ctypes.byref(dopt), ctypes.byref(dres),
+                                None, None) == -1
 
 
 def test_status_strings(lib):
