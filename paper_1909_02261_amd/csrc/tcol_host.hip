@@ -129,6 +129,7 @@ struct tcol_ctx {
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
     bool any_momentum = false;      // some graph takes heavy-ball steps (no epilogue path)
+    int update_var = 0;             // row-update variant: bit 0 added fitness term, bit 1 momentum
     int pg_R = 0, pg_PM = 0;        // class-gather penalty: rows per block, members per list group
     size_t pg_lds = 0;              // dynamic LDS of the class-gather kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
@@ -369,7 +370,7 @@ static bool use_fused(const tcol_ctx* c) { return path_of(c) == 2; }
 
 static hipError_t launch_update_any(tcol_ctx* c, int honor, int mode, int gsel, float* gs, float* gw, hipStream_t s) {
     if (update_rows_kpl(c->kmax))
-        return launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, honor, mode, gsel, gs, gw, s);
+        return launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, honor, mode, gsel, gs, gw, s);
     return launch_update(c->ddesc, c->G, c->total_rows, honor, mode, gsel, gs, gw, s);
 }
 
@@ -413,7 +414,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
     HIPRET(enqueue_gather_add(c, s));
     HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
-    HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, 1, 0, -1, nullptr, nullptr, s));
+    HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
     HIPRET(launch_advance(c->ddesc, c->G, s));
     return hipSuccess;
 }
@@ -562,6 +563,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         c->kmax = std::max(c->kmax, q.k);
         c->nmax = std::max(c->nmax, q.n);
         if (q.momentum != 0.0f) c->any_momentum = true;
+        if (q.momentum != 0.0f) c->update_var |= 2;
+        if (prob_added(q.problem) && q.nu != 0.0f) c->update_var |= 1;
     }
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
         fprintf(stderr, "libtcol: capture stream creation failed\n");

@@ -749,28 +749,35 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
     const int p = st->pS;
     if (threadIdx.x == 0) best = 0x7FFFFFFF;
     __syncthreads();
-    for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
-        long long fc = d.f2[m] / 2;
-        if (prob_partition(d.problem)) fc = d.edges - fc;
+    // one wave per member: the lanes sum the added fitness over the colours
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int prob = d.problem, k = d.k, c1 = d.c1, c2 = d.c2;
+    for (int m = threadIdx.x >> 6; m < d.D; m += nw) {
         long long fe = 0;
-        if (prob_equity(d.problem)) {
-            const int32_t* V = d.V[p] + (size_t)m * d.k;
-            for (int l = 0; l < d.k; ++l) {
-                // min(|#V - c1|, |#V - c2|)
-                long long v = V[l];
-                long long x = v > d.c1 ? v - d.c1 : d.c1 - v;
-                long long y = v > d.c2 ? v - d.c2 : d.c2 - v;
-                fe += x < y ? x : y;
+        if (prob_added(prob)) {
+            const int32_t* V = d.V[p] + (size_t)m * k;
+            for (int l = lane; l < k; l += 64) {
+                const long long v = V[l];
+                if (prob == kProbMSCP) {
+                    fe += (long long)(l + 1) * v;
+                } else {
+                    // min(|#V - c1|, |#V - c2|)
+                    const long long x = v > c1 ? v - c1 : c1 - v;
+                    const long long y = v > c2 ? v - c2 : c2 - v;
+                    fe += x < y ? x : y;
+                }
             }
-        } else if (d.problem == kProbMSCP) {
-            const int32_t* V = d.V[p] + (size_t)m * d.k;
-            for (int l = 0; l < d.k; ++l) fe += (long long)(l + 1) * V[l];
+            for (int s = 32; s >= 1; s >>= 1) fe += __shfl_xor(fe, s);
         }
-        d.fcol[m] = fc;
-        d.feq[m] = fe;
-        d.f[m] = fc + fe;
-        d.f2[m] = 0;
-        if (fc + fe == 0) atomicMin(&best, m);
+        if (lane == 0) {
+            long long fc = d.f2[m] / 2;
+            if (prob_partition(prob)) fc = d.edges - fc;
+            d.fcol[m] = fc;
+            d.feq[m] = fe;
+            d.f[m] = fc + fe;
+            d.f2[m] = 0;
+            if (fc + fe == 0) atomicMin(&best, m);
+        }
     }
     __syncthreads();
     if (flags & kFlagReport) return;
@@ -866,7 +873,10 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
 // gradient gW = s^ (G - sum_l s^_l G_l), update, smoothing, and in mode 0 the
 // argmax colouring of the updated row for the next iteration (written over
 // this iteration's colours).  Mode 1 writes gS and gW of graph gsel instead.
-template <int KPL>
+// VAR bit 0: some graph of the launch has an added fitness term (equity or colour
+// cost), bit 1: some graph takes heavy-ball steps; the plain variant carries neither
+// stream's registers.
+template <int KPL, int VAR>
 __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict__ gd, int G, int total_rows,
                                                      int honor_stop, int mode, int gsel, float* __restrict__ gS_out,
                                                      float* __restrict__ gW_out) {
@@ -893,16 +903,36 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     const float gam = d.momentum;
     float* __restrict__ vel = d.vel ? d.vel + (size_t)r * k : nullptr;
     int16_t* __restrict__ cnext = d.c[st->pS] + (size_t)m * d.cs;
-    float wv[KPL], gv[KPL];
+    // every load of the row first (indices clamped into the row instead of branches,
+    // so they are all in flight together), then the arithmetic
+    constexpr bool ADD = (VAR & 1) != 0, MOM = (VAR & 2) != 0;
+    float wv[KPL], gv[KPL], vv[MOM ? KPL : 1];
+    int32_t cv[ADD ? KPL : 1];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        const int l = min(l16 + 16 * q, k - 1);
+        wv[q] = gview(w)[l];
+        gv[q] = gview(gs)[l];
+    }
+    if constexpr (ADD) {
+        if (nut != 0.0f) {
+#pragma unroll
+            for (int q = 0; q < KPL; ++q) cv[q] = gview(V)[min(l16 + 16 * q, k - 1)];
+        }
+    }
+    if constexpr (MOM) {
+        if (vel && mode != 1) {
+#pragma unroll
+            for (int q = 0; q < KPL; ++q) vv[q] = gview((const float*)vel)[min(l16 + 16 * q, k - 1)];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         const int l = l16 + 16 * q;
-        if (l < k) {
-            wv[q] = w[l];
-            float x = gs[l];
-            if (nut != 0.0f) x += nut * added_grad(prob, V[l], l, c1, c2);
-            gv[q] = x;
-        } else {
+        if constexpr (ADD) {
+            if (nut != 0.0f) gv[q] += nut * added_grad(prob, cv[q], l, c1, c2);
+        }
+        if (l >= k) {
             wv[q] = -INFINITY;
             gv[q] = 0.0f;
         }
@@ -944,9 +974,11 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
         const int l = l16 + 16 * q;
         if (l < k) {
             float step = ev[q] * rz * (gv[q] - rq);
-            if (vel) {
-                step = gam * vel[l] + step;     // heavy-ball velocity
-                vel[l] = step;
+            if constexpr (MOM) {
+                if (vel) {
+                    step = gam * vv[q] + step;  // heavy-ball velocity
+                    vel[l] = step;
+                }
             }
             float nw = wv[q] - eta * step;
             if (smooth) nw = nw / rho;
@@ -1229,19 +1261,32 @@ int update_rows_kpl(int kmax) {
     return 0;
 }
 
-hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int honor_stop, int mode, int gsel,
-                              float* gS_out, float* gW_out, hipStream_t s) {
+hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int var, int honor_stop, int mode,
+                              int gsel, float* gS_out, float* gW_out, hipStream_t s) {
     if (total_rows <= 0) return hipSuccess;
+    if (var < 0 || var > 3) return hipErrorInvalidValue;
     const dim3 grid(ceil_div(total_rows, 16)), blk(256);
+#define TCOL_UR(KP)                                                                                                  \
+    switch (var) {                                                                                                   \
+        case 0: hipLaunchKernelGGL((k_update_rows<KP, 0>), grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, \
+                                   gS_out, gW_out); break;                                                           \
+        case 1: hipLaunchKernelGGL((k_update_rows<KP, 1>), grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, \
+                                   gS_out, gW_out); break;                                                           \
+        case 2: hipLaunchKernelGGL((k_update_rows<KP, 2>), grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, \
+                                   gS_out, gW_out); break;                                                           \
+        default: hipLaunchKernelGGL((k_update_rows<KP, 3>), grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, \
+                                    gS_out, gW_out); break;                                                          \
+    }
     switch (update_rows_kpl(kmax)) {
-        case 2: hipLaunchKernelGGL(k_update_rows<2>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
-        case 4: hipLaunchKernelGGL(k_update_rows<4>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
-        case 6: hipLaunchKernelGGL(k_update_rows<6>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
-        case 8: hipLaunchKernelGGL(k_update_rows<8>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
-        case 12: hipLaunchKernelGGL(k_update_rows<12>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
-        case 18: hipLaunchKernelGGL(k_update_rows<18>, grid, blk, 0, s, gd, G, total_rows, honor_stop, mode, gsel, gS_out, gW_out); break;
+        case 2: TCOL_UR(2) break;
+        case 4: TCOL_UR(4) break;
+        case 6: TCOL_UR(6) break;
+        case 8: TCOL_UR(8) break;
+        case 12: TCOL_UR(12) break;
+        case 18: TCOL_UR(18) break;
         default: return hipErrorInvalidValue;
     }
+#undef TCOL_UR
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

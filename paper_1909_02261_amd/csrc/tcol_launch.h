@@ -33,8 +33,9 @@ hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_st
                          float* gS_out, float* gW_out, hipStream_t s);
 // register-resident row update for k <= 288 (update_rows_kpl(kmax) != 0); mode 0 also colours the new rows
 int update_rows_kpl(int kmax);
-hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int honor_stop, int mode, int gsel,
-                              float* gS_out, float* gW_out, hipStream_t s);
+// var: bit 0 some graph has an added fitness term, bit 1 some graph takes heavy-ball steps
+hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int var, int honor_stop, int mode,
+                              int gsel, float* gS_out, float* gW_out, hipStream_t s);
 hipError_t launch_advance(const GraphDev* gd, int G, hipStream_t s);
 hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipStream_t s);
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,

@@ -401,3 +401,27 @@ def test_c5_full_size(prec):
     print(f"C5 precision {prec}: gradS {eS:.2e} gradW {eW:.2e}")
     assert eS <= 1e-2 and eW <= 1e-2
     s.close()
+
+
+@pytest.mark.parametrize("penalty", ["dense", "gather"])
+def test_c5_full_size_step(penalty):
+    """One fast-path step at the benchmark's size (n = 4000, k = 280, D = 32, fp4 A.S) with the
+    penalty active, against the oracle's iteration from the same weights: the class gather at
+    this size takes its 1024-thread, four-row blocks; the dense pass rounds its operand to bf16."""
+    case = tcolgen.case_c5(FP4)
+    case.stop_on_legal = 0
+    s, (A,) = make_solver([case], fused=1, penalty={"dense": 1, "gather": 2}[penalty])
+    t = 40
+    s.set_t(t)
+    W0 = host(s.W[0])
+    ref = oracle.iteration(orc_params(case.params()), t, A, W0, want_grads=False)
+    done, _ = s.step(1)
+    assert done == 1
+    e = normwise(host(s.W[0]), ref.W)
+    print(f"C5 {penalty}: W error vs FP64 {e:.2e}")
+    assert e <= (TOL if penalty == "gather" else 1e-2)
+    c, fc, _ = s.conflicts(0)
+    c_ref = oracle.colors(host(s.W[0]))
+    assert np.array_equal(host(c), c_ref)
+    assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
+    s.close()
