@@ -149,7 +149,8 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
     }
 }
 
-// Class sizes #V_{d,l} of member d and the vertex-major copy of its colours.
+// Class sizes #V_{d,l} of member d, its added fitness (equity or colour cost) and
+// the vertex-major copy of its colours.
 // For a graph on the class-gather penalty also the member's vertices grouped by
 // colour (stable counting sort: each class in increasing vertex order, so the
 // penalty sums run in the same order on every run).  One block per member.
@@ -198,6 +199,27 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     __syncthreads();
     int32_t* V = d.V[p] + (size_t)m * k;
     for (int l = tid; l < k; l += 256) V[l] = cnt[l];
+    // added fitness of the member from the counts: f_eq = sum_l min(|#V - c1|, |#V - c2|),
+    // or the colour cost sum_l (l + 1) #V_l (the fitness kernel of this iteration reads it)
+    if (prob_added(d.problem)) {
+        const int c1 = d.c1, c2 = d.c2;
+        long long fe = 0;
+        for (int l = tid; l < k; l += 256) {
+            const long long v = cnt[l];
+            if (d.problem == kProbMSCP) {
+                fe += (long long)(l + 1) * v;
+            } else {
+                const long long x = v > c1 ? v - c1 : c1 - v;
+                const long long y = v > c2 ? v - c2 : c2 - v;
+                fe += x < y ? x : y;
+            }
+        }
+        for (int sh = 32; sh >= 1; sh >>= 1) fe += __shfl_xor(fe, sh);
+        __shared__ long long fsum[4];
+        if ((tid & 63) == 0) fsum[tid >> 6] = fe;
+        __syncthreads();
+        if (tid == 0) d.feq[m] = fsum[0] + fsum[1] + fsum[2] + fsum[3];
+    }
     if (!lists) return;
     int16_t* lst = (int16_t*)(cw + NW * k);         // [n]
     int32_t* __restrict__ off = d.cls_off + (size_t)m * (k + 1);
@@ -734,8 +756,8 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
 // ------------------------------------------------------- step 2, stop rule -----
 
 // One block per graph: f_color = f2 / 2 (f2 gathered from A.S); the main
-// fitness f_color, or |E| - f_color for partitioning; the added fitness from the
-// class sizes (f_eq, or the colour cost sum_l (l + 1) #V_l); f = main + added;
+// fitness f_color, or |E| - f_color for partitioning; the added fitness (f_eq, or
+// the colour cost sum_l (l + 1) #V_l) as the class-size kernel left it; f = main + added;
 // lowest legal member; stop rule.  Clears f2.  With kFlagReport only the fitness
 // arrays are written.
 __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd, int G, int honor_stop,
@@ -749,35 +771,17 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
     const int p = st->pS;
     if (threadIdx.x == 0) best = 0x7FFFFFFF;
     __syncthreads();
-    // one wave per member: the lanes sum the added fitness over the colours
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    const int prob = d.problem, k = d.k, c1 = d.c1, c2 = d.c2;
-    for (int m = threadIdx.x >> 6; m < d.D; m += nw) {
-        long long fe = 0;
-        if (prob_added(prob)) {
-            const int32_t* V = d.V[p] + (size_t)m * k;
-            for (int l = lane; l < k; l += 64) {
-                const long long v = V[l];
-                if (prob == kProbMSCP) {
-                    fe += (long long)(l + 1) * v;
-                } else {
-                    // min(|#V - c1|, |#V - c2|)
-                    const long long x = v > c1 ? v - c1 : c1 - v;
-                    const long long y = v > c2 ? v - c2 : c2 - v;
-                    fe += x < y ? x : y;
-                }
-            }
-            for (int s = 32; s >= 1; s >>= 1) fe += __shfl_xor(fe, s);
-        }
-        if (lane == 0) {
-            long long fc = d.f2[m] / 2;
-            if (prob_partition(prob)) fc = d.edges - fc;
-            d.fcol[m] = fc;
-            d.feq[m] = fe;
-            d.f[m] = fc + fe;
-            d.f2[m] = 0;
-            if (fc + fe == 0) atomicMin(&best, m);
-        }
+    // the added fitness (equity or colour cost) was reduced by the class-size kernel
+    const bool added = prob_added(d.problem);
+    for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
+        long long fc = d.f2[m] / 2;
+        if (prob_partition(d.problem)) fc = d.edges - fc;
+        const long long fe = added ? d.feq[m] : 0;
+        d.fcol[m] = fc;
+        d.feq[m] = fe;
+        d.f[m] = fc + fe;
+        d.f2[m] = 0;
+        if (fc + fe == 0) atomicMin(&best, m);
     }
     __syncthreads();
     if (flags & kFlagReport) return;
