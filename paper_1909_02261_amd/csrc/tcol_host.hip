@@ -44,7 +44,7 @@ enum Buf {
 struct Layout {
     size_t off[B_COUNT];
     size_t total;
-    int n_pad, rows_S, mt_T, mt_tiles;
+    int n_pad, rows_S, mt_ts, mt_T, mt_tiles;
 };
 
 
@@ -52,7 +52,9 @@ Layout make_layout(const tcol_graph_params& p) {
     Layout L{};
     L.n_pad = round_up(p.n, kPadN);
     L.rows_S = round_up(p.D * p.k, 16) + kSRowSlack;
-    L.mt_T = L.n_pad / 64;
+    // group-concentration tiles: 32 x 32 for small graphs (more blocks), else 64 x 64
+    L.mt_ts = L.n_pad <= 2048 ? 32 : 64;
+    L.mt_T = L.n_pad / L.mt_ts;
     L.mt_tiles = L.mt_T * (L.mt_T + 1) / 2;
     const size_t n2 = (size_t)L.n_pad * L.n_pad;
     const size_t dnk = (size_t)p.D * p.n * p.k;
@@ -331,6 +333,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         if (d.pgather) pg += ceil_div(p.n, c->pg_R);
         d.mt_begin = mt;
         d.mt_T = L.mt_T;
+        d.mt_ts = L.mt_ts;
         mt += L.mt_tiles;
         d.ex_begin = ex;
         const long long items = (long long)p.D * p.k * (L.n_pad / 16);

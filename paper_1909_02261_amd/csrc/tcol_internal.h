@@ -105,7 +105,8 @@ struct GraphDev {
     int mem_begin;            // members d for per-member kernels
     int pg_begin;             // blocks of the class-gather penalty kernel (row tiles)
     int mt_begin;             // tiles of the group-concentration kernel
-    int mt_T;                 // 64-row tiles per side
+    int mt_T;                 // tiles per side
+    int mt_ts;                // tile side of the group-concentration kernel (32 or 64)
     int ex_begin;             // blocks of the S^T expansion kernel
     int ex_cblocks;           // column blocks per S^T row group
     int gm_begin[2];          // GEMM tiles of the separate (0) and fused (1) tilings

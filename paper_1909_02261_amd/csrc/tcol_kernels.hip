@@ -632,44 +632,37 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
 
 // ------------------------------------------------------------ step 3 -----------
 
-// Group concentration Mt_ij = #{d : c_d(i) = c_d(j)} over 64x64 tiles of the
-// upper triangle (mirrored), and from it the penalty operand
+// Group concentration Mt_ij = #{d : c_d(i) = c_d(j)} over TS x TS tiles of the
+// upper triangle (mirrored; TS = 64, or 32 when n_pad <= 2048 so small graphs still
+// give every CU work), and from it the penalty operand
 //   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)).
-// Optional: Mt to mt_out (int32 [n][n]) and kappa / varpi partial sums.
-__global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd, int G, int total_tiles,
-                                                int honor_stop, int flags, int gsel, int32_t* __restrict__ mt_out) {
-    constexpr int DC = 128;   // members per LDS chunk
-    __shared__ int16_t ci[DC][64];
-    __shared__ int16_t cj[DC][64];
-    __shared__ double red[2][256];
-    const int b = blockIdx.x;
-    if (b >= total_tiles) return;
-    const int g = find_graph(gd, G, b, [](const GraphDev& x) { return x.mt_begin; });
-    const GraphDev& d = gd[g];
-    GraphState* st = d.st;
-    if (honor_stop && st->stopped) return;
-    if (gsel >= 0 && g != gsel) return;
+// Optional: Mt to mt_out (int32 [n][n]) and kappa / varpi partial sums.  Each of the
+// 256 threads owns a PT x PT block of the tile (PT = TS / 16).
+constexpr int kMtChunk = 128;   // members per LDS chunk
+
+template <int PT>
+__device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags, int32_t* __restrict__ mt_out,
+                            int16_t (*ci)[64], int16_t (*cj)[64], double (*red)[256]) {
+    constexpr int TS = 16 * PT;
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
-    if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
-    if ((flags & kFlagGate) && d.pgather) return;
     const int p = st->pS;
     // upper-triangle tile (ti <= tj)
     int u = b - d.mt_begin, ti = 0, T = d.mt_T;
     while (u >= T - ti) { u -= T - ti; ++ti; }
     const int tj = ti + u;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i0 = ti * 64, j0 = tj * 64;
-    int cnt[4][4];
+    const int i0 = ti * TS, j0 = tj * TS;
+    int cnt[PT][PT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < PT; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cnt[a][q] = 0;
-    for (int dbase = 0; dbase < d.D; dbase += DC) {
-        const int dn = min(DC, d.D - dbase);
+        for (int q = 0; q < PT; ++q) cnt[a][q] = 0;
+    for (int dbase = 0; dbase < d.D; dbase += kMtChunk) {
+        const int dn = min(kMtChunk, d.D - dbase);
         __syncthreads();
-        for (int e = threadIdx.x; e < dn * 64; e += 256) {
-            int dm = e >> 6, x = e & 63;
+        for (int e = threadIdx.x; e < dn * TS; e += 256) {
+            const int dm = e / TS, x = e - dm * TS;
             const int16_t* cr = d.c[p] + (size_t)(dbase + dm) * d.cs;
             // out-of-range vertices get distinct sentinels so they never match
             ci[dm][x] = (i0 + x < d.n) ? cr[i0 + x] : (int16_t)-1;
@@ -677,14 +670,16 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
         }
         __syncthreads();
         for (int dm = 0; dm < dn; ++dm) {
-            int16_t a0 = ci[dm][ty * 4 + 0], a1 = ci[dm][ty * 4 + 1], a2 = ci[dm][ty * 4 + 2], a3 = ci[dm][ty * 4 + 3];
-            int16_t b0 = cj[dm][tx * 4 + 0], b1 = cj[dm][tx * 4 + 1], b2 = cj[dm][tx * 4 + 2], b3 = cj[dm][tx * 4 + 3];
-            int16_t av[4] = {a0, a1, a2, a3};
-            int16_t bv[4] = {b0, b1, b2, b3};
+            int16_t av[PT], bv[PT];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < PT; ++a) {
+                av[a] = ci[dm][ty * PT + a];
+                bv[a] = cj[dm][tx * PT + a];
+            }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
+            for (int a = 0; a < PT; ++a)
+#pragma unroll
+                for (int q = 0; q < PT; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
         }
     }
     const bool mirror = ti != tj;
@@ -700,19 +695,29 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
     const double* __restrict__ lut_vb = d.lut_vb;
     const bool bdiag = d.bonus_diag != 0;
     void* __restrict__ Pop = d.Pop;
+    // the thread's block: rows i0 + PT ty + a, columns j0 + PT tx + q; the adjacency of a
+    // row's PT columns is one load (A8 rows are n_pad bytes, PT | j), and the operand goes
+    // out as one vector store per row of the block and per row of its mirror
+    const int ib = i0 + ty * PT, jb = j0 + tx * PT;
+    float val[PT][PT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ty * 4 + a;
+    for (int a = 0; a < PT; ++a) {
+        const int i = ib + a;
+        uint32_t arow;
+        if constexpr (PT == 4)
+            arow = gview((const uint32_t*)(A8 + (size_t)i * n_pad + jb))[0];
+        else
+            arow = gview((const uint16_t*)(A8 + (size_t)i * n_pad + jb))[0];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = j0 + tx * 4 + q;
-            float val = 0.0f;
+        for (int q = 0; q < PT; ++q) {
+            const int j = jb + q;
+            float v = 0.0f;
             if (i < n && j < n) {
                 const int m = cnt[a][q];
-                const bool edge = A8[(size_t)i * n_pad + j] != 0;
+                const bool edge = ((arow >> (8 * q)) & 0xFFu) != 0;
                 const bool bon = !edge && (i != j || bdiag);
-                if (edge) val = tf * lut_pen[m];
-                else if (bon) val = -(tf * lut_bon[m]);
+                if (edge) v = tf * lut_pen[m];
+                else if (bon) v = -(tf * lut_bon[m]);
                 if (flags & kFlagLoss) {
                     const double wgt = mirror ? 2.0 : 1.0;
                     if (edge) ka += wgt * lut_ka[m];
@@ -723,14 +728,48 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
                     if (mirror) mt_out[(size_t)j * n + i] = m;
                 }
             }
-            if (pen || (flags & kFlagForcePen)) {
-                if (fp32) {
-                    ((float*)Pop)[(size_t)i * n_pad + j] = val;
-                    if (mirror) ((float*)Pop)[(size_t)j * n_pad + i] = val;
+            val[a][q] = v;
+        }
+    }
+    if (pen || (flags & kFlagForcePen)) {
+        if (fp32) {
+#pragma unroll
+            for (int a = 0; a < PT; ++a) {
+                float* o = (float*)Pop + (size_t)(ib + a) * n_pad + jb;
+                if constexpr (PT == 4) *(float4*)o = make_float4(val[a][0], val[a][1], val[a][2], val[a][3]);
+                else *(float2*)o = make_float2(val[a][0], val[a][1]);
+            }
+            if (mirror) {
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    float* o = (float*)Pop + (size_t)(jb + q) * n_pad + ib;
+                    if constexpr (PT == 4) *(float4*)o = make_float4(val[0][q], val[1][q], val[2][q], val[3][q]);
+                    else *(float2*)o = make_float2(val[0][q], val[1][q]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < PT; ++a) {
+                uint16_t* o = (uint16_t*)Pop + (size_t)(ib + a) * n_pad + jb;
+                const uint32_t lo = f32_to_bf16_rne(val[a][0]) | ((uint32_t)f32_to_bf16_rne(val[a][1]) << 16);
+                if constexpr (PT == 4) {
+                    const uint32_t hi = f32_to_bf16_rne(val[a][2]) | ((uint32_t)f32_to_bf16_rne(val[a][3]) << 16);
+                    *(uint2*)o = make_uint2(lo, hi);
                 } else {
-                    const uint16_t h = f32_to_bf16_rne(val);
-                    ((uint16_t*)Pop)[(size_t)i * n_pad + j] = h;
-                    if (mirror) ((uint16_t*)Pop)[(size_t)j * n_pad + i] = h;
+                    *(uint32_t*)o = lo;
+                }
+            }
+            if (mirror) {
+#pragma unroll
+                for (int q = 0; q < PT; ++q) {
+                    uint16_t* o = (uint16_t*)Pop + (size_t)(jb + q) * n_pad + ib;
+                    const uint32_t lo = f32_to_bf16_rne(val[0][q]) | ((uint32_t)f32_to_bf16_rne(val[1][q]) << 16);
+                    if constexpr (PT == 4) {
+                        const uint32_t hi = f32_to_bf16_rne(val[2][q]) | ((uint32_t)f32_to_bf16_rne(val[3][q]) << 16);
+                        *(uint2*)o = make_uint2(lo, hi);
+                    } else {
+                        *(uint32_t*)o = lo;
+                    }
                 }
             }
         }
@@ -751,6 +790,28 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
             d.part[2 * (b - d.mt_begin) + 1] = red[1][0];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd, int G, int total_tiles,
+                                                int honor_stop, int flags, int gsel, int32_t* __restrict__ mt_out) {
+    __shared__ int16_t ci[kMtChunk][64];
+    __shared__ int16_t cj[kMtChunk][64];
+    __shared__ double red[2][256];
+    const int b = blockIdx.x;
+    if (b >= total_tiles) return;
+    const int g = find_graph(gd, G, b, [](const GraphDev& x) { return x.mt_begin; });
+    const GraphDev& d = gd[g];
+    GraphState* st = d.st;
+    if (honor_stop && st->stopped) return;
+    if (gsel >= 0 && g != gsel) return;
+    const float tf = (float)st->t;
+    const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
+    if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
+    if ((flags & kFlagGate) && d.pgather) return;
+    if (d.mt_ts == 32)
+        mtilde_tile<2>(d, st, b, flags, mt_out, ci, cj, red);
+    else
+        mtilde_tile<4>(d, st, b, flags, mt_out, ci, cj, red);
 }
 
 // ------------------------------------------------------- step 2, stop rule -----
