@@ -265,6 +265,159 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const
     }
 }
 
+// ---- penalty pass of the fp4 mode: P (bf16) against S^T straight from the fp4 operand ----
+//
+// A K-stage covers 64 K-values: 128 bytes of each P row (as in the sweep above) and 32
+// bytes of each S^T row in fp4, whose 0/1 nibbles (1.0 = 0x2) become bf16 in registers
+// when the MFMAs need them.  They become 2.0 rather than 1.0: bf16 2.0 is 0x4000, a
+// single byte, so one shift-and-mask and one byte permute make each pair; the operand
+// P of an fp4 graph is stored halved (exact in bf16), so the products are unchanged.  This avoids a bf16 copy of S and quarters the S bytes
+// staged and read from LDS, so three stage buffers fit where the fp4 A.S sweep keeps
+// two.  The S rows move with 4-byte direct-to-LDS loads (a load writes 4 bytes per lane,
+// 256 per wave: 8 rows of 32 bytes); word w of row r sits at slot w ^ (((r >> 3) & 1) << 2),
+// so a fragment read (16 consecutive rows, one word each) touches 16 different banks
+// pairs.
+template <int BM, int NTW>
+struct PenTile {
+    using T = Tile<BM, NTW>;
+    static constexpr int BN = T::BN;
+    static constexpr int BROW = 32;                              // fp4 bytes of S per row per stage
+    static constexpr int A_BYTES = BM * kStageRowBytes;
+    static constexpr int STAGE = A_BYTES + BN * BROW;
+    static constexpr int AG = BM / (8 * T::WAVES);               // 16-byte-lane loads of P per wave per stage
+    static constexpr int BG = BN * BROW / (256 * T::WAVES);      // 4-byte-lane loads of S per wave per stage
+    static_assert(BM % (8 * T::WAVES) == 0 && (BN * BROW) % (256 * T::WAVES) == 0, "penalty load split");
+    static constexpr int NB = 3 * STAGE <= T::NB * T::STAGE ? 3 : 2;   // within the block's stage buffers
+    static_assert(NB * STAGE <= T::NB * T::STAGE, "penalty stages fit");
+};
+
+template <int BM, int NTW>
+struct PenFrags {
+    uint4 a[2][tile_mt(BM)];     // P: 16 bytes (8 bf16) per lane per K-step
+    uint32_t b[2][NTW];          // S: 4 bytes (8 fp4) per lane per K-step
+};
+
+// eight fp4 nibbles equal to 0 or 0x2 (0.0 or 1.0), the lowest first, as eight bf16
+// equal to 0.0 or 2.0: even nibbles' flag bit moved to bit 6 of their byte (0x40, the
+// high byte of bf16 2.0), odd nibbles' likewise, then each output word takes
+// [0, even byte j, 0, odd byte j]
+__device__ __forceinline__ bf16x8 fp4_01_to_bf16x2(uint32_t x) {
+    const uint32_t e = (x << 5) & 0x40404040u;    // nibbles 0, 2, 4, 6
+    const uint32_t o = (x << 1) & 0x40404040u;    // nibbles 1, 3, 5, 7
+    // v_perm_b32 byte selectors: 0-3 pick bytes of the second source, 4-7 of the first,
+    // 0x0C gives 0x00
+    uint4 r;
+    r.x = __builtin_amdgcn_perm(o, e, 0x040C000Cu);
+    r.y = __builtin_amdgcn_perm(o, e, 0x050C010Cu);
+    r.z = __builtin_amdgcn_perm(o, e, 0x060C020Cu);
+    r.w = __builtin_amdgcn_perm(o, e, 0x070C030Cu);
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int BM, int NTW>
+__device__ __forceinline__ void pen_read(PenFrags<BM, NTW>& F, const uint8_t* L, int lane, int wm, int wn) {
+    using T = Tile<BM, NTW>;
+    using P = PenTile<BM, NTW>;
+    const int ra = wm * T::RW + (lane & 15);
+    const int rb = wn * (NTW * 16) + (lane & 15);
+    const int q = lane >> 4;
+    const int swz = (lane & 15) >> 1;                 // P rows: (row >> 1) & 7
+    const int swb = ((lane & 15) >> 3) << 2;          // S rows: ((row >> 3) & 1) << 2
+    const uint8_t* LB = L + P::A_BYTES;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int o = ((ks * 4 + q) ^ swz) * 16;
+#pragma unroll
+        for (int mt = 0; mt < T::MT; ++mt) F.a[ks][mt] = *(const uint4*)(L + (ra + mt * 16) * kStageRowBytes + o);
+        const int ob = ((ks * 4 + q) ^ swb) * 4;
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt) F.b[ks][nt] = *(const uint32_t*)(LB + (rb + nt * 16) * P::BROW + ob);
+    }
+}
+
+template <int BM, int NTW>
+__device__ __forceinline__ void pen_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const PenFrags<BM, NTW>& F) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt) {
+            const bf16x8 b = fp4_01_to_bf16x2(F.b[ks][nt]);
+#pragma unroll
+            for (int mt = 0; mt < tile_mt(BM); ++mt)
+                acc[mt][nt] = mfma_bf16(__builtin_bit_cast(bf16x8, F.a[ks][mt]), b, acc[mt][nt]);
+        }
+}
+
+// P rows: as stage_load (8-row groups of 128 bytes, 16 bytes per lane); S rows: 8-row
+// groups of 32 bytes, 4 bytes per lane (lane L: row L / 8, slot L % 8, which receives
+// global word (L % 8) ^ (((row >> 3) & 1) << 2))
+template <int BM, int NTW>
+__device__ __forceinline__ void pen_load(const uint8_t* __restrict__ Prow, const uint8_t* __restrict__ Srow,
+                                         size_t ldp, size_t lds_, int s, uint8_t* buf, int lane, int wave) {
+    using T = Tile<BM, NTW>;
+    using P = PenTile<BM, NTW>;
+    {
+        const int rsub = lane >> 3, slot = lane & 7;
+#pragma unroll
+        for (int gi = 0; gi < P::AG; ++gi) {
+            const int grp = wave + T::WAVES * gi;
+            const int r = grp * 8 + rsub;
+            const int c = slot ^ ((r >> 1) & 7);
+            const uint8_t* src = Prow + (size_t)r * ldp + (size_t)s * kStageRowBytes + c * 16;
+            __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(buf + grp * 8 * kStageRowBytes), 16, 0, 0);
+        }
+    }
+    {
+        uint8_t* bb = buf + P::A_BYTES;
+        const int rsub = lane >> 3, slot = lane & 7;
+#pragma unroll
+        for (int gi = 0; gi < P::BG; ++gi) {
+            const int grp = wave + T::WAVES * gi;
+            const int r = grp * 8 + rsub;
+            const int w = slot ^ (((r >> 3) & 1) << 2);
+            const uint8_t* src = Srow + (size_t)r * lds_ + (size_t)s * P::BROW + w * 4;
+            __builtin_amdgcn_global_load_lds((gbl_ptr)src, (lds_ptr)(bb + grp * 8 * P::BROW), 4, 0, 0);
+        }
+    }
+}
+
+// acc += Prows . (S^T rows)^T over `nstages` stages of 64 K-values; the same two
+// pipelines as gemm_sweep's pipelined form (loads NB stages ahead, fragments one ahead).
+template <int BM, int NTW>
+__device__ __forceinline__ void pen_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const uint8_t* __restrict__ Prow,
+                                          const uint8_t* __restrict__ Srow, size_t ldp, size_t lds_, int nstages,
+                                          uint8_t* lds) {
+    using P = PenTile<BM, NTW>;
+    constexpr int NB = P::NB, PER = P::AG + P::BG;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pen_load<BM, NTW>(Prow, Srow, ldp, lds_, min(b, nstages - 1), lds + b * P::STAGE, lane, wave);
+    wait_vm<(NB - 1) * PER>();   // stage 0 has landed
+    stage_barrier();
+    PenFrags<BM, NTW> F0, F1;
+    pen_read<BM, NTW>(F0, lds, lane, wm, wn);
+    int cur = 0;
+    for (int s = 0; s < nstages; s += 2) {
+        wait_vm<(NB - 2) * PER>();   // stage s+1 has landed
+        stage_barrier();
+        pen_load<BM, NTW>(Prow, Srow, ldp, lds_, min(s + NB, nstages - 1), lds + cur * P::STAGE, lane, wave);
+        cur = cur == NB - 1 ? 0 : cur + 1;
+        if (s + 1 < nstages) pen_read<BM, NTW>(F1, lds + cur * P::STAGE, lane, wm, wn);
+        __builtin_amdgcn_sched_barrier(0);
+        pen_mma<BM, NTW>(acc, F0);
+        if (s + 1 >= nstages) break;
+        wait_vm<(NB - 2) * PER>();
+        stage_barrier();
+        pen_load<BM, NTW>(Prow, Srow, ldp, lds_, min(s + 1 + NB, nstages - 1), lds + cur * P::STAGE, lane, wave);
+        cur = cur == NB - 1 ? 0 : cur + 1;
+        if (s + 2 < nstages) pen_read<BM, NTW>(F0, lds + cur * P::STAGE, lane, wm, wn);
+        __builtin_amdgcn_sched_barrier(0);
+        pen_mma<BM, NTW>(acc, F1);
+    }
+}
+
 // XCD-aware order: hardware deals block b to XCD b mod 8, so give each XCD a
 // contiguous range of tiles (neighbouring tiles share operand panels in its L2)
 __device__ inline int xcd_remap(int b, int nb) {
@@ -394,7 +547,12 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     }
     if ((passes & 2) && dense_pen) {
         __syncthreads();
-        if constexpr (PREC == kPrecFP8 || PREC == kPrecFP4) {
+        if constexpr (PREC == kPrecFP4) {
+            // bf16 P against the fp4 S^T operand itself
+            const size_t ld2 = (size_t)d.n_pad * 2;
+            pen_sweep<BM, NTW>(acc, (const uint8_t*)d.Pop + (size_t)m0 * ld2,
+                               (const uint8_t*)d.Sop[pS] + (size_t)n0 * ld, ld2, ld, d.n_pad / 64, lds);
+        } else if constexpr (PREC == kPrecFP8) {
             const size_t ld2 = (size_t)d.n_pad * 2;
             gemm_sweep<kPrecBF16, BM, NTW>(acc, (const uint8_t*)d.Pop + (size_t)m0 * ld2,
                                            (const uint8_t*)d.Sp2[pS] + (size_t)n0 * ld2, ld2,

@@ -27,8 +27,9 @@ __device__ inline float added_grad(int problem, int32_t v, int l, int c1, int c2
     return (float)((v > c2) - (v < c1));
 }
 
-// A.S in fp8 or fp4: the penalty pass then runs on bf16 copies of the operands
-__host__ __device__ inline bool prec_split(int prec) { return prec == kPrecFP8 || prec == kPrecFP4; }
+// A.S in fp8: the penalty pass then runs on a bf16 copy of S (in fp4 it expands the fp4
+// operand to bf16 in registers)
+__host__ __device__ inline bool prec_split(int prec) { return prec == kPrecFP8; }
 // bytes of one operand row of n_pad elements (n_pad a multiple of 256)
 __host__ __device__ inline size_t op_row_bytes(int prec, int n_pad) {
     return prec == kPrecFP32 ? 4 * (size_t)n_pad
@@ -80,9 +81,9 @@ struct GraphDev {
     float* W[2];              // [0] caller's weights, [1] fused-path ping-pong buffer
     const uint8_t* A8;        // [n_pad][n_pad] 0/1 bytes (zero padded)
     void* Aop;                // [n_pad][n_pad] A in the operand precision
-    void* Pop;                // [n_pad][n_pad] penalty operand (fp32, or bf16 for BF16/FP8)
+    void* Pop;                // [n_pad][n_pad] penalty operand (fp32; bf16 for BF16/FP8; bf16, halved, for FP4)
     void* Sop[2];             // [rows_S][n_pad] S^T in the A.S operand precision
-    void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 / FP4 penalty pass (else null)
+    void* Sp2[2];             // [rows_S][n_pad] S^T in bf16 for the FP8 penalty pass (else null)
     int16_t* c[2];            // colours [D][cs] (member-major; entries n..cs-1 unused)
     int32_t* V[2];            // class sizes [D][k]
     float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)

@@ -551,7 +551,8 @@ __global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ 
 
 // One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread
 // (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
-// and FP4 graphs the bf16 copy used by the penalty pass is written as well.
+// graphs the bf16 copy used by the penalty pass is written as well (the fp4 penalty
+// pass reads the fp4 operand itself).
 __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                 int honor_stop, int next, int gate) {
     const int b = blockIdx.x;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
-    // the bf16 copy of S feeds only the dense penalty pass of FP8 / FP4 graphs
+    // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
     const bool want_sp2 = prec_split(d.precision) && (!gate || !d.pgather);
     const int cgs = d.n_pad / 16;
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
@@ -596,11 +597,13 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
             o[v] = x;
         }
     } else {
+        // bf16: the BF16 operand itself, or the FP8 graphs' copy for the penalty pass
+        const bool bf16_out = d.precision == kPrecBF16 || want_sp2;
         uint16_t* sb = d.precision == kPrecBF16 ? (uint16_t*)d.Sop[p] : (uint16_t*)d.Sp2[p];
         uint4* o = (uint4*)(sb + off);
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            if (!want_sp2 && prec_split(d.precision)) break;
+            if (!bf16_out) break;
             uint32_t w[4];
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -748,6 +751,14 @@ __device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags,
                 }
             }
         } else {
+            // fp4 graphs: the penalty pass multiplies by 2 S (cheaper to widen from fp4), so
+            // their operand is stored halved, exactly
+            if (d.precision == kPrecFP4) {
+#pragma unroll
+                for (int a = 0; a < PT; ++a)
+#pragma unroll
+                    for (int q = 0; q < PT; ++q) val[a][q] *= 0.5f;
+            }
 #pragma unroll
             for (int a = 0; a < PT; ++a) {
                 uint16_t* o = (uint16_t*)Pop + (size_t)(ib + a) * n_pad + jb;

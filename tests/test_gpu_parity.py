@@ -425,3 +425,31 @@ def test_c5_full_size_step(penalty):
     assert np.array_equal(host(c), c_ref)
     assert np.array_equal(host(fc), oracle.fcolor(A, c_ref))
     s.close()
+
+
+@pytest.mark.parametrize("prec", [FP4, FP8])
+def test_penalty_pass_every_tile_shape(prec):
+    """The dense penalty pass (bf16 P against S; in fp4 mode S comes from the fp4 operand and
+    is widened in registers) for every tile shape: gradient with respect to S against the
+    oracle on a graph with a ragged n over several row tiles and D k not a multiple of any
+    column tile."""
+    case = GraphCase("penshapes", KCOL, 1000, 28, 40, prec, "gnp", 0.5, graph_seed=14, lam=1e-2, mu=3e-3,
+                     rho=10.0, stop_on_legal=0)
+    A = case.adjacency()
+    W = case.weights()
+    p = orc_params(case.params())
+    t = 9
+    c = oracle.colors(W.astype(np.float64))
+    Mt = oracle.mtilde(c)
+    gS_ref = oracle.grad_s(p, t, A, c, Mt, oracle.class_sizes(c, case.k))
+    s, _ = make_solver([case], As=[A], Ws=[W])
+    s.set_t(t)
+    worst = {}
+    for bm, ntw in SHAPES:
+        s.set_options(tile_bm=bm, tile_ntw=ntw)
+        _, gs, _ = s.loss_grad(0, want_loss=False, want_gw=False)
+        worst[(bm, ntw)] = normwise(host(gs), gS_ref)
+    s.close()
+    print(f"precision {prec}: gradS error per shape {worst}")
+    # bf16 penalty operand: relative rounding 2^-9 per entry
+    assert max(worst.values()) <= 1e-2, worst
