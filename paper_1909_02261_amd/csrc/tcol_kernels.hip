@@ -75,38 +75,42 @@ __device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((
 // Checks A (n x n, row-major 0/1, symmetric, zero diagonal) and writes the
 // zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]; in fp4 two
 // entries per byte, the lower column in the low nibble, 1.0 = 0x2).
-__global__ void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
-                             uint8_t* __restrict__ A8, void* __restrict__ Aop, int* __restrict__ bad,
-                             unsigned long long* __restrict__ ones) {
-    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long total = (long long)n_pad * n_pad;
-    int i = 0, j = 0;
-    uint8_t a = 0;
-    if (e < total) {
-        i = (int)(e / n_pad);
-        j = (int)(e - (long long)i * n_pad);
+__global__ __launch_bounds__(256) void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
+                                                    uint8_t* __restrict__ A8, void* __restrict__ Aop,
+                                                    int* __restrict__ bad, unsigned long long* __restrict__ ones) {
+    __shared__ unsigned int wcount[4];
+    const long long total = (long long)n_pad * n_pad;
+    unsigned int count = 0;   // ones of A seen by this thread (2 |E| over all threads of a valid graph)
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n_pad), j = (int)(e - (long long)i * n_pad);
+        uint8_t a = 0;
         if (i < n && j < n) {
             a = A[(size_t)i * n + j];
             uint8_t b = A[(size_t)j * n + i];
             if (a > 1 || a != b || (i == j && a != 0)) atomicOr(bad, 1);
             a = a ? 1 : 0;
         }
+        count += a;
+        A8[e] = a;
+        if (prec == kPrecFP32)
+            ((float*)Aop)[e] = a ? 1.0f : 0.0f;
+        else if (prec == kPrecBF16)
+            ((uint16_t*)Aop)[e] = a ? 0x3F80 : 0;
+        else if (prec == kPrecFP8)
+            ((uint8_t*)Aop)[e] = a ? 0x38 : 0;
+        else if ((j & 1) == 0) {
+            // the even column writes the byte of the pair (n_pad is even)
+            const uint8_t a1 = (i < n && j + 1 < n) ? (A[(size_t)i * n + j + 1] ? 1 : 0) : 0;
+            ((uint8_t*)Aop)[e >> 1] = (uint8_t)((a ? 0x2 : 0) | (a1 ? 0x20 : 0));
+        }
     }
-    // count of ones (2 |E| for a valid graph): one atomic per wave
-    const unsigned long long wb = __ballot(a != 0);
-    if ((threadIdx.x & 63) == 0 && wb) atomicAdd(ones, (unsigned long long)__builtin_popcountll(wb));
-    if (e >= total) return;
-    A8[e] = a;
-    if (prec == kPrecFP32)
-        ((float*)Aop)[e] = a ? 1.0f : 0.0f;
-    else if (prec == kPrecBF16)
-        ((uint16_t*)Aop)[e] = a ? 0x3F80 : 0;
-    else if (prec == kPrecFP8)
-        ((uint8_t*)Aop)[e] = a ? 0x38 : 0;
-    else if ((j & 1) == 0) {
-        // the even column writes the byte of the pair (n_pad is even)
-        const uint8_t a1 = (i < n && j + 1 < n) ? (A[(size_t)i * n + j + 1] ? 1 : 0) : 0;
-        ((uint8_t*)Aop)[e >> 1] = (uint8_t)((a ? 0x2 : 0) | (a1 ? 0x20 : 0));
+    // one atomic per block
+    for (int sh = 32; sh >= 1; sh >>= 1) count += __shfl_xor(count, sh);
+    if ((threadIdx.x & 63) == 0) wcount[threadIdx.x >> 6] = count;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long c = (unsigned long long)wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (c) atomicAdd(ones, c);
     }
 }
 
@@ -1222,8 +1226,8 @@ hipError_t launch_init_weights(float* W, long long count, unsigned long long see
 
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
                              unsigned long long* ones, hipStream_t s) {
-    long long total = (long long)n_pad * n_pad;
-    int blocks = (int)((total + 255) / 256);
+    const long long total = (long long)n_pad * n_pad;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_pack_graph, dim3(blocks), dim3(256), 0, s, A, n, n_pad, prec, A8, Aop, bad, ones);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
