@@ -161,7 +161,8 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
-    ap.add_argument("--penalty", default="dense", choices=["auto", "dense", "gather"])
+    ap.add_argument("--penalty", default="auto", choices=["auto", "dense", "sparse"],
+                    help="penalty product: per-iteration choice (auto), dense MFMA pass, or sparse rows")
     ap.add_argument("--problem", default=None, choices=list(PROBLEMS),
                     help="run the workload's graph and sizes as another problem (default: its own)")
     ap.add_argument("--momentum", type=float, default=0.0, help="heavy-ball coefficient (0: plain step)")
@@ -212,7 +213,7 @@ def main():
     s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
     s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
-                  penalty={"auto": 0, "dense": 1, "gather": 2}[args.penalty])
+                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
     if args.autotune:
         print("[bench] autotuning tile shape / penalty mode", file=sys.stderr, flush=True)
         s.autotune()
@@ -237,7 +238,7 @@ def main():
     t_now = s.get_t()
     f_as, f_pen = gemm_flops(case, t_now)
     if opts["penalty"] == 2:
-        f_pen = 0.0          # the class gather, not the contraction, computes the penalty term
+        f_pen = 0.0          # the sparse rows, not the contraction, compute the penalty term
     gemm_s = ph["gemm"] / 1e3
     achieved = (f_as + f_pen) / gemm_s
     peak = mixed_peak(prec, f_as, f_pen)
@@ -267,7 +268,7 @@ def main():
     config = {"workload": case.name, "problem": PROBLEM_NAMES[case.problem], "n": case.n,
               "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
               "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
-              "penalty": {0: "auto", 1: "dense", 2: "gather"}[opts["penalty"]], "fused": opts["fused"]}
+              "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]}
     if case.momentum:
         config["momentum"] = case.momentum
     roof["traffic"] = measured_traffic(config)

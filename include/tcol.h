@@ -117,12 +117,20 @@ typedef struct {
     int32_t tile_ntw;       /* GEMM 16-column subtiles per wave; the instantiated (tile_bm, tile_ntw)
                                pairs are (64,2) (64,4) (128,4) (128,6) (128,8) (64,9) (128,9)
                                (256,4; 8 waves) */
-    int32_t penalty;        /* fast and epilogue paths, penalty term (A o Mt^(alpha-1) and
-                               (J-A) o Mt^(beta-1) times S, eq. 17): 0 = choose (default),
-                               1 = dense operand pass on MFMA, 2 = class gather in FP32: with
-                               one-hot S_d, (P.S_d)[i, l] is the sum of P_ij over the vertices of
-                               colour l in member d (D n terms per row instead of D n k
-                               multiply-adds); 0 currently takes 1 */
+    int32_t penalty;        /* fast and epilogue paths, penalty term P.S with
+                               P = 2 alpha lambda t A o Mt^(alpha-1) - 2 beta mu t (J-A) o Mt^(beta-1)
+                               (eq. 17, Section 3.8.2): 1 = dense operand pass on MFMA (operand
+                               bf16 in the fp4 / fp8 / bf16 modes); 2 = sparse rows in every
+                               iteration: with one-hot S_d, (P.S_d)[i, l] is the sum of P_ij over
+                               the vertices of colour l in member d, and P_ij = 0 unless j shares
+                               i's colour in some member, so each row adds its nonzeros (exact
+                               64-bit fixed-point sums of the FP32 values, rounded once);
+                               0 = choose (default): the sparse rows in the iterations where the
+                               rows average at most n / 4 class-mates and the dense pass in the
+                               others (decided on the device each iteration), the dense pass
+                               throughout when 4 D > k, the sparse rows throughout for
+                               k-partitioning.  Graphs too large for the sparse kernel's LDS
+                               take the dense pass. */
 } tcol_options;
 
 typedef struct tcol_ctx tcol_ctx;
@@ -213,14 +221,14 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * captured graph) with HIP events around each kernel on the context's stream
  * and writes the average milliseconds per iteration of each phase to
  * ms[TCOL_NPHASES]: 0 argmax colours, 1 class sizes, 2 one-hot S expansion,
- * 3 penalty (group concentration + dense operand, or the class gather, which on
- * the fast path runs after the contraction and adds its rows to G),
+ * 3 penalty (group concentration + dense operand, or the sparse rows, which on
+ * the fast path run after the contraction and add their rows to G),
  * 4 contraction A.S (+ dense penalty pass)
  * with fitness gather and, on the fused path, the update epilogue,
  * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
  * 7 counter advance.  Phase 4 is timed separately as `steps` contraction
  * launches back to back on the operands of the last iteration (one event pair,
- * so launch gaps do not count).  When as_only is non-zero it then also times
+ * so launch gaps do not count), with the dense penalty pass unless penalty = 2.  When as_only is non-zero it then also times
  * `steps` back-to-back launches of the contraction restricted to A.S with the
  * gather (W unchanged) into ms[8]; otherwise ms[8] = 0.  Synchronises the stream.
  * Errors: TCOL_EINVAL, TCOL_EHIP. */

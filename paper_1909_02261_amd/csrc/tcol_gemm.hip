@@ -461,11 +461,12 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     const int pS = st->pS;
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
-    // a graph takes either the dense operand pass or the penalty rows of the class-gather
-    // kernel (in G for the fused epilogue, in Gp for the row update); the plain path
+    // a graph takes either the dense operand pass or, in the iterations where its graph
+    // state asks for them, the sparse penalty rows (written to G before the fused
+    // epilogue, added to G after the fast path's store); the plain path
     // (passes bit 3) always takes the dense pass
-    const bool gather_pen = pen && d.pgather && !(passes & 8);
-    const bool dense_pen = pen && !gather_pen;
+    const bool sparse_pen = pen && d.psparse && !st->pdense && !(passes & 8);
+    const bool dense_pen = pen && !sparse_pen;
     // partitioning: the fitness term is -A.S, and with the operand built over D - Mt the
     // penalty product is negated as well
     const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;
@@ -564,8 +565,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     }
     if (!(passes & 4)) return;
     if constexpr (MODE == 0) {
-        // G[d][i][l] = acc (class-gather penalty rows, when present, are in Gp and the
-        // row update adds them)
+        // G[d][i][l] = acc (sparse penalty rows, when present, are added afterwards)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -620,7 +620,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 const float* w = Wc + rowoff;
                 float* wo = Wn + rowoff;
                 const float* gr = Gt + r * LDG + dm * k;
-                const float* g1 = Gg + rowoff;      // penalty rows of the class-gather kernel
+                const float* g1 = Gg + rowoff;      // sparse penalty rows
                 const int32_t* V = Vp + (size_t)dd * k;
                 float mx = -INFINITY;
                 for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
@@ -629,7 +629,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx);
                     float gv = sgn * gr[l];
-                    if (gather_pen) gv += g1[l];
+                    if (sparse_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
                     z += e;
                     q += e * gv;
@@ -645,7 +645,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
                 for (int l = l16; l < k; l += 16) {
                     const float e = expf(w[l] - mx) * rz;
                     float gv = sgn * gr[l];
-                    if (gather_pen) gv += g1[l];
+                    if (sparse_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
                     float nw = w[l] - eta * (e * (gv - rq));
                     if (smooth) nw = nw / rho;

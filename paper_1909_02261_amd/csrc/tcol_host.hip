@@ -11,7 +11,7 @@
 // Three step sequences (tcol_options.fused):
 //   0 plain: colours -> classes -> one-hot S -> dense penalty operand -> contraction
 //     storing G -> fitness / stop -> update -> counter;
-//   1 fast: classes -> penalty rows (class-gather kernel) or dense operand -> one-hot S ->
+//   1 fast: classes -> penalty rows (sparse kernel) or dense operand -> one-hot S ->
 //     contraction storing G -> fitness / stop -> update that also colours the new rows
 //     -> counter (the colours of the first iteration come from one argmax pass);
 //   2 epilogue: classes -> penalty -> one-hot S -> contraction whose epilogue updates W
@@ -38,7 +38,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_VEL, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_CINFO, B_SQ, B_VEL, B_COUNT
 };
 
 struct Layout {
@@ -79,6 +79,8 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     sz[B_CLSV] = sizeof(int16_t) * (size_t)p.D * round_up(p.n, 64);
     sz[B_CLSOFF] = sizeof(int32_t) * (size_t)p.D * (p.k + 1);
+    sz[B_CINFO] = 8 * (size_t)round_up(p.D, 8) * p.n;
+    sz[B_SQ] = sizeof(long long) * (size_t)p.D;
     sz[B_VEL] = p.momentum != 0.0f ? sizeof(float) * dnk : 0;
     size_t o = 0;
     for (int b = 0; b < B_COUNT; ++b) {
@@ -132,10 +134,10 @@ struct tcol_ctx {
     bool fused_ok = false;          // the fused path is available for these graphs
     bool any_momentum = false;      // some graph takes heavy-ball steps (no epilogue path)
     int update_var = 0;             // row-update variant: bit 0 added fitness term, bit 1 momentum
-    int pg_R = 0, pg_PM = 0;        // class-gather penalty: rows per block, members per list group
-    size_t pg_lds = 0;              // dynamic LDS of the class-gather kernel
+    int ps_PM = 0, ps_threads = 0;  // sparse penalty: members per accumulator group, block size
+    size_t ps_lds = 0;              // dynamic LDS of the sparse penalty kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
-    int total_pg = 0;               // blocks of the class-gather kernel (0: no graph uses it)
+    int total_ps = 0;               // blocks of the sparse penalty kernel (0: no graph uses it)
     int total_rows = 0, total_mem = 0, total_mt = 0, total_ex = 0;
     int total_gm[2] = {0, 0};
     int kmax = 0, nmax = 0;
@@ -259,27 +261,27 @@ static void pick_shapes(tcol_ctx* c) {
     c->fused_ok = f.ntw > 0 && common_precision(c) >= 0;
 }
 
-// Automatic penalty mode: the dense bf16 (fp32) operand pass.  The class gather does
-// k times fewer operations but is latency-bound in its current form and slower on
-// every workload measured, so it runs only on request.
-static bool gather_preferred(const tcol_graph_params&) { return false; }
+// Automatic penalty mode.  A balanced colouring gives each row about D n / k class-mates,
+// and the per-iteration choice takes the sparse rows only while the rows average at most
+// n / 4 of them: with 4 D > k that never happens, so such graphs keep the dense operand
+// pass (and skip the class lists).  Otherwise the choice is made per iteration, and
+// partitioning, whose rows are dense either way, always takes the sparse rows.
+static bool sparse_preferred(const tcol_graph_params& p) {
+    return p.problem == TCOL_KPART || p.problem == TCOL_BKPART || 4LL * p.D <= p.k;
+}
 
-// Rows per block R and members per list group PM of the class-gather kernel: the largest
-// R <= 4 that keeps at least 500 blocks, with the largest PM <= min(D, 16) whose LDS fits
-// two blocks per CU (80 KB), else one block per CU (160 KB); R is lowered when neither
-// fits.  Returns false when nothing fits.
-static bool pick_gather(int kmax, int dmax, int nmax, int rows_total, int& R, int& PM) {
-    int r = 4;
-    while (r > 1 && rows_total / r < 500) r /= 2;
-    for (; r >= 1; r /= 2)
-        for (size_t budget : {(size_t)80 * 1024, (size_t)160 * 1024})
-            for (int pm = std::min(dmax, 16); pm >= 1; --pm)
-                if (penalty_gather_group_fits(pm, kmax, nmax) &&
-                    penalty_gather_lds(r, pm, kmax, dmax, nmax) <= budget) {
-                    R = r;
-                    PM = pm;
-                    return true;
-                }
+// Members per accumulator group PM of the sparse penalty kernel (a multiple of 8, at most
+// D rounded up to 8): the largest whose LDS keeps three 512-thread blocks per CU (53 KB),
+// else two (80 KB), else one (160 KB).  Returns false when not even PM = 8 fits.
+static bool pick_sparse(int kmax, int dmax, int nmax, int& PM, int& threads) {
+    const int top = round_up(dmax, 8);
+    for (size_t budget : {(size_t)53 * 1024, (size_t)80 * 1024, (size_t)160 * 1024})
+        for (int pm = top; pm >= 8; pm -= 8)
+            if (penalty_sparse_lds(pm, kmax, dmax, nmax) <= budget) {
+                PM = pm;
+                threads = budget > 80 * 1024 ? 1024 : 512;
+                return true;
+            }
     return false;
 }
 
@@ -288,38 +290,38 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     pick_shapes(c);
     HIPCHK(gemm_prepare(c->shape));
     if (c->fused_ok) HIPCHK(gemm_prepare(c->fshape));
-    HIPCHK(penalty_gather_prepare());
+    HIPCHK(penalty_sparse_prepare());
     const int BN0 = gemm_bn(c->shape.ntw);
     const int BN1 = c->fused_ok ? gemm_bn(c->fshape.ntw) : 0;
-    // class-gather penalty: a graph takes it on request (penalty 2) or when the automatic
-    // choice prefers it
-    int pg_k = 0, pg_D = 0, pg_n = 0, pg_rows = 0;
+    // sparse penalty: a graph takes it on request (penalty 2) or when the automatic choice
+    // prefers it
+    int ps_k = 0, ps_D = 0, ps_n = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const int pen = c->opt.penalty;
-        c->hdesc[g].pgather = (pen == 2 || (pen == 0 && gather_preferred(p))) ? 1 : 0;
-        if (c->hdesc[g].pgather) {
-            pg_k = std::max(pg_k, p.k);
-            pg_D = std::max(pg_D, p.D);
-            pg_n = std::max(pg_n, p.n);
-            pg_rows += p.n;
+        c->hdesc[g].psparse = (pen == 2 || (pen == 0 && sparse_preferred(p))) ? 1 : 0;
+        c->hdesc[g].ps_mode = pen == 2 ? 1 : 2;
+        if (c->hdesc[g].psparse) {
+            ps_k = std::max(ps_k, p.k);
+            ps_D = std::max(ps_D, p.D);
+            ps_n = std::max(ps_n, p.n);
         }
     }
-    c->pg_R = c->pg_PM = 0;
-    c->pg_lds = 0;
-    if (pg_k > 0) {
+    c->ps_PM = c->ps_threads = 0;
+    c->ps_lds = 0;
+    if (ps_k > 0) {
         // graphs too large for the kernel's LDS take the dense pass
-        int R = 0, PM = 0;
-        if (pick_gather(pg_k, pg_D, pg_n, pg_rows, R, PM)) {
-            c->pg_R = R;
-            c->pg_PM = PM;
-            c->pg_lds = penalty_gather_lds(R, PM, pg_k, pg_D, pg_n);
+        int PM = 0, threads = 0;
+        if (pick_sparse(ps_k, ps_D, ps_n, PM, threads)) {
+            c->ps_PM = PM;
+            c->ps_threads = threads;
+            c->ps_lds = penalty_sparse_lds(PM, ps_k, ps_D, ps_n);
         } else {
-            for (int g = 0; g < c->G; ++g) c->hdesc[g].pgather = 0;
-            pg_k = 0;
+            for (int g = 0; g < c->G; ++g) c->hdesc[g].psparse = 0;
+            ps_k = 0;
         }
     }
-    c->prep_lds = prep_lds(c->kmax, c->nmax, pg_k > 0);
+    c->prep_lds = prep_lds(c->kmax, c->nmax, ps_k > 0);
     int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
@@ -329,8 +331,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         rows += p.D * p.n;
         d.mem_begin = mem;
         mem += p.D;
-        d.pg_begin = pg;
-        if (d.pgather) pg += ceil_div(p.n, c->pg_R);
+        d.ps_begin = pg;
+        if (d.psparse) pg += p.n;
         d.mt_begin = mt;
         d.mt_T = L.mt_T;
         d.mt_ts = L.mt_ts;
@@ -353,7 +355,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     }
     c->total_rows = rows;
     c->total_mem = mem;
-    c->total_pg = pg;
+    c->total_ps = pg;
     c->total_mt = mt;
     c->total_ex = ex;
     c->total_gm[0] = gm0;
@@ -392,30 +394,38 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     return hipSuccess;
 }
 
-// penalty of the fast and epilogue paths: class-gather rows or the dense operand, per graph
-// (the epilogue path takes the class-gather rows in G before the contraction, whose
-// epilogue adds them; the fast path adds them to the contraction's G afterwards,
-// enqueue_gather_add)
+// penalty of the fast and epilogue paths: sparse penalty rows or the dense operand, per
+// graph and, for graphs that choose per iteration, per iteration (launch_decide).  On
+// the epilogue path the sparse rows go to G before the contraction, whose epilogue adds
+// them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
-    if (c->total_pg > 0 && path_of(c) == 2)
-        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_PM, c->pg_lds, 1, 0, s));
+    if (c->total_ps > 0 && path_of(c) == 2)
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
 
-static hipError_t enqueue_gather_add(tcol_ctx* c, hipStream_t s) {
-    if (c->total_pg > 0)
-        HIPRET(launch_penalty_gather(c->ddesc, c->G, c->total_pg, c->pg_R, c->pg_PM, c->pg_lds, 1, 1, s));
+// class sizes and lists of the current colours, then (fast and epilogue paths) the
+// iteration's penalty choice, which the expansion, penalty and contraction read
+static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+    if (c->total_ps > 0) HIPRET(launch_decide(c->ddesc, c->G, s));
+    return hipSuccess;
+}
+
+static hipError_t enqueue_sparse_add(tcol_ctx* c, hipStream_t s) {
+    if (c->total_ps > 0)
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1, s));
     return hipSuccess;
 }
 
 // one iteration on the fast path; c[pS] holds the colours of the current weights
 static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+    HIPRET(enqueue_prep(c, s));
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
-    HIPRET(enqueue_gather_add(c, s));
+    HIPRET(enqueue_sparse_add(c, s));
     HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
     HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
     HIPRET(launch_advance(c->ddesc, c->G, s));
@@ -424,7 +434,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
 
 // one iteration on the epilogue path; c[pS] holds the colours of the current weights
 static hipError_t enqueue_step_fused(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+    HIPRET(enqueue_prep(c, s));
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
@@ -670,6 +680,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.cTs = round_up(q.D, 8);
         d.cls_v = (int16_t*)(b + L.off[B_CLSV]);
         d.cls_off = (int32_t*)(b + L.off[B_CLSOFF]);
+        d.cinfo = (int2*)(b + L.off[B_CINFO]);
+        d.sq = (long long*)(b + L.off[B_SQ]);
         // look-up tables over the group concentration m = 0..D (host libm, FP64); for
         // partitioning the powers are of D - m (M replaced by J - M)
         std::vector<float> lp(q.D + 1), lb(q.D + 1);
@@ -844,7 +856,10 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(hipEventRecord(ev[0], s));
         if (path == 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
         HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+        if (path != 0)
+            HIPCHK(enqueue_prep(c, s));
+        else
+            HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
         HIPCHK(hipEventRecord(ev[2], s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, path != 0 ? 1 : 0, s));
         HIPCHK(hipEventRecord(ev[3], s));
@@ -858,7 +873,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         else
             HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
-        if (path == 1) HIPCHK(enqueue_gather_add(c, s));
+        if (path == 1) HIPCHK(enqueue_sparse_add(c, s));
         HIPCHK(hipEventRecord(ev[6], s));
         HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
         HIPCHK(hipEventRecord(ev[7], s));
@@ -869,7 +884,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(hipEventSynchronize(ev[9]));
         float x[NE - 1];
         for (int i = 0; i + 1 < NE; ++i) HIPCHK(hipEventElapsedTime(&x[i], ev[i], ev[i + 1]));
-        // phases: colours, class sizes, expansion, penalty (operand or class gather),
+        // phases: colours, class sizes, expansion, penalty (operand or sparse rows),
         // contraction, fitness, update, advance
         acc[0] += x[0];
         acc[1] += x[1];
@@ -882,14 +897,16 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     }
     for (int i = 0; i < 8; ++i) ms[i] = (float)(acc[i] / steps);
     // the contraction again, `steps` launches back to back on the operands of the last
-    // iteration (its G store is idempotent; the conflict accumulators are cleared after)
+    // iteration, with the dense penalty pass unless the graphs take the sparse rows in
+    // every iteration (its G store is idempotent; the conflict accumulators are cleared
+    // after; the operand values may be stale, which does not change the work)
     {
         HIPCHK(hipEventRecord(ev[0], s));
         for (int it = 0; it < steps; ++it) {
             if (path == 2)
                 HIPCHK(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
             else
-                HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
+                HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 || c->opt.penalty != 2 ? 15 : 7, 0, s));
         }
         HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(launch_state(c->ddesc, c->G, 4, -1, 0, s));

@@ -57,7 +57,7 @@ struct GraphState {
     int pW;             // fused path: which W buffer holds the current weights (0 = caller's)
     int pS;             // fused path: which colour / S buffer set is current
     int next_bad;       // fused path: the update produced a non-finite weight
-    int pad_;
+    int pdense;         // sparse penalty graphs: this iteration takes the dense operand pass
 };
 
 // per-graph descriptor, uploaded once at init
@@ -97,14 +97,18 @@ struct GraphDev {
     GraphState* st;
     int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
     int cTs;                  // row stride of cT (D rounded up to 8)
-    int pgather;              // fast / epilogue paths: penalty rows by the class-gather kernel
-                              // (else the dense operand pass of the contraction)
-    int16_t* cls_v;           // [D][cs] vertices of each member grouped by colour, increasing j in a class
+    int psparse;              // fast / epilogue paths: penalty rows from the nonzeros of P, in
+                              // every iteration or in those that ask for them (ps_mode); else
+                              // the dense operand pass of the contraction
+    int16_t* cls_v;           // [D][cs] vertices of each member grouped by colour
     int32_t* cls_off;         // [D][k + 1] start of colour l's vertices in cls_v (last entry n)
+    int2* cinfo;              // [n][cTs] start in cls_v and size of the class of vertex i in member d
+    long long* sq;            // [D] sum over colours of the squared class sizes of each member
+    int ps_mode;              // sparse penalty: 1 every iteration, 2 when the classes are small
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
-    int pg_begin;             // blocks of the class-gather penalty kernel (row tiles)
+    int ps_begin;             // blocks (rows) of the sparse penalty kernel
     int mt_begin;             // tiles of the group-concentration kernel
     int mt_T;                 // tiles per side
     int mt_ts;                // tile side of the group-concentration kernel (32 or 64)
@@ -121,7 +125,7 @@ enum : int {
     kFlagMtOut = 2,       // ... and Mt to an output buffer
     kFlagForcePen = 4,    // build the penalty operand even when lambda t = mu t = 0
     kFlagReport = 8,      // fitness kernel only reports (no stop, no state change)
-    kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty
+    kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty this iteration
     kFlagFused = 32,      // fitness kernel of the fused path: accept the update by flipping buffers
 };
 

@@ -155,10 +155,11 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
 
 // Class sizes #V_{d,l} of member d, its added fitness (equity or colour cost) and
 // the vertex-major copy of its colours.
-// For a graph on the class-gather penalty also the member's vertices grouped by
-// colour (stable counting sort: each class in increasing vertex order, so the
-// penalty sums run in the same order on every run).  One block per member.
-// Dynamic LDS: k counts, and with the class lists 4 k per-wave cursors and n entries.
+// For a graph on the sparse penalty also the member's vertices grouped by colour
+// (counting sort) and, for each vertex, the start and size of its class.  One block
+// per member.
+// Dynamic LDS: k counts, and with the class lists 4 k per-wave cursors, k class starts
+// and n entries.
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
                                               int next) {
     extern __shared__ int prep_sh[];
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     int16_t* __restrict__ cT = d.cT;
     const size_t cTs = d.cTs;
     int* cnt = prep_sh;
-    const bool lists = d.pgather != 0;              // uniform over the block
+    const bool lists = d.psparse != 0;              // uniform over the block
     // with the class lists each wave counts its own quarter of the vertices
     constexpr int NW = 4;
     const int wv = tid >> 6, lane = tid & 63;
@@ -225,7 +226,18 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
         if (tid == 0) d.feq[m] = fsum[0] + fsum[1] + fsum[2] + fsum[3];
     }
     if (!lists) return;
-    int16_t* lst = (int16_t*)(cw + NW * k);         // [n]
+    {
+        // sum_l #V_l^2: the class-mate increments of all rows for this member
+        long long q2 = 0;
+        for (int l = tid; l < k; l += 256) q2 += (long long)cnt[l] * cnt[l];
+        for (int sh = 32; sh >= 1; sh >>= 1) q2 += __shfl_xor(q2, sh);
+        __shared__ long long qsum[4];
+        if ((tid & 63) == 0) qsum[tid >> 6] = q2;
+        __syncthreads();
+        if (tid == 0) d.sq[m] = qsum[0] + qsum[1] + qsum[2] + qsum[3];
+    }
+    int* offl = cw + NW * k;                        // [k] class starts
+    int16_t* lst = (int16_t*)(offl + k);            // [n]
     int32_t* __restrict__ off = d.cls_off + (size_t)m * (k + 1);
     int16_t* __restrict__ cv = d.cls_v + (size_t)m * d.cs;
     // exclusive scan of the counts: runs of `per` classes per thread, the 256 run sums
@@ -256,6 +268,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     int acc = part[tid];
     for (int l = lb; l < le; ++l) {
         off[l] = acc;
+        offl[l] = acc;
         int q = acc;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -267,289 +280,344 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     }
     if (tid == 0) off[k] = n;
     __syncthreads();
-    // stable placement: each wave walks its quarter in order, 64 vertices at a time
-    // (colours loaded eight chunks ahead); lanes of one colour find each other with
-    // one ballot per colour bit and take consecutive slots
+    // placement: each vertex takes the next slot of its colour in its wave's range (the
+    // order inside a class is not used: the penalty counts do not depend on it), and
+    // records its class's start and size for this member
     {
-        int nb = 0;
-        while ((1 << nb) < k) ++nb;
-        const unsigned long long lt = (1ull << lane) - 1ull;
         int* cur = cw + wv * k;
+        int2* __restrict__ cinfo = d.cinfo;
         const int qb = wv * Q, qe = min(n, (wv + 1) * Q);
-        for (int i8 = qb; i8 < qe; i8 += 512) {
-            int xs[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i8 + 64 * u + lane;
-                xs[u] = i < qe ? (int)gview(c)[i] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i8 + 64 * u + lane;
-                if (i8 + 64 * u >= qe) break;           // uniform over the wave
-                const bool v = i < qe;
-                const int x = xs[u];
-                unsigned long long match = __ballot(v);
-                for (int bit = 0; bit < nb; ++bit) {
-                    const bool on = (x >> bit) & 1;
-                    const unsigned long long bb = __ballot(on);
-                    match &= on ? bb : ~bb;
-                }
-                const int base = v ? cur[x] : 0;
-                wave_sync();
-                if (v) {
-                    lst[base + __builtin_popcountll(match & lt)] = (int16_t)i;
-                    if ((match >> lane) == 1ull) cur[x] = base + __builtin_popcountll(match);   // last of its colour
-                }
-                wave_sync();
-            }
+        for (int i = qb + lane; i < qe; i += 64) {
+            const int x = gview(c)[i];
+            const int pos = atomicAdd(&cur[x], 1);
+            lst[pos] = (int16_t)i;
+            cinfo[(size_t)i * cTs + m] = make_int2(offl[x], cnt[x]);
         }
     }
     __syncthreads();
     for (int i = tid; i < n; i += 256) cv[i] = lst[i];
 }
 
-// ------------------------------------------------------ class-gather penalty ----
+// -------------------------------------------------------- sparse penalty rows ----
 
-// Penalty rows by class gather.  The penalty operand
-//   P_ij = t * (a_ij ? 2 alpha lambda m^(alpha-1) : -[i != j or bonus_diag] 2 beta mu m^(beta-1)),
-// m = Mt_ij, enters the gradient as (P.S_d)[i, l], and with one-hot S_d that is the
-// sum of P_ij over the vertices j of colour l in member d: D n terms per row,
-// against D n k multiply-adds for the dense product.  A block of NT threads (1024
-// when it has a CU's LDS to itself, else 512) takes R rows:
-//   1. Mt_ij for its rows from the class lists: j shares row i's colour in member d
-//      exactly when j is in the class of c_d(i) in d, so each member adds one to the
-//      count of every vertex of that class (D |class| increments per row, against
-//      n D comparisons for the whole row);
-//   2. the counts become the values P_ij, FP32, kept in LDS as [j][R];
-//   3. the class lists go to LDS PM members at a time (two buffers: the next group
-//      is loaded while the current one is summed); for every (member, colour) one
-//      thread walks the class (increasing j) and sums the values of its vertices
-//      for the R rows in FP32; the sums are added to G[d][i][l] = (A.S_d)[i, l] after
-//      the contraction (accumulate 1), or written there for the contraction's
-//      epilogue to add A.S_d (accumulate 0).
-// Dynamic LDS (penalty_gather_lds): values [n_pad + 1][R] f32 (the last row stays
-// zero: list slots outside a class read it, so a chunk's eight reads issue without
-// branches), table [2 (D + 1)] f32, lists [2][PM][cs] i16, offsets [2][PM][k + 1] i32.
-constexpr int kPgMaxL = 8;      // 16-byte list units per thread per group (512 threads)
-constexpr int kPgMaxO = 9;      // offsets per thread per group (512 threads)
+// Penalty rows from the nonzeros of P.  The penalty operand
+//   P_ij = t * (a_ij ? 2 alpha lambda x^(alpha-1) : -[i != j or bonus_diag] 2 beta mu x^(beta-1)),
+// x = Mt_ij (D - Mt_ij for partitioning), enters the gradient as (P.S_d)[i, l], and
+// with one-hot S_d that is the sum of P_ij over the vertices j of colour l in member
+// d.  For colouring P_ij vanishes unless j shares row i's colour in some member
+// (alpha, beta > 1 give 0^(alpha-1) = 0): a few hundred of the n entries of a row
+// in a typical iteration.  One block of NT threads per row i:
+//   1. Mt_ij from the class lists: j shares i's colour in member d exactly when j is
+//      in the class of c_d(i), so each member adds one to the count of every vertex
+//      of that class; the sum_d |class| increments are spread over the whole block.
+//      When the classes are large (more than n D / 8 increments: the population
+//      briefly collapses into a few giant classes after each smoothing) every j
+//      compares its vertex-major colours with row i's instead (n D comparisons);
+//   2. the counts become table indices of P_ij, and the nonzero entries go to a list
+//      (j, index);
+//   3. members are taken PM at a time: every listed j adds P_ij to the accumulator
+//      of (d, c_d(j)) for each member d of the group (c_d(j) from the vertex-major
+//      colours; consecutive lanes take consecutive members, so the atomics of one
+//      instruction hit different accumulators even when a class holds most of the
+//      vertices), then the group's sums go to G[d][i][l], added to the contraction's
+//      A.S_d (accumulate 1) or written for the contraction's epilogue (accumulate 0).
+// A graph choosing per iteration (ps_mode 2) takes these rows only in the iterations
+// where k_decide found its classes small; otherwise the contraction's dense pass.
+// Steps 1 and 3 issue the loads of their next batch before the atomics of the current
+// one.  The sums are taken in 64-bit fixed point: every table value times 2^sc, with sc
+// chosen so that n max|P| stays below 2^62, is an integer (for any table whose values
+// span less than 2^26) and integer sums do not depend on the order of the additions,
+// so the LDS atomics give the same bits on every run.  The result is the exact sum of
+// the FP32 values P_ij rounded once to FP32.
+// Dynamic LDS (penalty_sparse_lds): table [2 (D + 1) + 1] i64 (the last entry 0, for
+// an excluded diagonal), class starts and the prefix of the class sizes [D + 1] i32
+// each, the list length, row i's colours [cTs] i16, list [n_pad] u32, then counts
+// [n_pad] u32 overlaid by the group's accumulators [PM][k] i64.
+__host__ __device__ inline size_t ps_tab_words(int D) { return ((size_t)2 * (D + 1) + 1 + 1) & ~(size_t)1; }
+__host__ __device__ inline size_t ps_int_words(int D) { return ((size_t)D + 1 + 3) & ~(size_t)3; }
+constexpr int kPsBatch = 8;     // entries per thread per batch in steps 1 and 3
+constexpr int kPsA8 = 2;        // adjacency words per thread loaded at the start
 
-__host__ __device__ inline size_t pg_off_words(int PM, int k) { return ((size_t)PM * (k + 1) + 3) & ~(size_t)3; }
-
-template <int R, int NT>
-__global__ __launch_bounds__(NT) void k_pen_gather(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                           int honor_stop, int PM, int accumulate) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t pg_sh[];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                   int honor_stop, int PM, int accumulate) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t ps_sh[];
+    constexpr int B = kPsBatch;
     const int b = blockIdx.x;
     if (b >= total_blocks) return;
-    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.pg_begin; })];
+    const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
-    if (!d.pgather || !pen_active(d, st)) return;
+    if (!d.psparse || st->pdense || !pen_active(d, st)) return;
     const int n = d.n, k = d.k, D = d.D, cs = d.cs;
     const int n_pad = d.n_pad;
     const size_t cTs = d.cTs;
-    const int16_t* __restrict__ cT = d.cT;
-    const uint8_t* __restrict__ A8 = d.A8;
-    const int16_t* __restrict__ clsv = d.cls_v;
-    const int32_t* __restrict__ clsoff = d.cls_off;
-    float* __restrict__ Gg = d.G;
+    const int i = b - d.ps_begin;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int T = 2 * (D + 1) + 1, zslot = T - 1;
+    long long* tab = (long long*)ps_sh;                       // [ps_tab_words(D)]
+    int* cbeg = (int*)(tab + ps_tab_words(D));                 // [ps_int_words(D)]
+    int* pre = cbeg + ps_int_words(D);                         // [ps_int_words(D)]
+    int* nzc = pre + ps_int_words(D);                          // [4]: list length, max-exponent
+    int16_t* ci = (int16_t*)(nzc + 4);                         // [cTs]
+    uint32_t* list = (uint32_t*)(ci + cTs);                    // [n_pad]
+    uint32_t* cnt = list + n_pad;                              // [n_pad], steps 1-2
+    unsigned long long* acc = (unsigned long long*)cnt;        // [PM][k], step 3
+    const float tf = (float)st->t;
     const bool diag = d.bonus_diag != 0;
-    const int i0 = (b - d.pg_begin) * R;
-    const int rows = min(R, n - i0);
-    const int tid = threadIdx.x;
-    float* vals = (float*)pg_sh;                               // [n_pad + 1][R]
-    uint32_t* cnt = (uint32_t*)pg_sh;                          // the same words, phase 1
-    const int vrows = n_pad + (R >= 4 ? 1 : 4 / R);            // whole 16-byte units
-    float* lut = vals + (size_t)vrows * R;                     // [2 (D + 1) + 1], last entry 0
-    int16_t* lists = (int16_t*)(lut + ((2 * (D + 1) + 1 + 3) & ~3));   // [2][PM][cs]
-    const int zslot = 2 * (D + 1);
+    const int16_t* __restrict__ cT = d.cT;
     // partitioning: the values are those of the dense operand, whose product the
     // contraction negates along with A.S
     const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;
-    const size_t lst_stage = (size_t)PM * cs;
-    const size_t off_stage = pg_off_words(PM, k);
-    int32_t* offs = (int32_t*)(lists + 2 * lst_stage);         // [2][off_stage]
-    const int ngroups = (D + PM - 1) / PM;
 
-    // group loads go through registers: issued early, written to LDS after the
-    // work that hides them
-    constexpr int ML = kPgMaxL * 512 / NT, MO = (kPgMaxO * 512 + NT - 1) / NT;
-    u32x4n lr[ML];
-    int32_t orr[MO];
-    auto fetch = [&](int grp) {
-        const int dg = grp * PM, mc = min(PM, D - dg);
-        const int nu = mc * cs / 8;
-        const int16_t* src = clsv + (size_t)dg * cs;
+    // 0. the adjacency bytes of step 2's first passes, the row's colours and classes
+    // (one round of loads); counts cleared; the table's largest magnitude
+    const uint8_t* __restrict__ arow = d.A8 + (size_t)i * n_pad;
+    uint32_t a4pre[kPsA8];
 #pragma unroll
-        for (int u = 0; u < ML; ++u) {
-            const int e = tid + u * NT;
-            if (e < nu) lr[u] = gload16(src + 8 * e);
-        }
-        const int no = mc * (k + 1);
-        const int32_t* so = clsoff + (size_t)dg * (k + 1);
-#pragma unroll
-        for (int u = 0; u < MO; ++u) {
-            const int e = tid + u * NT;
-            if (e < no) orr[u] = gview(so)[e];
-        }
-    };
-    auto put = [&](int grp, int buf) {
-        const int dg = grp * PM, mc = min(PM, D - dg);
-        const int nu = mc * cs / 8;
-        int16_t* dl = lists + buf * lst_stage;
-#pragma unroll
-        for (int u = 0; u < ML; ++u) {
-            const int e = tid + u * NT;
-            if (e < nu) *(u32x4n*)(dl + 8 * e) = lr[u];
-        }
-        const int no = mc * (k + 1);
-        int32_t* dof = offs + buf * off_stage;
-#pragma unroll
-        for (int u = 0; u < MO; ++u) {
-            const int e = tid + u * NT;
-            if (e < no) dof[e] = orr[u];
-        }
-    };
-
-    fetch(0);
-    const float tf = (float)st->t;
-    for (int e = tid; e < vrows * R / 4; e += NT) ((u32x4n*)cnt)[e] = u32x4n{0u, 0u, 0u, 0u};
-    for (int m = tid; m <= D; m += NT) {
-        lut[m] = -(tf * d.lut_bon[m]);
-        lut[D + 1 + m] = tf * d.lut_pen[m];
+    for (int u = 0; u < kPsA8; ++u) {
+        const int j0 = 4 * (tid + u * NT);
+        a4pre[u] = j0 < n ? gview((const uint32_t*)(arow + j0))[0] : 0u;
     }
-    if (tid == 0) lut[zslot] = 0.0f;                           // the excluded diagonal
+    for (int dm = tid; dm < (int)cTs; dm += NT) {
+        ci[dm] = gview(cT)[(size_t)i * cTs + dm];
+        if (dm < D) {
+            // (start, size) as one 8-byte load: start in the low word
+            const unsigned long long cl = gview((const unsigned long long*)d.cinfo)[(size_t)i * cTs + dm];
+            cbeg[dm] = (int)(uint32_t)cl;
+            pre[dm + 1] = (int)(uint32_t)(cl >> 32);
+        }
+    }
+    for (int e = tid; e < n_pad / 4; e += NT) ((u32x4n*)cnt)[e] = u32x4n{0u, 0u, 0u, 0u};
+    if (tid == 0) { nzc[0] = 0; nzc[1] = 0; pre[0] = 0; }
     __syncthreads();
-    // 1. Mt_ij: one thread per (row, member) adds one for each vertex of the row's class
-    for (int e = tid; e < rows * D; e += NT) {
-        const int r = e / D, dm = e - r * D;
-        const int col = gview(cT)[(size_t)(i0 + r) * cTs + dm];
-        const int32_t* o = clsoff + (size_t)dm * (k + 1) + col;
-        const int beg = gview(o)[0], end = gview(o)[1];
-        const int16_t* lv = clsv + (size_t)dm * cs;
-        for (int q0 = beg & ~7; q0 < end; q0 += 8) {
-            const u32x4n w = gload16(lv + q0);
-            const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+    for (int vi = tid; vi < T - 1; vi += NT) {
+        const float v = vi <= D ? tf * d.lut_bon[vi] : tf * d.lut_pen[vi - D - 1];
+        if (v != 0.0f) {
+            int ex;
+            frexpf(v, &ex);
+            // exponents are compared as ex + 256 > 0 (the counter starts at 0 = none)
+            atomicMax(&nzc[1], ex + 256);
+        }
+    }
+    // prefix of the class sizes (wave 0, 64 members at a time)
+    if (tid < 64) {
+        int carry = 0;
+        for (int base = 0; base < D; base += 64) {
+            const int dm = base + lane;
+            int x = dm < D ? pre[dm + 1] : 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int q = q0 + u;
-                if (q >= beg && q < end) {
-                    const int j = (int)((wv[u >> 1] >> (16 * (u & 1))) & 0xFFFFu);
-                    atomicAdd(&cnt[j * R + r], 1u);
+            for (int sh = 1; sh < 64; sh <<= 1) {
+                const int y = __shfl_up(x, sh);
+                if (lane >= sh) x += y;
+            }
+            if (dm < D) pre[dm + 1] = carry + x;
+            carry += __shfl(x, 63);
+        }
+    }
+    __syncthreads();
+    // fixed-point scale: |P_ij| < 2^E1 and n < 2^E2, so sums stay below 2^(E1 + E2) <= 2^62
+    const int emax = nzc[1];
+    const int sc = 62 - ((emax > 0 ? emax - 256 : 0) + (32 - __builtin_clz((unsigned)n)));
+    for (int vi = tid; vi < T; vi += NT) {
+        float v = 0.0f;
+        if (vi < T - 1) v = vi <= D ? -(tf * d.lut_bon[vi]) : tf * d.lut_pen[vi - D - 1];
+        tab[vi] = (long long)rint(ldexp((double)v, sc));
+    }
+    // 1. Mt_ij
+    const int W1 = pre[D];
+    if ((long long)W1 * 8 <= (long long)n * D) {
+        // from the class lists: entry q of the concatenated classes belongs to member dm
+        // with pre[dm] <= q < pre[dm + 1] (found once by bisection, then advanced)
+        int dm = 0;
+        if (tid < W1) {
+            int lo = 0, hi = D - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= tid) lo = mid; else hi = mid - 1;
+            }
+            dm = lo;
+        }
+        int js[B];
+        auto fetch = [&](int q0) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int q = q0 + u * NT;
+                js[u] = -1;
+                if (q < W1) {
+                    while (pre[dm + 1] <= q) ++dm;
+                    js[u] = gview(d.cls_v)[(size_t)dm * cs + cbeg[dm] + (q - pre[dm])];
                 }
             }
+        };
+        fetch(tid);
+        for (int q0 = tid; q0 < W1; q0 += B * NT) {
+            int cur[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) cur[u] = js[u];
+            if (q0 + B * NT < W1) fetch(q0 + B * NT);
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (cur[u] >= 0) atomicAdd(&cnt[cur[u]], 1u);
         }
-    }
-    __syncthreads();
-    // 2. counts -> P_ij, 16 vertices per thread (the diagonal, m = D, is excluded
-    // from the bonus unless bonus_diag)
-    for (int j0 = 16 * tid; j0 < n; j0 += 16 * NT) {
-        // a_ij of the 16 vertices for each row as a bit mask (A8 bytes are 0 or 1)
-        uint32_t em[R];
+    } else {
+        // by comparison: eight members per 16-byte word of a vertex-major row; members
+        // beyond D (the row padding) are masked out
+        const int nw = (int)(cTs / 8);
+        for (int j0 = tid; j0 < n; j0 += 2 * NT) {
+            int m2[2] = {0, 0};
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const u32x4n a = r < rows ? gload16(A8 + (size_t)(i0 + r) * n_pad + j0) : u32x4n{0u, 0u, 0u, 0u};
-            const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
-            uint32_t m = 0;
+            for (int u = 0; u < 2; ++u) {
+                const int j = j0 + u * NT;
+                if (j >= n) continue;
+                const int16_t* row = cT + (size_t)j * cTs;
+                for (int w = 0; w < nw; ++w) {
+                    const u32x4n x = gload16(row + 8 * w);
+                    const u32x4n y = *(const u32x4n*)(ci + 8 * w);
+                    const uint32_t xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
-                m |= ((aw[h] & 1u) | ((aw[h] >> 7) & 2u) | ((aw[h] >> 14) & 4u) | ((aw[h] >> 21) & 8u)) << (4 * h);
-            em[r] = m;
-        }
-#pragma unroll 2
-        for (int u = 0; u < 16; ++u) {
-            const int j = j0 + u;
-            uint32_t cw[R];
-            uint32_t* cp = cnt + (size_t)j * R;
-            if constexpr (R >= 4) {
-#pragma unroll
-                for (int h = 0; h < R; h += 4) {
-                    const u32x4n x = *(const u32x4n*)(cp + h);
-                    cw[h] = x.x; cw[h + 1] = x.y; cw[h + 2] = x.z; cw[h + 3] = x.w;
-                }
-            } else if constexpr (R == 2) {
-                const uint2 x = *(const uint2*)cp;
-                cw[0] = x.x; cw[1] = x.y;
-            } else {
-                cw[0] = cp[0];
-            }
-            float fv[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int m = (int)cw[r];
-                const bool edge = (em[r] >> u) & 1u;
-                const bool excl = !edge && !diag && j == i0 + r;
-                fv[r] = lut[excl ? zslot : (edge ? D + 1 + m : m)];
-            }
-            if constexpr (R >= 4) {
-#pragma unroll
-                for (int h = 0; h < R; h += 4)
-                    *(u32x4n*)(cp + h) = u32x4n{__float_as_uint(fv[h]), __float_as_uint(fv[h + 1]),
-                                                __float_as_uint(fv[h + 2]), __float_as_uint(fv[h + 3])};
-            } else if constexpr (R == 2) {
-                *(uint2*)cp = uint2{__float_as_uint(fv[0]), __float_as_uint(fv[1])};
-            } else {
-                cp[0] = __float_as_uint(fv[0]);
-            }
-        }
-    }
-    put(0, 0);
-    __syncthreads();
-    // 3. class sums, one thread per (member, colour) of the staged group
-    for (int grp = 0; grp < ngroups; ++grp) {
-        const int buf = grp & 1;
-        if (grp + 1 < ngroups) fetch(grp + 1);
-        const int dg = grp * PM, mc = min(PM, D - dg);
-        const int16_t* gl = lists + buf * lst_stage;
-        const int32_t* go = offs + buf * off_stage;
-        for (int e = tid; e < mc * k; e += NT) {
-            const int dm = e / k, l = e - dm * k;
-            const int beg = go[dm * (k + 1) + l], end = go[dm * (k + 1) + l + 1];
-            const int16_t* lv = gl + (size_t)dm * cs;
-            float* out = Gg + ((size_t)(dg + dm) * n + i0) * k + l;
-            // the contraction's values, loaded before the sums that hide their latency
-            float prev[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) prev[r] = (accumulate && r < rows) ? out[(size_t)r * k] : 0.0f;
-            float acc[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = 0.0f;
-            for (int q0 = beg & ~7; q0 < end; q0 += 8) {
-                const u32x4n w = *(const u32x4n*)(lv + q0);
-                const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
-                // all eight reads first (slots outside the class read the zero row), then
-                // the additions in list order
-                float v[8][R];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int q = q0 + u;
-                    const int j = (q >= beg && q < end) ? (int)((wv[u >> 1] >> (16 * (u & 1))) & 0xFFFFu) : n_pad;
-                    const float* vj = vals + j * R;
-                    if constexpr (R >= 4) {
-#pragma unroll
-                        for (int h = 0; h < R; h += 4) {
-                            const float4 x = *(const float4*)(vj + h);
-                            v[u][h] = x.x; v[u][h + 1] = x.y; v[u][h + 2] = x.z; v[u][h + 3] = x.w;
-                        }
-                    } else if constexpr (R == 2) {
-                        const float2 x = *(const float2*)vj;
-                        v[u][0] = x.x; v[u][1] = x.y;
-                    } else {
-                        v[u][0] = vj[0];
+                    for (int h = 0; h < 4; ++h) {
+                        const int m0 = 8 * w + 2 * h;
+                        const uint32_t valid = (m0 < D ? 0x8000u : 0u) | (m0 + 1 < D ? 0x80000000u : 0u);
+                        m2[u] += equal_halves_in(xs[h], ys[h], valid);
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] += v[u][r];
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (r < rows) out[(size_t)r * k] = accumulate ? prev[r] + sgn * acc[r] : sgn * acc[r];
+            for (int u = 0; u < 2; ++u)
+                if (j0 + u * NT < n) cnt[j0 + u * NT] = (uint32_t)m2[u];
         }
-        if (grp + 1 < ngroups) put(grp + 1, buf ^ 1);
+    }
+    __syncthreads();
+    // 2. table index of P_ij for every j; the nonzero entries go to the list
+    for (int base = 0, pass = 0; base < n; base += 4 * NT, ++pass) {
+        const int j0 = base + 4 * tid;
+        int vi[4];
+        bool nz[4];
+        if (j0 < n) {
+            uint32_t a4 = 0;
+            if (pass < kPsA8) {
+#pragma unroll
+                for (int u = 0; u < kPsA8; ++u)
+                    if (u == pass) a4 = a4pre[u];
+            } else {
+                a4 = gview((const uint32_t*)(arow + j0))[0];
+            }
+            const u32x4n c4 = *(const u32x4n*)(cnt + j0);
+            const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                const bool edge = ((a4 >> (8 * u)) & 0xFFu) != 0;
+                const bool excl = !edge && !diag && j == i;
+                vi[u] = excl ? zslot : (edge ? D + 1 + (int)cw[u] : (int)cw[u]);
+                nz[u] = j < n && tab[vi[u]] != 0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { vi[u] = zslot; nz[u] = false; }
+        }
+        unsigned long long bal[4];
+        int tot = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bal[u] = __ballot(nz[u]);
+            tot += __popcll(bal[u]);
+        }
+        int off = 0;
+        if (lane == 0 && tot > 0) off = atomicAdd(&nzc[0], tot);
+        off = __shfl(off, 0);
+        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (nz[u]) list[off + __popcll(bal[u] & below)] = (uint32_t)(j0 + u) | ((uint32_t)vi[u] << 16);
+            off += __popcll(bal[u]);
+        }
+    }
+    __syncthreads();
+    const int nnz = nzc[0];
+    // 3. members PM at a time; entry e = (list entry e / pm, member e % pm), advanced
+    // by NT per entry
+    __attribute__((address_space(1))) float* Gg = (__attribute__((address_space(1))) float*)d.G;
+    const double inv = ldexp(1.0, -sc);
+    for (int d0 = 0; d0 < D; d0 += PM) {
+        const int pm = min(PM, D - d0);
+        for (int e = tid; e < pm * k / 2; e += NT) ((u32x4n*)acc)[e] = u32x4n{0u, 0u, 0u, 0u};
+        if ((pm * k) & 1)
+            if (tid == 0) acc[pm * k - 1] = 0ull;
         __syncthreads();
+        const int total = nnz * pm;
+        const int sle = NT / pm, sdm = NT - sle * pm;
+        int le = tid / pm, dm = tid - le * pm;
+        // per entry: its colour, and member | table index << 16 (-1: none)
+        int col[B], dv[B];
+        auto fetch = [&](int e0) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                dv[u] = -1;
+                if (e0 + u * NT < total) {
+                    const uint32_t ent = list[le];
+                    col[u] = gview(cT)[(size_t)(ent & 0xFFFFu) * cTs + d0 + dm];
+                    dv[u] = dm | (int)((ent >> 16) << 16);
+                }
+                le += sle;
+                dm += sdm;
+                if (dm >= pm) { dm -= pm; ++le; }
+            }
+        };
+        fetch(tid);
+        for (int e0 = tid; e0 < total; e0 += B * NT) {
+            int ccol[B], cdv[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) { ccol[u] = col[u]; cdv[u] = dv[u]; }
+            if (e0 + B * NT < total) fetch(e0 + B * NT);
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (cdv[u] >= 0)
+                    atomicAdd(&acc[(cdv[u] & 0xFFFF) * k + ccol[u]], (unsigned long long)tab[cdv[u] >> 16]);
+        }
+        __syncthreads();
+        for (int e0 = tid; e0 < pm * k; e0 += 4 * NT) {
+            float prev[4];
+            size_t off[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * NT;
+                prev[u] = 0.0f;
+                off[u] = 0;
+                if (e < pm * k) {
+                    const int dd = e / k, l = e - dd * k;
+                    off[u] = ((size_t)(d0 + dd) * n + i) * k + l;
+                    if (accumulate) prev[u] = Gg[off[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * NT;
+                if (e < pm * k) Gg[off[u]] = prev[u] + sgn * (float)((double)(long long)acc[e] * inv);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per-iteration penalty choice of graphs on the sparse rows (ps_mode 2): row i has at
+// most sum_d |class of c_d(i)| nonzeros in P, and over all rows that is
+// sum_d sum_l #V_{d,l}^2.  While its average over the rows stays within n / 4 the
+// iteration takes the sparse rows; beyond (the population collapsing into a few large
+// classes) the dense pass, whose cost does not depend on the classes.  Partitioning
+// keeps the sparse rows: its operand over D - Mt has nonzeros wherever Mt < D, so its
+// rows are dense anyway and the sparse kernel is the faster on them.  One block per graph.
+__global__ __launch_bounds__(64) void k_decide(const GraphDev* __restrict__ gd, int G) {
+    const GraphDev& d = gd[blockIdx.x];
+    GraphState* st = d.st;
+    if (!d.psparse) return;
+    long long w = 0;
+    for (int m = threadIdx.x; m < d.D; m += 64) w += gview(d.sq)[m];
+    for (int sh = 32; sh >= 1; sh >>= 1) w += __shfl_xor(w, sh);
+    if (threadIdx.x == 0) {
+        const bool dense = d.ps_mode == 2 && !prob_partition(d.problem) && w > (long long)d.n * d.n / 4;
+        st->pdense = dense ? 1 : 0;
     }
 }
 
@@ -566,7 +634,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
-    const bool want_sp2 = prec_split(d.precision) && (!gate || !d.pgather);
+    const bool want_sp2 = prec_split(d.precision) && (!gate || !d.psparse || st->pdense);
     const int cgs = d.n_pad / 16;
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
     const int row = (int)(item / cgs);
@@ -822,7 +890,7 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
     const float tf = (float)st->t;
     const bool pen = (d.lambda * tf != 0.0f) || (d.mu * tf != 0.0f);
     if (!pen && !(flags & (kFlagForcePen | kFlagLoss | kFlagMtOut))) return;
-    if ((flags & kFlagGate) && d.pgather) return;
+    if ((flags & kFlagGate) && d.psparse && !st->pdense) return;
     if (d.mt_ts == 32)
         mtilde_tile<2>(d, st, b, flags, mt_out, ci, cj, red);
     else
@@ -1240,9 +1308,9 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
     return hipSuccess;
 }
 
-size_t prep_lds(int kmax, int nmax, int gather) {
+size_t prep_lds(int kmax, int nmax, int lists) {
     size_t b = sizeof(int) * (size_t)kmax;
-    if (gather) b += sizeof(int) * 4 * (size_t)kmax + sizeof(int16_t) * (size_t)nmax;
+    if (lists) b += sizeof(int) * 5 * (size_t)kmax + sizeof(int16_t) * (size_t)nmax;
     return (b + 15) / 16 * 16;
 }
 
@@ -1254,11 +1322,9 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int
     return hipSuccess;
 }
 
-hipError_t penalty_gather_prepare() {
-    const void* fns[] = {(const void*)k_pen_gather<1, 512>,  (const void*)k_pen_gather<2, 512>,
-                         (const void*)k_pen_gather<4, 512>,  (const void*)k_pen_gather<8, 512>,
-                         (const void*)k_pen_gather<1, 1024>, (const void*)k_pen_gather<2, 1024>,
-                         (const void*)k_pen_gather<4, 1024>, (const void*)k_pen_gather<8, 1024>};
+hipError_t penalty_sparse_prepare() {
+    const void* fns[] = {(const void*)k_pen_sparse<256>, (const void*)k_pen_sparse<512>,
+                         (const void*)k_pen_sparse<1024>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -1267,39 +1333,33 @@ hipError_t penalty_gather_prepare() {
     return hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
 
-size_t penalty_gather_lds(int R, int PM, int kmax, int dmax, int nmax) {
-    const size_t n_pad = (size_t)round_up(nmax, kPadN), cs = (size_t)round_up(nmax, 64);
-    const size_t vrows = n_pad + (R >= 4 ? 1 : 4 / R);
-    const size_t b = 4 * (size_t)R * vrows + 4 * (size_t)((2 * (dmax + 1) + 1 + 3) & ~3) + 2 * 2 * (size_t)PM * cs +
-                     4 * 2 * pg_off_words(PM, kmax);
+size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
+    const size_t n_pad = (size_t)round_up(nmax, kPadN);
+    const size_t acc = 8 * (size_t)PM * (size_t)kmax;
+    const size_t work = acc > 4 * n_pad ? acc : 4 * n_pad;
+    const size_t b = 8 * ps_tab_words(dmax) + 2 * 4 * ps_int_words(dmax) + 16 + 2 * (size_t)round_up(dmax, 8) +
+                     4 * n_pad + work;
     return (b + 15) / 16 * 16;
 }
 
-bool penalty_gather_group_fits(int PM, int kmax, int nmax) {
-    const long long cs = round_up(nmax, 64);
-    return (long long)PM * cs / 8 <= (long long)kPgMaxL * 512 &&
-           (long long)PM * (kmax + 1) <= (long long)kPgMaxO * 512;
+hipError_t launch_decide(const GraphDev* gd, int G, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(G), dim3(64), 0, s, gd, G);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
 }
 
-hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int PM, size_t lds, int honor_stop,
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
                                  int accumulate, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    if (PM < 1 || lds > 160 * 1024) return hipErrorInvalidValue;
-    const bool wide = lds > 80 * 1024;     // one block per CU: 1024 threads
-#define TCOL_PG(RR)                                                                                     \
-    if (wide)                                                                                           \
-        k_pen_gather<RR, 1024><<<blocks, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate);    \
-    else                                                                                                \
-        k_pen_gather<RR, 512><<<blocks, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate);
-    switch (R) {
-        case 1: TCOL_PG(1) break;
-        case 2: TCOL_PG(2) break;
-        case 4: TCOL_PG(4) break;
-        case 8: TCOL_PG(8) break;
+    if (PM < 8 || (PM & 7) || lds > 160 * 1024) return hipErrorInvalidValue;
+    switch (threads) {
+        case 256: k_pen_sparse<256><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
+        case 512: k_pen_sparse<512><<<blocks, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
+        case 1024: k_pen_sparse<1024><<<blocks, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
         default: return hipErrorInvalidValue;
     }
-#undef TCOL_PG
-    return hipGetLastError();
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
 }
 
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,

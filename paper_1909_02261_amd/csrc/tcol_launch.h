@@ -11,19 +11,20 @@ hipError_t launch_init_weights(float* W, long long count, unsigned long long see
 hipError_t launch_pack_graph(const uint8_t* A, int n, int n_pad, int prec, uint8_t* A8, void* Aop, int* bad,
                              unsigned long long* ones, hipStream_t s);
 hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_stop, hipStream_t s);
-// class sizes and vertex-major colours; with gather != 0 also the class lists of graphs on the
-// class-gather penalty (dynamic LDS from prep_lds)
-size_t prep_lds(int kmax, int nmax, int gather);
+// class sizes and vertex-major colours; with lists != 0 also the class lists of graphs on the
+// sparse penalty (dynamic LDS from prep_lds)
+size_t prep_lds(int kmax, int nmax, int lists);
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s);
-hipError_t penalty_gather_prepare();
-// class-gather penalty rows: blocks of R rows (R in {1, 2, 4, 8}), class lists staged PM members at a time
-size_t penalty_gather_lds(int R, int PM, int kmax, int dmax, int nmax);
-// a group of PM members fits the kernel's per-thread staging registers
-bool penalty_gather_group_fits(int PM, int kmax, int nmax);
+hipError_t penalty_sparse_prepare();
+// sparse penalty rows: one row per block of `threads` (256, 512 or 1024), members PM at a
+// time (a multiple of 8)
+size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax);
 // accumulate 0: rows written to G before the contraction (epilogue path); 1: added to the
 // contraction's G (fast path)
-hipError_t launch_penalty_gather(const GraphDev* gd, int G, int blocks, int R, int PM, size_t lds, int honor_stop,
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
                                  int accumulate, hipStream_t s);
+// the iteration's penalty choice of graphs on the sparse rows (after launch_prep)
+hipError_t launch_decide(const GraphDev* gd, int G, hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
@@ -45,7 +46,7 @@ hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long
 // MFMA contraction G = A.S (+ P.S) with the conflict gather.
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
 //   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
-//           bit 3 = dense penalty operand even for graphs on the class-gather penalty
+//           bit 3 = dense penalty operand even for graphs on the sparse penalty
 struct GemmShape {
     int prec, bm, ntw, mode;
 };

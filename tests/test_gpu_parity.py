@@ -150,8 +150,8 @@ def run_resynced(case, steps, tol, check_every=1, t0=0, W=None, **opts):
     return worst
 
 
-PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_gather": dict(fused=1, penalty=2),
-         "epi_dense": dict(fused=2, penalty=1), "epi_gather": dict(fused=2, penalty=2)}
+PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_sparse": dict(fused=1, penalty=2),
+         "epi_dense": dict(fused=2, penalty=1), "epi_sparse": dict(fused=2, penalty=2)}
 
 
 @pytest.mark.parametrize("path", list(PATHS))
@@ -167,15 +167,16 @@ def test_fused_large_k_resynced(path, prec):
     ECP so every loss term is active, a ragged n and several tiles."""
     case = GraphCase(f"ecp_n600_k120_D8_p{prec}", ECP, 600, 120, 8, prec, "gnp", 0.5, graph_seed=31, rho=10.0,
                      lam=2e-2, mu=5e-3, nu=0.05)
-    tol = TOL if (prec == FP32 or path.endswith("gather")) else 1e-2
+    tol = TOL if (prec == FP32 or path.endswith("sparse")) else 1e-2
     worst = run_resynced(case, 8, tol, t0=3, **PATHS[path])
     print(f"{case.name} {path}: worst W error vs FP64 {worst:.2e}")
 
 
 @pytest.mark.parametrize("path", [p for p in PATHS if p != "plain"])
 def test_degenerate_population(path):
-    """Every vertex in one colour in every member: Mt is all D, the penalty operand is dense
-    and the class-gather kernel sees one class of n vertices per member."""
+    """Every vertex in one colour in every member: Mt is all D, the penalty operand is dense,
+    the sparse kernel lists every vertex of a row and counts by comparison, and the
+    per-iteration choice takes the dense pass."""
     n, k, D = 300, 100, 8
     case = GraphCase("degenerate", KCOL, n, k, D, FP32, "gnp", 0.5, graph_seed=33, lam=1e-2, mu=1e-3)
     W = case.weights()
@@ -189,7 +190,7 @@ def test_degenerate_population(path):
 def test_small_resynced_low_precision(prec, path):
     case = GraphCase("kcol90", KCOL, 90, 9, 6, prec, "gnp", 0.5, graph_seed=12, rho=10.0, lam=1e-2, mu=3e-3)
     # bf16 penalty operand: errors against FP64 are reported; the bound only catches wrong arithmetic
-    worst = run_resynced(case, 30, TOL if path.endswith("gather") else 1e-2, **PATHS[path])
+    worst = run_resynced(case, 30, TOL if path.endswith("sparse") else 1e-2, **PATHS[path])
     print(f"prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
@@ -403,14 +404,14 @@ def test_c5_full_size(prec):
     s.close()
 
 
-@pytest.mark.parametrize("penalty", ["dense", "gather"])
+@pytest.mark.parametrize("penalty", ["dense", "sparse"])
 def test_c5_full_size_step(penalty):
     """One fast-path step at the benchmark's size (n = 4000, k = 280, D = 32, fp4 A.S) with the
-    penalty active, against the oracle's iteration from the same weights: the class gather at
-    this size takes its 1024-thread, four-row blocks; the dense pass rounds its operand to bf16."""
+    penalty active, against the oracle's iteration from the same weights: the sparse rows at
+    this size take two groups of 16 members per row; the dense pass rounds its operand to bf16."""
     case = tcolgen.case_c5(FP4)
     case.stop_on_legal = 0
-    s, (A,) = make_solver([case], fused=1, penalty={"dense": 1, "gather": 2}[penalty])
+    s, (A,) = make_solver([case], fused=1, penalty={"dense": 1, "sparse": 2}[penalty])
     t = 40
     s.set_t(t)
     W0 = host(s.W[0])
@@ -419,7 +420,7 @@ def test_c5_full_size_step(penalty):
     assert done == 1
     e = normwise(host(s.W[0]), ref.W)
     print(f"C5 {penalty}: W error vs FP64 {e:.2e}")
-    assert e <= (TOL if penalty == "gather" else 1e-2)
+    assert e <= (TOL if penalty == "sparse" else 1e-2)
     c, fc, _ = s.conflicts(0)
     c_ref = oracle.colors(host(s.W[0]))
     assert np.array_equal(host(c), c_ref)
@@ -453,3 +454,30 @@ def test_penalty_pass_every_tile_shape(prec):
     print(f"precision {prec}: gradS error per shape {worst}")
     # bf16 penalty operand: relative rounding 2^-9 per entry
     assert max(worst.values()) <= 1e-2, worst
+
+
+@pytest.mark.parametrize("prec", [FP32, FP8, FP4])
+def test_auto_penalty_small_classes(prec):
+    """Automatic penalty choice on rows that stay sparse (n = 600, k = 60, D = 4: about
+    40 class-mates per row against n / 4 = 150), so every iteration takes the sparse
+    rows, which are FP32 in every operand mode."""
+    case = GraphCase("auto_sparse", KCOL, 600, 60, 4, prec, "gnp", 0.3, graph_seed=61, rho=10.0,
+                     lam=1e-2, mu=3e-3, stop_on_legal=0)
+    worst = run_resynced(case, 8, TOL, t0=2, fused=1, penalty=0)
+    print(f"auto penalty, prec {prec}: worst W error vs FP64 {worst:.2e}")
+
+
+@pytest.mark.parametrize("path", ["fast_auto", "epi_auto"])
+@pytest.mark.parametrize("prec", [FP32, FP8])
+def test_auto_penalty_switches(prec, path):
+    """Automatic penalty choice along a trajectory whose smoothing (rho = 100 every second
+    iteration) drives the population in and out of large classes, so iterations take the
+    dense pass and the sparse rows in turn; FP8 also checks that the bf16 copy of S the
+    dense pass reads is written in exactly the iterations that need it."""
+    case = GraphCase("auto_switch", KCOL, 400, 40, 4, prec, "gnp", 0.5, graph_seed=62, rho=100.0,
+                     nb_iter=2, lam=1e-2, mu=3e-3, stop_on_legal=0)
+    W = case.weights()
+    W[0, :200, 0] += 0.05       # member 0 starts with a class of 200 vertices
+    fused = 1 if path == "fast_auto" else 2
+    worst = run_resynced(case, 12, TOL if prec == FP32 else 1e-2, W=W, fused=fused, penalty=0)
+    print(f"auto switching {path}, prec {prec}: worst W error vs FP64 {worst:.2e}")

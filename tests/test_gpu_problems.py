@@ -21,8 +21,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 PROBLEMS = {"kpart": KPART, "bkpart": BKPART, "mscp": MSCP}
-PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_gather": dict(fused=1, penalty=2),
-         "epi_dense": dict(fused=2, penalty=1), "epi_gather": dict(fused=2, penalty=2)}
+PATHS = {"plain": dict(fused=0), "fast_dense": dict(fused=1, penalty=1), "fast_sparse": dict(fused=1, penalty=2),
+         "epi_dense": dict(fused=2, penalty=1), "epi_sparse": dict(fused=2, penalty=2)}
 
 
 def host(t):
@@ -121,7 +121,7 @@ def test_resynced_steps_every_path(name, path):
 @pytest.mark.parametrize("name", list(PROBLEMS))
 def test_resynced_low_precision(name, prec):
     case = case_for(PROBLEMS[name], prec, stop_on_legal=0)
-    worst = run_resynced(case, 5, TOL, fused=1, penalty=2)      # FP32 class-gather penalty
+    worst = run_resynced(case, 5, TOL, fused=1, penalty=2)      # FP32 sparse penalty rows
     print(f"{case.name}: worst W error {worst:.2e}")
     worst = run_resynced(case, 5, 1e-2, fused=1, penalty=1)     # bf16 dense penalty operand
     print(f"{case.name} dense: worst W error {worst:.2e}")
@@ -159,7 +159,7 @@ def test_partition_stop_on_zero_cut():
 
 
 @pytest.mark.parametrize("gamma", [0.5, 0.9])
-@pytest.mark.parametrize("path", ["plain", "fast_dense", "fast_gather", "epi_dense"])
+@pytest.mark.parametrize("path", ["plain", "fast_dense", "fast_sparse", "epi_dense"])
 @pytest.mark.parametrize("problem", [KCOL, BKPART])
 def test_momentum_trajectory(problem, path, gamma):
     """Heavy-ball steps from the same weights: the GPU trajectory (velocity kept on the device)
