@@ -79,7 +79,7 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     sz[B_CLSV] = sizeof(int16_t) * (size_t)p.D * round_up(p.n, 64);
     sz[B_CLSOFF] = sizeof(int32_t) * (size_t)p.D * (p.k + 1);
-    sz[B_CINFO] = 8 * (size_t)round_up(p.D, 8) * p.n;
+    sz[B_CINFO] = 8 * (size_t)p.D * round_up(p.n, 64);
     sz[B_SQ] = sizeof(long long) * (size_t)p.D;
     sz[B_VEL] = p.momentum != 0.0f ? sizeof(float) * dnk : 0;
     size_t o = 0;

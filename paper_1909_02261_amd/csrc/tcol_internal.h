@@ -102,7 +102,7 @@ struct GraphDev {
                               // the dense operand pass of the contraction
     int16_t* cls_v;           // [D][cs] vertices of each member grouped by colour
     int32_t* cls_off;         // [D][k + 1] start of colour l's vertices in cls_v (last entry n)
-    int2* cinfo;              // [n][cTs] start in cls_v and size of the class of vertex i in member d
+    int2* cinfo;              // [D][cs] start in cls_v and size of the class of vertex i in member d
     long long* sq;            // [D] sum over colours of the squared class sizes of each member
     int ps_mode;              // sparse penalty: 1 every iteration, 2 when the classes are small
     // flattened work offsets (prefix sums over graphs)

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
             const int x = gview(c)[i];
             const int pos = atomicAdd(&cur[x], 1);
             lst[pos] = (int16_t)i;
-            cinfo[(size_t)i * cTs + m] = make_int2(offl[x], cnt[x]);
+            cinfo[(size_t)m * d.cs + i] = make_int2(offl[x], cnt[x]);
         }
     }
     __syncthreads();
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
         ci[dm] = gview(cT)[(size_t)i * cTs + dm];
         if (dm < D) {
             // (start, size) as one 8-byte load: start in the low word
-            const unsigned long long cl = gview((const unsigned long long*)d.cinfo)[(size_t)i * cTs + dm];
+            const unsigned long long cl = gview((const unsigned long long*)d.cinfo)[(size_t)dm * d.cs + i];
             cbeg[dm] = (int)(uint32_t)cl;
             pre[dm + 1] = (int)(uint32_t)(cl >> 32);
         }
