@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 // [n_pad] u32 overlaid by the group's accumulators [PM][k] i64.
 __host__ __device__ inline size_t ps_tab_words(int D) { return ((size_t)2 * (D + 1) + 1 + 1) & ~(size_t)1; }
 __host__ __device__ inline size_t ps_int_words(int D) { return ((size_t)D + 1 + 3) & ~(size_t)3; }
-constexpr int kPsBatch = 8;     // entries per thread per batch in steps 1 and 3
+constexpr int kPsBatch = 4;     // entries per thread per batch in steps 1 and 3 (48 registers: eight waves per SIMD)
 constexpr int kPsA8 = 2;        // adjacency words per thread loaded at the start
 
 template <int NT>
