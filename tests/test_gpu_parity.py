@@ -481,3 +481,32 @@ def test_auto_penalty_switches(prec, path):
     fused = 1 if path == "fast_auto" else 2
     worst = run_resynced(case, 12, TOL if prec == FP32 else 1e-2, W=W, fused=fused, penalty=0)
     print(f"auto switching {path}, prec {prec}: worst W error vs FP64 {worst:.2e}")
+
+
+def test_c5b_batch_step_every_graph():
+    """The uneven batch (16 graphs, n from 250 to 2000, p cycling .1/.5/.9, each with its
+    greedy colour count as k, D = 16) in one context: one launch sequence steps all of them,
+    the penalty taken per graph and iteration (sparse rows or the bf16 dense pass).  One
+    step from t = 10 is compared with the oracle graph by graph, and the colours and
+    conflict counts after it are exact."""
+    cases = tcolgen.cases_c5b(BF16)
+    for c in cases:
+        c.stop_on_legal = 0
+    s, As = make_solver(cases)
+    t0 = 10
+    s.set_t(t0)
+    W0 = [host(w).copy() for w in s.W]
+    done, _ = s.step(1)
+    assert done == 1
+    worst = 0.0
+    for g, c in enumerate(cases):
+        ref = oracle.iteration(orc_params(c.params()), t0, As[g], W0[g], want_grads=False)
+        e = normwise(host(s.W[g]), ref.W)
+        worst = max(worst, e)
+        assert e <= 1e-2, (c.name, e)
+        col, fc, _ = s.conflicts(g)
+        c_ref = oracle.colors(host(s.W[g]))
+        assert np.array_equal(host(col), c_ref)
+        assert np.array_equal(host(fc), oracle.fcolor(As[g], c_ref))
+    print(f"C5b: worst W error vs FP64 over 16 graphs {worst:.2e}")
+    s.close()
