@@ -123,8 +123,9 @@ typedef struct {
                                bf16 in the fp4 / fp8 / bf16 modes); 2 = sparse rows in every
                                iteration: with one-hot S_d, (P.S_d)[i, l] is the sum of P_ij over
                                the vertices of colour l in member d, and P_ij = 0 unless j shares
-                               i's colour in some member, so each row adds its nonzeros (exact
-                               64-bit fixed-point sums of the FP32 values, rounded once);
+                               i's colour in some member, so each row adds its nonzeros (64-bit
+                               fixed-point sums of the FP32 values, exact for the paper's
+                               parameters up to n = 4000, rounded once to FP32);
                                0 = choose (default): the sparse rows in the iterations where the
                                rows average at most n / 4 class-mates and the dense pass in the
                                others (decided on the device each iteration), the dense pass

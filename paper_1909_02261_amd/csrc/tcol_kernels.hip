@@ -325,10 +325,12 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 // where k_decide found its classes small; otherwise the contraction's dense pass.
 // Steps 1 and 3 issue the loads of their next batch before the atomics of the current
 // one.  The sums are taken in 64-bit fixed point: every table value times 2^sc, with sc
-// chosen so that n max|P| stays below 2^62, is an integer (for any table whose values
-// span less than 2^26) and integer sums do not depend on the order of the additions,
-// so the LDS atomics give the same bits on every run.  The result is the exact sum of
-// the FP32 values P_ij rounded once to FP32.
+// chosen so that n max|P| stays below 2^62, is an integer whenever the table's binary
+// exponents span at most 38 - bits(n) (every setting of the paper's parameter grid up
+// to n = 4000; beyond, each term is rounded at 2^-sc, at most 2^-30 of max|P| over a
+// row), and integer sums do not depend on the order of the additions, so the LDS
+// atomics give the same bits on every run.  The result is the sum of the FP32 values
+// P_ij, exact in those cases, rounded once to FP32.
 // Dynamic LDS (penalty_sparse_lds): table [2 (D + 1) + 1] i64 (the last entry 0, for
 // an excluded diagonal), class starts and the prefix of the class sizes [D + 1] i32
 // each, the list length, row i's colours [cTs] i16, list [n_pad] u32, then counts
