@@ -251,6 +251,15 @@ def main():
                "frac": f_as / as_s / PEAK[prec], "ms_per_launch": ph["gemm_as_only"]}
     print(f"[bench] phases ms {json.dumps({k: round(v, 4) for k, v in ph.items()})}", file=sys.stderr, flush=True)
     s.close()
+    # the same fractions against this device's measured MFMA throughput (register-operand
+    # chains on every CU, no memory traffic), beside the published peaks above
+    pm_as = max(pk.mfma_peak(PREC[prec]) for _ in range(3)) * 1e12
+    pm_pen = max(pk.mfma_peak(tcolgen.BF16) for _ in range(3)) * 1e12 if prec in ("fp8", "fp4") else pm_as
+    mixed_m = (f_as + f_pen) / (f_as / pm_as + f_pen / pm_pen)
+    measured_peak = {"unit": "TFLOP/s", "operand": pm_as / 1e12, "penalty_operand": pm_pen / 1e12,
+                     "k_gemm_peak": mixed_m / 1e12, "k_gemm_frac": achieved / mixed_m,
+                     "as_only_frac": f_as / as_s / pm_as, "method": "tcol_mfma_peak"}
+    print(f"[bench] measured MFMA peak {json.dumps(measured_peak)}", file=sys.stderr, flush=True)
     if args.calib_copy_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the others
         nb = args.calib_copy_mib << 20
@@ -288,6 +297,7 @@ def main():
         "config": config,
         "roofline": roof,
         "roofline_as_only": roof_as,
+        "mfma_peak_measured": measured_peak,
         "phases_ms": ph,
         "cpu_baseline": cpu,
     }

@@ -236,6 +236,17 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
 #define TCOL_NPHASES 9
 tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *ms);
 
+/* Measurement utility, no context: the achievable MFMA throughput of the current
+ * device for one operand type (precision as in tcol_graph_params: the fp4 / fp8
+ * 16x16x128 scaled form, bf16 16x16x32 or fp32 16x16x4), from `iters` rounds of
+ * eight dependent-chain MFMAs per wave on register operands over every CU
+ * (32 waves per CU, no memory traffic), timed with HIP events on a private
+ * stream after a short warm-up.  Writes TFLOP/s (dense, 2 m n k per
+ * instruction) to *tflops (host).  Synchronises its stream; allocates no
+ * device memory.  Errors: TCOL_EINVAL (NULL, iters < 1, unknown precision),
+ * TCOL_EHIP. */
+tcol_status tcol_mfma_peak(int32_t precision, int32_t iters, double *tflops);
+
 /* Release the context (and the workspace it allocated).  NULL is ignored. */
 void tcol_destroy(tcol_ctx *ctx);
 

@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, BKPART, ECP, FP4, FP8, FP32, KCOL, KPART, MSCP, TcolError
 
-__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "KCOL", "ECP", "KPART", "BKPART", "MSCP",
+__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "mfma_peak", "KCOL", "ECP", "KPART", "BKPART", "MSCP",
            "FP32", "BF16", "FP8", "FP4", "TcolError"]
 
 
@@ -185,6 +185,15 @@ class Solver:
         bm, ntw = ctypes.c_int32(0), ctypes.c_int32(0)
         _lib.check(self._lib.tcol_autotune(self._ctx, ctypes.byref(bm), ctypes.byref(ntw)), "tcol_autotune")
         return bm.value, ntw.value
+
+
+def mfma_peak(precision: int, iters: int = 4000) -> float:
+    """Achievable dense MFMA TFLOP/s of the current device for one operand type
+    (tcol_mfma_peak: register operands, every CU, no memory traffic)."""
+    lib = _lib.load()
+    out = ctypes.c_double(0.0)
+    _lib.check(lib.tcol_mfma_peak(int(precision), int(iters), ctypes.byref(out)), "tcol_mfma_peak")
+    return out.value
 
 
 def init_weights(W, seed: int, sigma0: float = 0.01, stream=None) -> None:

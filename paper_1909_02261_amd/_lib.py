@@ -48,7 +48,7 @@ class TcolError(RuntimeError):
 EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_options",
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
            "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
-           "tcol_init_weights", "tcol_descent"]
+           "tcol_init_weights", "tcol_descent", "tcol_mfma_peak"]
 NPHASES = 9
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only"]
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_reset.argtypes = [P]
     lib.tcol_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tcol_profile.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_float)]
+    lib.tcol_mfma_peak.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double)]
     lib.tcol_init_weights.argtypes = [P, i64, ctypes.c_uint64, ctypes.c_double, P]
     lib.tcol_descent.argtypes = [P, ctypes.POINTER(GraphParams), ctypes.POINTER(DescentOptions),
                                  ctypes.POINTER(DescentResult), P, P]
