@@ -510,3 +510,14 @@ def test_c5b_batch_step_every_graph():
         assert np.array_equal(host(fc), oracle.fcolor(As[g], c_ref))
     print(f"C5b: worst W error vs FP64 over 16 graphs {worst:.2e}")
     s.close()
+
+
+@pytest.mark.parametrize("prec,published", [(FP4, 10100.0), (FP8, 5000.0), (BF16, 2500.0), (FP32, 157.3)],
+                         ids=["fp4", "fp8", "bf16", "fp32"])
+def test_mfma_peak_measurement_is_plausible(prec, published):
+    """The MFMA throughput measurement runs and lands between a quarter of and slightly
+    above the published dense peak of its operand type (TFLOP/s)."""
+    import paper_1909_02261_amd as pk
+    v = max(pk.mfma_peak(prec, 1000) for _ in range(2))
+    print(f"measured {v:.1f} TFLOP/s against {published}")
+    assert 0.25 * published < v < 1.1 * published

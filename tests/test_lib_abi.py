@@ -128,3 +128,12 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
     finally:
         _lib._lib = old
+
+
+def test_mfma_peak_rejects_bad_arguments_without_gpu(lib):
+    """tcol_mfma_peak validates its arguments before any HIP call."""
+    out = ctypes.c_double(0.0)
+    assert lib.tcol_mfma_peak(3, 10, None) == -1       # TCOL_EINVAL
+    assert lib.tcol_mfma_peak(3, 0, ctypes.byref(out)) == -1
+    assert lib.tcol_mfma_peak(4, 10, ctypes.byref(out)) == -1
+    assert lib.tcol_mfma_peak(-1, 10, ctypes.byref(out)) == -1
