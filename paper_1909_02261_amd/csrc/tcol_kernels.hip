@@ -372,8 +372,16 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     // contraction negates along with A.S
     const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;
 
-    // 0. the adjacency bytes of step 2's first passes, the row's colours and classes
-    // (one round of loads); counts cleared; the table's largest magnitude
+    // 0. the adjacency bytes of step 2's first passes, the row's colours and classes,
+    // the value table (one round of loads); counts cleared; the table's largest magnitude
+    constexpr int TV = (2 * (kMaxD + 1) + 1 + NT - 1) / NT;   // table entries per thread
+    float tv[TV];
+#pragma unroll
+    for (int u = 0; u < TV; ++u) {
+        const int vi = tid + u * NT;
+        tv[u] = 0.0f;
+        if (vi < T - 1) tv[u] = vi <= D ? -(tf * gview(d.lut_bon)[vi]) : tf * gview(d.lut_pen)[vi - D - 1];
+    }
     const uint8_t* __restrict__ arow = d.A8 + (size_t)i * n_pad;
     uint32_t a4pre[kPsA8];
 #pragma unroll
@@ -393,11 +401,11 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     for (int e = tid; e < n_pad / 4; e += NT) ((u32x4n*)cnt)[e] = u32x4n{0u, 0u, 0u, 0u};
     if (tid == 0) { nzc[0] = 0; nzc[1] = 0; pre[0] = 0; }
     __syncthreads();
-    for (int vi = tid; vi < T - 1; vi += NT) {
-        const float v = vi <= D ? tf * d.lut_bon[vi] : tf * d.lut_pen[vi - D - 1];
-        if (v != 0.0f) {
+#pragma unroll
+    for (int u = 0; u < TV; ++u) {
+        if (tv[u] != 0.0f) {
             int ex;
-            frexpf(v, &ex);
+            frexpf(tv[u], &ex);
             // exponents are compared as ex + 256 > 0 (the counter starts at 0 = none)
             atomicMax(&nzc[1], ex + 256);
         }
@@ -421,10 +429,10 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     // fixed-point scale: |P_ij| < 2^E1 and n < 2^E2, so sums stay below 2^(E1 + E2) <= 2^62
     const int emax = nzc[1];
     const int sc = 62 - ((emax > 0 ? emax - 256 : 0) + (32 - __builtin_clz((unsigned)n)));
-    for (int vi = tid; vi < T; vi += NT) {
-        float v = 0.0f;
-        if (vi < T - 1) v = vi <= D ? -(tf * d.lut_bon[vi]) : tf * d.lut_pen[vi - D - 1];
-        tab[vi] = (long long)rint(ldexp((double)v, sc));
+#pragma unroll
+    for (int u = 0; u < TV; ++u) {
+        const int vi = tid + u * NT;
+        if (vi < T) tab[vi] = (long long)rint(ldexp((double)tv[u], sc));
     }
     // 1. Mt_ij
     const int W1 = pre[D];
