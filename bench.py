@@ -153,12 +153,70 @@ def run_descent(args, torch, pk):
     print(json.dumps(out))
 
 
+def run_batch(args, torch, pk):
+    """The uneven batch: 16 graphs (n from 250 to 2000, p cycling .1/.5/.9, k their greedy
+    colour counts, D = 16) stepped by one launch sequence; value = sum_g D_g steps / s."""
+    prec = args.precision or "bf16"
+    cases = tcolgen.cases_c5b(PREC[prec])
+    for c in cases:
+        c.stop_on_legal = 0
+    print(f"[bench] batch of {len(cases)} graphs, precision {prec}: generating inputs", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    graphs = [(torch.from_numpy(c.adjacency()).to(dev), torch.from_numpy(c.weights()).to(dev)) for c in cases]
+    s = pk.Solver(graphs, [pk.Params.from_dict(c.params()) for c in cases])
+    s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
+                  tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
+                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
+    opts = s.options()
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    done, _ = s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert done == args.steps
+    dsum = sum(c.D for c in cases)
+    ph = s.profile(args.profile_steps, as_only=True)
+    t_now = s.get_t()
+    f_as = f_pen = 0.0
+    for c in cases:
+        a, b = gemm_flops(c, t_now)
+        f_as += a
+        f_pen += b
+    if opts["penalty"] == 2:
+        f_pen = 0.0
+    achieved = (f_as + f_pen) / (ph["gemm"] / 1e3)
+    peak = mixed_peak(prec, f_as, f_pen)
+    s.close()
+    out = {
+        "metric": "population-iterations/s (D*steps/s)", "value": dsum * args.steps / (ms / 1e3),
+        "unit": "population-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic (seeded Philox G(n,p) graphs and N(0, 0.01^2) weights)",
+        "config": {"workload": "kcol_batch16_gnp_uneven", "graphs": len(cases), "n": [c.n for c in cases],
+                   "k": [c.k for c in cases], "D": cases[0].D, "precision": prec, "path": args.path,
+                   "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
+                   "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]]},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_gemm over the 16 graphs (A.S pass + penalty pass + fitness gather)",
+                     "flops_per_launch": f_as + f_pen, "ms_per_launch": ph["gemm"]},
+        "phases_ms": ph,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5", "c5b"],
+                    help="c5b: the batch of 16 uneven graphs in one context")
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
     ap.add_argument("--penalty", default="auto", choices=["auto", "dense", "sparse"],
@@ -191,6 +249,9 @@ def main():
 
     if args.descent:
         run_descent(args, torch, pk)
+        return
+    if args.workload == "c5b":
+        run_batch(args, torch, pk)
         return
 
     prec = args.precision or {"c1": "fp32", "c2": "fp32", "c3": "fp4", "c4": "bf16", "c5": "fp4"}[args.workload]

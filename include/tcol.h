@@ -106,11 +106,11 @@ typedef struct {
     int32_t fused;          /* step schedule: 0 = plain path (argmax, dense penalty operand,
                                contraction, update as separate kernels every iteration);
                                1 = fast path (default): the update kernel also colours the
-                               updated rows, no separate argmax pass (k <= 288, else the plain
+                               updated rows, no separate argmax pass (k <= 576, else the plain
                                order); the penalty term as `penalty` selects;
                                2 = epilogue path: the contraction kernel itself applies softmax,
                                gradient, update and the next argmax, into a second weight
-                               buffer (k <= 288) */
+                               buffer (k <= 576) */
     int32_t use_graph;      /* 1: replay each step from a captured hipGraph (default) */
     int32_t unroll;         /* steps per captured graph (1..64, default 8) */
     int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */

@@ -1406,7 +1406,7 @@ hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_st
 
 int update_rows_kpl(int kmax) {
     const int need = (kmax + 15) / 16;
-    for (int kpl : {2, 4, 6, 8, 12, 18})
+    for (int kpl : {2, 4, 6, 8, 12, 18, 24, 36})
         if (kpl >= need) return kpl;
     return 0;
 }
@@ -1434,6 +1434,8 @@ hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kma
         case 8: TCOL_UR(8) break;
         case 12: TCOL_UR(12) break;
         case 18: TCOL_UR(18) break;
+        case 24: TCOL_UR(24) break;
+        case 36: TCOL_UR(36) break;
         default: return hipErrorInvalidValue;
     }
 #undef TCOL_UR

@@ -32,7 +32,7 @@ hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_s
 hipError_t launch_fitness(const GraphDev* gd, int G, int honor_stop, int flags, int gsel, hipStream_t s);
 hipError_t launch_update(const GraphDev* gd, int G, int total_rows, int honor_stop, int mode, int gsel,
                          float* gS_out, float* gW_out, hipStream_t s);
-// register-resident row update for k <= 288 (update_rows_kpl(kmax) != 0); mode 0 also colours the new rows
+// register-resident row update for k <= 576 (update_rows_kpl(kmax) != 0); mode 0 also colours the new rows
 int update_rows_kpl(int kmax);
 // var: bit 0 some graph has an added fitness term, bit 1 some graph takes heavy-ball steps
 hipError_t launch_update_rows(const GraphDev* gd, int G, int total_rows, int kmax, int var, int honor_stop, int mode,

@@ -193,3 +193,34 @@ def test_momentum_trajectory(problem, path, gamma):
     s.step(1)
     assert normwise(host(s.W[0]), r.W) <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("k", [300, 576])
+@pytest.mark.parametrize("added,gamma", [(0, 0.0), (1, 0.0), (0, 0.9), (1, 0.9)],
+                         ids=["plain", "added", "momentum", "added_momentum"])
+def test_fast_path_many_colours(added, gamma, k):
+    """k from 289 to 576 on the fast schedule: the row update holds 24 or 36 colours per
+    lane, with and without the added fitness term (colour cost) and the velocity.  The
+    trajectory follows the oracle over 4 steps, colours and fitness exact at each step."""
+    case = case_for(MSCP if added else KCOL, FP32, n=333, k=k, D=4, seed=57, stop_on_legal=0, momentum=gamma,
+                    eta=0.05)
+    s, (A,) = make_solver([case], fused=1)
+    p = orc_params(case.params())
+    W = host(s.W[0]).astype(np.float64)
+    vel = np.zeros_like(W)
+    worst = 0.0
+    for t in range(4):
+        r = oracle.iteration(p, t, A, W, want_grads=False, vel=vel)
+        W = r.W
+        done, _ = s.step(1)
+        assert done == 1
+        e = normwise(host(s.W[0]), W)
+        worst = max(worst, e)
+        assert e <= TOL, (t, e)
+        c, fm, fs = s.conflicts(0)
+        c_ref = oracle.colors(W)
+        assert np.array_equal(host(c), c_ref)
+        fm_ref, fs_ref, _ = oracle.fitness(p, A, c_ref)
+        assert np.array_equal(host(fm), fm_ref) and np.array_equal(host(fs), fs_ref)
+    print(f"k={k} added={added} momentum={gamma}: worst W error {worst:.2e}")
+    s.close()
