@@ -120,6 +120,49 @@ __device__ __forceinline__ void stage_read(StageFrags<PREC, BM, NTW>& F, const u
     }
 }
 
+// One K-step (16-byte chunk ks*4 + q of every row) of a two-K-step stage, for the
+// staggered sweep below: the same chunks as stage_read's K-step ks.
+template <int PREC, int BM, int NTW>
+struct KStepFrags {
+    uint4 a[Tile<BM, NTW>::MT], b[NTW];
+};
+
+template <int PREC, int BM, int NTW>
+__device__ __forceinline__ void kstep_read(KStepFrags<PREC, BM, NTW>& F, const uint8_t* L, int ks, int lane, int wm,
+                                           int wn) {
+    const int ra = wm * Tile<BM, NTW>::RW + (lane & 15);
+    const int rb = BM + wn * (NTW * 16) + (lane & 15);
+    const int o = ((ks * 4 + (lane >> 4)) ^ ((lane & 15) >> 1)) * 16;
+#pragma unroll
+    for (int mt = 0; mt < Tile<BM, NTW>::MT; ++mt) F.a[mt] = *(const uint4*)(L + (ra + mt * 16) * kStageRowBytes + o);
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) F.b[nt] = *(const uint4*)(L + (rb + nt * 16) * kStageRowBytes + o);
+}
+
+template <int PREC, int BM, int NTW>
+__device__ __forceinline__ void kstep_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const KStepFrags<PREC, BM, NTW>& F) {
+    static_assert(PREC != kPrecFP8, "fp8 stages hold one K-step");
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < Tile<BM, NTW>::MT; ++mt) {
+            const uint4 a0 = F.a[mt], b0 = F.b[nt];
+            if constexpr (PREC == kPrecFP4) {
+                const i32x8 a{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, 0, 0, 0, 0};
+                const i32x8 b{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, 0, 0, 0, 0};
+                acc[mt][nt] = mfma_fp4(a, b, acc[mt][nt]);
+            } else if constexpr (PREC == kPrecBF16) {
+                acc[mt][nt] = mfma_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[mt][nt]);
+            } else {
+                const float4 a = __builtin_bit_cast(float4, a0), b = __builtin_bit_cast(float4, b0);
+                acc[mt][nt] = mfma_f32(a.x, b.x, acc[mt][nt]);
+                acc[mt][nt] = mfma_f32(a.y, b.y, acc[mt][nt]);
+                acc[mt][nt] = mfma_f32(a.z, b.z, acc[mt][nt]);
+                acc[mt][nt] = mfma_f32(a.w, b.w, acc[mt][nt]);
+            }
+        }
+}
+
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void stage_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const StageFrags<PREC, BM, NTW>& F) {
     using Fr = StageFrags<PREC, BM, NTW>;
@@ -202,7 +245,8 @@ __device__ __forceinline__ void stage_barrier() {
 // and LDS -> registers one stage ahead through two fragment sets, so the fragment
 // reads of stage s+1 proceed while the MFMAs of stage s run.  At the top of
 // iteration s every wave has finished reading stage s, so its buffer takes the
-// loads of stage s+NB.  Large tiles, whose two fragment sets would spill, keep one.
+// loads of stage s+NB.  Large tiles, whose two fragment sets would spill, keep one:
+// with two K-steps per stage they put the barrier between the K-steps instead.
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const uint8_t* __restrict__ Arow,
                                            const uint8_t* __restrict__ Brow, size_t ld, int nstages,
@@ -212,9 +256,40 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64) {
-        // tiles whose fragments would not fit twice in registers: one fragment set, the
-        // global -> LDS loads NB - 1 stages ahead
+    if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64 && Fr::SUB == 2) {
+        // tiles whose stage fragments would not fit twice in registers, two K-steps per
+        // stage: the barrier falls between the K-steps.  The second K-step's fragments
+        // are read before it and its MFMAs run after it, while the next stage's first
+        // K-step is read; the buffer freed at the barrier takes the loads of stage s+NB
+        // at once, so a load has a whole stage of MFMAs to land.  Two K-step sets hold
+        // as many registers as one stage set.
+        constexpr int NB = T::NB;
+        using KF = KStepFrags<PREC, BM, NTW>;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            stage_load<BM, NTW>(Arow, Brow, ld, min(b, nstages - 1), lds + b * T::STAGE, lane, wave);
+        wait_vm<(NB - 1) * T::GROUPS>();   // stage 0 has landed
+        stage_barrier();
+        KF Fa, Fb;
+        kstep_read<PREC, BM, NTW>(Fa, lds, 0, lane, wm, wn);
+        int cur = 0;
+        for (int s = 0; s < nstages; ++s) {
+            kstep_read<PREC, BM, NTW>(Fb, lds + cur * T::STAGE, 1, lane, wm, wn);
+            __builtin_amdgcn_sched_barrier(0);
+            kstep_mma<PREC, BM, NTW>(acc, Fa);
+            wait_vm<(NB - 2) * T::GROUPS>();   // stage s+1 has landed (later ones may be in flight)
+            stage_barrier();                   // ... for every wave, and no wave reads stage s any more
+            // past the end, the last stage again into the freed buffer; nobody reads it
+            stage_load<BM, NTW>(Arow, Brow, ld, min(s + NB, nstages - 1), lds + cur * T::STAGE, lane, wave);
+            cur = cur == NB - 1 ? 0 : cur + 1;
+            if (s + 1 < nstages) kstep_read<PREC, BM, NTW>(Fa, lds + cur * T::STAGE, 0, lane, wm, wn);
+            __builtin_amdgcn_sched_barrier(0);
+            kstep_mma<PREC, BM, NTW>(acc, Fb);
+        }
+        return;
+    } else if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64) {
+        // fp8 tiles whose fragments would not fit twice in registers: one fragment set,
+        // the global -> LDS loads NB - 1 stages ahead
         constexpr int NB = T::NB;
 #pragma unroll
         for (int b = 0; b < NB - 1; ++b)
