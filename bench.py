@@ -29,6 +29,10 @@ import tcolgen
 PEAK = {"fp4": 10.1e15, "fp8": 5.0e15, "bf16": 2.5e15, "fp32": 157.3e12}
 GEMM_SRC = os.path.join(ROOT, "paper_1909_02261_amd", "csrc", "tcol_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_hbm_traffic.txt")
+# penalty product: per-iteration choice (auto; the dense pass below a floor on n), dense MFMA
+# pass, sparse rows, per-iteration choice at any size
+PENALTY_MODES = {"auto": 0, "dense": 1, "sparse": 2, "auto-any-n": 3}
+PENALTY_NAMES = {v: k for k, v in PENALTY_MODES.items()}
 HBM_PEAK = 8.0e12
 PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8, "fp4": tcolgen.FP4}
 PROBLEMS = {"kcol": tcolgen.KCOL, "ecp": tcolgen.ECP, "kpart": tcolgen.KPART, "bkpart": tcolgen.BKPART,
@@ -166,7 +170,7 @@ def run_batch(args, torch, pk):
     s = pk.Solver(graphs, [pk.Params.from_dict(c.params()) for c in cases])
     s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
-                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
+                  penalty=PENALTY_MODES[args.penalty])
     opts = s.options()
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -199,7 +203,7 @@ def run_batch(args, torch, pk):
         "config": {"workload": "kcol_batch16_gnp_uneven", "graphs": len(cases), "n": [c.n for c in cases],
                    "k": [c.k for c in cases], "D": cases[0].D, "precision": prec, "path": args.path,
                    "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
-                   "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]]},
+                   "penalty": PENALTY_NAMES[opts["penalty"]]},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "k_gemm over the 16 graphs (A.S pass + penalty pass + fitness gather)",
@@ -219,7 +223,7 @@ def main():
                     help="c5b: the batch of 16 uneven graphs in one context")
     ap.add_argument("--precision", default=None, choices=list(PREC))
     ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
-    ap.add_argument("--penalty", default="auto", choices=["auto", "dense", "sparse"],
+    ap.add_argument("--penalty", default="auto", choices=list(PENALTY_MODES),
                     help="penalty product: per-iteration choice (auto), dense MFMA pass, or sparse rows")
     ap.add_argument("--problem", default=None, choices=list(PROBLEMS),
                     help="run the workload's graph and sizes as another problem (default: its own)")
@@ -274,7 +278,7 @@ def main():
     s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
     s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
-                  penalty={"auto": 0, "dense": 1, "sparse": 2}[args.penalty])
+                  penalty=PENALTY_MODES[args.penalty])
     if args.autotune:
         print("[bench] autotuning tile shape / penalty mode", file=sys.stderr, flush=True)
         s.autotune()
@@ -338,7 +342,7 @@ def main():
     config = {"workload": case.name, "problem": PROBLEM_NAMES[case.problem], "n": case.n,
               "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
               "hipgraph": not args.no_graph, "tile_bm": opts["tile_bm"], "tile_ntw": opts["tile_ntw"],
-              "penalty": {0: "auto", 1: "dense", 2: "sparse"}[opts["penalty"]], "fused": opts["fused"]}
+              "penalty": PENALTY_NAMES[opts["penalty"]], "fused": opts["fused"]}
     if case.momentum:
         config["momentum"] = case.momentum
     roof["traffic"] = measured_traffic(config)

@@ -129,9 +129,11 @@ typedef struct {
                                0 = choose (default): the sparse rows in the iterations where the
                                rows average at most n / 4 class-mates and the dense pass in the
                                others (decided on the device each iteration), the dense pass
-                               throughout when 4 D > k, the sparse rows throughout for
-                               k-partitioning.  Graphs too large for the sparse kernel's LDS
-                               take the dense pass. */
+                               throughout when 4 D > k or n < 2750, the sparse rows throughout
+                               for k-partitioning with n >= 2048 (the dense pass below: the
+                               faster route at those sizes); 3 = as 0 without the floors on n.
+                               Graphs too large for the sparse kernel's LDS take the dense
+                               pass. */
 } tcol_options;
 
 typedef struct tcol_ctx tcol_ctx;

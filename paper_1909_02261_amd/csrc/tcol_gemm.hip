@@ -141,7 +141,7 @@ __device__ __forceinline__ void kstep_read(KStepFrags<PREC, BM, NTW>& F, const u
 
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void kstep_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const KStepFrags<PREC, BM, NTW>& F) {
-    static_assert(PREC != kPrecFP8, "fp8 stages hold one K-step");
+    static_assert(PREC == kPrecFP4 || PREC == kPrecBF16, "fp4 and bf16 stages hold two K-steps");
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
@@ -151,14 +151,8 @@ __device__ __forceinline__ void kstep_mma(f32x4 (&acc)[tile_mt(BM)][NTW], const 
                 const i32x8 a{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, 0, 0, 0, 0};
                 const i32x8 b{(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, 0, 0, 0, 0};
                 acc[mt][nt] = mfma_fp4(a, b, acc[mt][nt]);
-            } else if constexpr (PREC == kPrecBF16) {
-                acc[mt][nt] = mfma_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[mt][nt]);
             } else {
-                const float4 a = __builtin_bit_cast(float4, a0), b = __builtin_bit_cast(float4, b0);
-                acc[mt][nt] = mfma_f32(a.x, b.x, acc[mt][nt]);
-                acc[mt][nt] = mfma_f32(a.y, b.y, acc[mt][nt]);
-                acc[mt][nt] = mfma_f32(a.z, b.z, acc[mt][nt]);
-                acc[mt][nt] = mfma_f32(a.w, b.w, acc[mt][nt]);
+                acc[mt][nt] = mfma_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[mt][nt]);
             }
         }
 }
@@ -246,7 +240,7 @@ __device__ __forceinline__ void stage_barrier() {
 // reads of stage s+1 proceed while the MFMAs of stage s run.  At the top of
 // iteration s every wave has finished reading stage s, so its buffer takes the
 // loads of stage s+NB.  Large tiles, whose two fragment sets would spill, keep one:
-// with two K-steps per stage they put the barrier between the K-steps instead.
+// in fp4 and bf16 (two K-steps per stage) they put the barrier between the K-steps.
 template <int PREC, int BM, int NTW>
 __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const uint8_t* __restrict__ Arow,
                                            const uint8_t* __restrict__ Brow, size_t ld, int nstages,
@@ -256,9 +250,9 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64 && Fr::SUB == 2) {
-        // tiles whose stage fragments would not fit twice in registers, two K-steps per
-        // stage: the barrier falls between the K-steps.  The second K-step's fragments
+    if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64 && Fr::SUB == 2 && PREC != kPrecFP32) {
+        // fp4 and bf16 tiles whose stage fragments would not fit twice in registers (two
+        // K-steps per stage): the barrier falls between the K-steps.  The second K-step's fragments
         // are read before it and its MFMAs run after it, while the next stage's first
         // K-step is read; the buffer freed at the barrier takes the loads of stage s+NB
         // at once, so a load has a whole stage of MFMAs to land.  Two K-step sets hold
@@ -288,8 +282,9 @@ __device__ __forceinline__ void gemm_sweep(f32x4 (&acc)[tile_mt(BM)][NTW], const
         }
         return;
     } else if constexpr (Fr::SUB * (Fr::MT + NTW) * Fr::W * 4 > 64) {
-        // fp8 tiles whose fragments would not fit twice in registers: one fragment set,
-        // the global -> LDS loads NB - 1 stages ahead
+        // fp8 and fp32 tiles whose fragments would not fit twice in registers: one
+        // fragment set, the global -> LDS loads NB - 1 stages ahead (fp32, whose K-step is
+        // four MFMAs, ran 8 % slower at C5 in the staggered form)
         constexpr int NB = T::NB;
 #pragma unroll
         for (int b = 0; b < NB - 1; ++b)

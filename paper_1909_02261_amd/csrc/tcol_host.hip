@@ -265,9 +265,15 @@ static void pick_shapes(tcol_ctx* c) {
 // and the per-iteration choice takes the sparse rows only while the rows average at most
 // n / 4 of them: with 4 D > k that never happens, so such graphs keep the dense operand
 // pass (and skip the class lists).  Otherwise the choice is made per iteration, and
-// partitioning, whose rows are dense either way, always takes the sparse rows.
-static bool sparse_preferred(const tcol_graph_params& p) {
-    return p.problem == TCOL_KPART || p.problem == TCOL_BKPART || 4LL * p.D <= p.k;
+// partitioning, whose rows are dense either way, always takes the sparse rows.  Below a
+// floor on n the dense pass is the faster route anyway: on G(n, .5) with k = n / 14.3
+// the two cost the same at n = 2600-2900 for colouring (D = 16 and 32, fp4 and bf16
+// operands; the dense pass 2-22 % faster below) and at about n = 2000 for partitioning
+// (D = 32, fp4; 15 % faster at n = 1000).  Penalty 3 drops the floors.
+constexpr int kSparseMinN = 2750, kSparseMinNPartition = 2048;
+static bool sparse_preferred(const tcol_graph_params& p, bool size_floor) {
+    if (p.problem == TCOL_KPART || p.problem == TCOL_BKPART) return !size_floor || p.n >= kSparseMinNPartition;
+    return 4LL * p.D <= p.k && (!size_floor || p.n >= kSparseMinN);
 }
 
 // Members per accumulator group PM of the sparse penalty kernel (a multiple of 8, at most
@@ -301,7 +307,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const int pen = c->opt.penalty;
-        c->hdesc[g].psparse = (pen == 2 || (pen == 0 && sparse_preferred(p))) ? 1 : 0;
+        c->hdesc[g].psparse = (pen == 2 || ((pen == 0 || pen == 3) && sparse_preferred(p, pen == 0))) ? 1 : 0;
         c->hdesc[g].ps_mode = pen == 2 ? 1 : 2;
         if (c->hdesc[g].psparse) {
             ps_k = std::max(ps_k, p.k);
@@ -740,7 +746,7 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
 tcol_status tcol_set_options(tcol_ctx* c, const tcol_options* o) {
     if (!c || !o) return TCOL_EINVAL;
     if (o->unroll < 0 || o->unroll > 64) return TCOL_EINVAL;
-    if (o->penalty < 0 || o->penalty > 2) return TCOL_EINVAL;
+    if (o->penalty < 0 || o->penalty > 3) return TCOL_EINVAL;
     if (o->fused < 0 || o->fused > 2) return TCOL_EINVAL;
     if ((o->tile_bm || o->tile_ntw) && !shape_listed(o->tile_bm, o->tile_ntw)) return TCOL_EINVAL;
     tcol_options old = c->opt;

@@ -458,19 +458,19 @@ def test_penalty_pass_every_tile_shape(prec):
 
 @pytest.mark.parametrize("prec", [FP32, FP8, FP4])
 def test_auto_penalty_small_classes(prec):
-    """Automatic penalty choice on rows that stay sparse (n = 600, k = 60, D = 4: about
-    40 class-mates per row against n / 4 = 150), so every iteration takes the sparse
-    rows, which are FP32 in every operand mode."""
+    """Per-iteration penalty choice without the size floor (penalty 3) on rows that stay
+    sparse (n = 600, k = 60, D = 4: about 40 class-mates per row against n / 4 = 150), so
+    every iteration takes the sparse rows, which are FP32 in every operand mode."""
     case = GraphCase("auto_sparse", KCOL, 600, 60, 4, prec, "gnp", 0.3, graph_seed=61, rho=10.0,
                      lam=1e-2, mu=3e-3, stop_on_legal=0)
-    worst = run_resynced(case, 8, TOL, t0=2, fused=1, penalty=0)
+    worst = run_resynced(case, 8, TOL, t0=2, fused=1, penalty=3)
     print(f"auto penalty, prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
 @pytest.mark.parametrize("path", ["fast_auto", "epi_auto"])
 @pytest.mark.parametrize("prec", [FP32, FP8])
 def test_auto_penalty_switches(prec, path):
-    """Automatic penalty choice along a trajectory whose smoothing (rho = 100 every second
+    """Per-iteration penalty choice (penalty 3, no size floor) along a trajectory whose smoothing (rho = 100 every second
     iteration) drives the population in and out of large classes, so iterations take the
     dense pass and the sparse rows in turn; FP8 also checks that the bf16 copy of S the
     dense pass reads is written in exactly the iterations that need it."""
@@ -479,20 +479,22 @@ def test_auto_penalty_switches(prec, path):
     W = case.weights()
     W[0, :200, 0] += 0.05       # member 0 starts with a class of 200 vertices
     fused = 1 if path == "fast_auto" else 2
-    worst = run_resynced(case, 12, TOL if prec == FP32 else 1e-2, W=W, fused=fused, penalty=0)
+    worst = run_resynced(case, 12, TOL if prec == FP32 else 1e-2, W=W, fused=fused, penalty=3)
     print(f"auto switching {path}, prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
-def test_c5b_batch_step_every_graph():
+@pytest.mark.parametrize("penalty", [0, 3])
+def test_c5b_batch_step_every_graph(penalty):
     """The uneven batch (16 graphs, n from 250 to 2000, p cycling .1/.5/.9, each with its
-    greedy colour count as k, D = 16) in one context: one launch sequence steps all of them,
-    the penalty taken per graph and iteration (sparse rows or the bf16 dense pass).  One
-    step from t = 10 is compared with the oracle graph by graph, and the colours and
-    conflict counts after it are exact."""
+    greedy colour count as k, D = 16) in one context: one launch sequence steps all of them.
+    With penalty 0 every graph is below the sparse rows' size floor and takes the bf16
+    dense pass; with penalty 3 the penalty is taken per graph and iteration (sparse rows
+    or the dense pass).  One step from t = 10 is compared with the oracle graph by graph,
+    and the colours and conflict counts after it are exact."""
     cases = tcolgen.cases_c5b(BF16)
     for c in cases:
         c.stop_on_legal = 0
-    s, As = make_solver(cases)
+    s, As = make_solver(cases, penalty=penalty)
     t0 = 10
     s.set_t(t0)
     W0 = [host(w).copy() for w in s.W]
