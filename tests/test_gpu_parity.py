@@ -467,6 +467,24 @@ def test_auto_penalty_small_classes(prec):
     print(f"auto penalty, prec {prec}: worst W error vs FP64 {worst:.2e}")
 
 
+def test_auto_penalty_size_floor():
+    """Below the size floor (n = 600) the automatic choice keeps the dense pass even though
+    the classes are small: its steps equal those of penalty 1 bit for bit, while penalty 3
+    (no floor) takes the sparse FP32 rows, which differ from the bf16 dense operand."""
+    case = GraphCase("floor", KCOL, 600, 60, 4, BF16, "gnp", 0.3, graph_seed=61, rho=10.0,
+                     lam=1e-2, mu=3e-3, stop_on_legal=0)
+    out = {}
+    for pen in (0, 1, 3):
+        s, _ = make_solver([case], fused=1, penalty=pen)
+        s.set_t(2)
+        done, _ = s.step(4)
+        assert done == 4
+        out[pen] = host(s.W[0]).copy()
+        s.close()
+    assert np.array_equal(out[0], out[1])
+    assert not np.array_equal(out[3], out[1])
+
+
 @pytest.mark.parametrize("path", ["fast_auto", "epi_auto"])
 @pytest.mark.parametrize("prec", [FP32, FP8])
 def test_auto_penalty_switches(prec, path):
