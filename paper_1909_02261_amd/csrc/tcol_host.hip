@@ -392,7 +392,7 @@ static hipError_t launch_update_any(tcol_ctx* c, int honor, int mode, int gsel, 
 // one Algorithm-1 iteration for every running graph (plain path)
 static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     HIPRET(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 15, 0, s));
@@ -403,7 +403,7 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 }
 
 // penalty of the fast and epilogue paths: sparse penalty rows or the dense operand, per
-// graph and, for graphs that choose per iteration, per iteration (launch_decide).  On
+// graph and, for graphs that choose per iteration, per iteration (by launch_prep).  On
 // the epilogue path the sparse rows go to G before the contraction, whose epilogue adds
 // them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
@@ -416,8 +416,7 @@ static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
 // class sizes and lists of the current colours, then (fast and epilogue paths) the
 // iteration's penalty choice, which the expansion, penalty and contraction read
 static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
-    if (c->total_ps > 0) HIPRET(launch_decide(c->ddesc, c->G, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, c->total_ps > 0 ? 1 : 0, s));
     return hipSuccess;
 }
 
@@ -797,7 +796,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     // steps 1-2 for all graphs of the context (cheap), reporting only
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, c->stream));
     HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
@@ -808,7 +807,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
 tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* gradS_dev, float* gradW_dev) {
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagLoss | kFlagForcePen, g, nullptr, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 15, 0, c->stream));
@@ -867,7 +866,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         if (path != 0)
             HIPCHK(enqueue_prep(c, s));
         else
-            HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, s));
+            HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, s));
         HIPCHK(hipEventRecord(ev[2], s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, path != 0 ? 1 : 0, s));
         HIPCHK(hipEventRecord(ev[3], s));
@@ -928,7 +927,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     ms[8] = 0.0f;
     if (as_only) {
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
-        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
         HIPCHK(hipEventRecord(ev[0], s));
         for (int it = 0; it < steps; ++it) HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, s));

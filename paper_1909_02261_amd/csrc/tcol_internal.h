@@ -58,6 +58,8 @@ struct GraphState {
     int pS;             // fused path: which colour / S buffer set is current
     int next_bad;       // fused path: the update produced a non-finite weight
     int pdense;         // sparse penalty graphs: this iteration takes the dense operand pass
+    int prep_ticket;    // member blocks of the class-size kernel done this iteration (the
+                        // last one takes the penalty choice and sets it back to 0)
 };
 
 // per-graph descriptor, uploaded once at init

@@ -153,15 +153,27 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
     }
 }
 
+// Per-iteration penalty choice of graphs on the sparse rows (ps_mode 2): row i has at
+// most sum_d |class of c_d(i)| nonzeros in P, and over all rows that is
+// w = sum_d sum_l #V_{d,l}^2.  While its average over the rows stays within n / 4 the
+// iteration takes the sparse rows; beyond (the population collapsing into a few large
+// classes) the dense pass, whose cost does not depend on the classes.  Partitioning
+// keeps the sparse rows: its operand over D - Mt has nonzeros wherever Mt < D, so its
+// rows are dense anyway and the sparse kernel is the faster on them.  Returns pdense.
+__device__ inline int penalty_choice(const GraphDev& d, long long w) {
+    return d.ps_mode == 2 && !prob_partition(d.problem) && w > (long long)d.n * d.n / 4 ? 1 : 0;
+}
+
 // Class sizes #V_{d,l} of member d, its added fitness (equity or colour cost) and
 // the vertex-major copy of its colours.
 // For a graph on the sparse penalty also the member's vertices grouped by colour
-// (counting sort) and, for each vertex, the start and size of its class.  One block
-// per member.
+// (counting sort) and, for each vertex, the start and size of its class; with `decide`
+// the last of the graph's member blocks then takes the iteration's penalty choice
+// (penalty_choice).  One block per member.
 // Dynamic LDS: k counts, and with the class lists 4 k per-wave cursors, k class starts
 // and n entries.
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
-                                              int next) {
+                                              int next, int decide) {
     extern __shared__ int prep_sh[];
     __shared__ int part[257];
     const int mem = blockIdx.x;
@@ -235,6 +247,27 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
         if ((tid & 63) == 0) qsum[tid >> 6] = q2;
         __syncthreads();
         if (tid == 0) d.sq[m] = qsum[0] + qsum[1] + qsum[2] + qsum[3];
+        if (decide) {
+            // the last member block to get here sums every member's value (a ticket
+            // counter after a release fence; the last block reads the others' values
+            // with atomic loads after an acquire fence) and resets the counter
+            __shared__ int last_block;
+            if (tid == 0) {
+                __threadfence();
+                last_block = atomicAdd(&st->prep_ticket, 1) == d.D - 1;
+            }
+            __syncthreads();
+            if (last_block && tid < 64) {
+                __threadfence();
+                long long w = 0;
+                for (int mm = tid; mm < d.D; mm += 64) w += __atomic_load_n(d.sq + mm, __ATOMIC_RELAXED);
+                for (int sh = 32; sh >= 1; sh >>= 1) w += __shfl_xor(w, sh);
+                if (tid == 0) {
+                    st->pdense = penalty_choice(d, w);
+                    st->prep_ticket = 0;
+                }
+            }
+        }
     }
     int* offl = cw + NW * k;                        // [k] class starts
     int16_t* lst = (int16_t*)(offl + k);            // [n]
@@ -322,7 +355,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 //      vertices), then the group's sums go to G[d][i][l], added to the contraction's
 //      A.S_d (accumulate 1) or written for the contraction's epilogue (accumulate 0).
 // A graph choosing per iteration (ps_mode 2) takes these rows only in the iterations
-// where k_decide found its classes small; otherwise the contraction's dense pass.
+// where the class-size kernel found its classes small; otherwise the contraction's dense pass.
 // Steps 1 and 3 issue the loads of their next batch before the atomics of the current
 // one.  The sums are taken in 64-bit fixed point: every table value times 2^sc, with sc
 // chosen so that n max|P| stays below 2^62, is an integer whenever the table's binary
@@ -611,25 +644,6 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     }
 }
 
-// Per-iteration penalty choice of graphs on the sparse rows (ps_mode 2): row i has at
-// most sum_d |class of c_d(i)| nonzeros in P, and over all rows that is
-// sum_d sum_l #V_{d,l}^2.  While its average over the rows stays within n / 4 the
-// iteration takes the sparse rows; beyond (the population collapsing into a few large
-// classes) the dense pass, whose cost does not depend on the classes.  Partitioning
-// keeps the sparse rows: its operand over D - Mt has nonzeros wherever Mt < D, so its
-// rows are dense anyway and the sparse kernel is the faster on them.  One block per graph.
-__global__ __launch_bounds__(64) void k_decide(const GraphDev* __restrict__ gd, int G) {
-    const GraphDev& d = gd[blockIdx.x];
-    GraphState* st = d.st;
-    if (!d.psparse) return;
-    long long w = 0;
-    for (int m = threadIdx.x; m < d.D; m += 64) w += gview(d.sq)[m];
-    for (int sh = 32; sh >= 1; sh >>= 1) w += __shfl_xor(w, sh);
-    if (threadIdx.x == 0) {
-        const bool dense = d.ps_mode == 2 && !prob_partition(d.problem) && w > (long long)d.n * d.n / 4;
-        st->pdense = dense ? 1 : 0;
-    }
-}
 
 // One-hot S^T [rows (d,l)][cols j] in the operand format; 16 columns per thread
 // (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
@@ -1324,10 +1338,11 @@ size_t prep_lds(int kmax, int nmax, int lists) {
     return (b + 15) / 16 * 16;
 }
 
-hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s) {
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, int decide,
+                       hipStream_t s) {
     if (total_mem <= 0) return hipSuccess;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), lds, s, gd, G, total_mem, honor_stop, next);
+    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), lds, s, gd, G, total_mem, honor_stop, next, decide);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -1350,12 +1365,6 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
     const size_t b = 8 * ps_tab_words(dmax) + 2 * 4 * ps_int_words(dmax) + 16 + 2 * (size_t)round_up(dmax, 8) +
                      4 * n_pad + work;
     return (b + 15) / 16 * 16;
-}
-
-hipError_t launch_decide(const GraphDev* gd, int G, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(G), dim3(64), 0, s, gd, G);
-    TCOL_LAUNCH_CHECK();
-    return hipSuccess;
 }
 
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,

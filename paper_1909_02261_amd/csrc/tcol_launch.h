@@ -14,7 +14,9 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
 // class sizes and vertex-major colours; with lists != 0 also the class lists of graphs on the
 // sparse penalty (dynamic LDS from prep_lds)
 size_t prep_lds(int kmax, int nmax, int lists);
-hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, hipStream_t s);
+// decide: graphs on the sparse rows also take the iteration's penalty choice (pdense)
+hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, int decide,
+                       hipStream_t s);
 hipError_t penalty_sparse_prepare();
 // sparse penalty rows: one row per block of `threads` (256, 512 or 1024), members PM at a
 // time (a multiple of 8)
@@ -23,8 +25,6 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax);
 // contraction's G (fast path)
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
                                  int accumulate, hipStream_t s);
-// the iteration's penalty choice of graphs on the sparse rows (after launch_prep)
-hipError_t launch_decide(const GraphDev* gd, int G, hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
