@@ -408,7 +408,7 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 // them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
     if (c->total_ps > 0 && path_of(c) == 2)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 0, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
@@ -420,9 +420,14 @@ static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
     return hipSuccess;
 }
 
-static hipError_t enqueue_sparse_add(tcol_ctx* c, hipStream_t s) {
+// fast path: the sparse rows added to the contraction's G; with `fitness` the same launch
+// takes every graph's fitness too (one launch fewer), else the caller launches it
+static hipError_t enqueue_sparse_add(tcol_ctx* c, bool fitness, hipStream_t s) {
     if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1,
+                                     fitness ? c->G : 0, s));
+    else if (fitness)
+        HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
     return hipSuccess;
 }
 
@@ -432,8 +437,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
     HIPRET(enqueue_penalty(c, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
-    HIPRET(enqueue_sparse_add(c, s));
-    HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+    HIPRET(enqueue_sparse_add(c, true, s));
     HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
     HIPRET(launch_advance(c->ddesc, c->G, s));
     return hipSuccess;
@@ -880,7 +884,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         else
             HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
-        if (path == 1) HIPCHK(enqueue_sparse_add(c, s));
+        if (path == 1) HIPCHK(enqueue_sparse_add(c, false, s));
         HIPCHK(hipEventRecord(ev[6], s));
         HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
         HIPCHK(hipEventRecord(ev[7], s));

@@ -368,6 +368,10 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 // an excluded diagonal), class starts and the prefix of the class sizes [D + 1] i32
 // each, the list length, row i's colours [cTs] i16, list [n_pad] u32, then counts
 // [n_pad] u32 overlaid by the group's accumulators [PM][k] i64.
+// the fitness of one graph (the fitness kernel's body; the fast path runs it in extra
+// blocks of the sparse penalty launch, since both follow the contraction)
+__device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best);
+
 __host__ __device__ inline size_t ps_tab_words(int D) { return ((size_t)2 * (D + 1) + 1 + 1) & ~(size_t)1; }
 __host__ __device__ inline size_t ps_int_words(int D) { return ((size_t)D + 1 + 3) & ~(size_t)3; }
 constexpr int kPsBatch = 4;     // entries per thread per batch in steps 1 and 3 (48 registers: eight waves per SIMD)
@@ -375,11 +379,17 @@ constexpr int kPsA8 = 2;        // adjacency words per thread loaded at the star
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                   int honor_stop, int PM, int accumulate) {
+                                                   int honor_stop, int PM, int accumulate, int fit_graphs) {
     extern __shared__ __attribute__((aligned(16))) uint8_t ps_sh[];
     constexpr int B = kPsBatch;
     const int b = blockIdx.x;
-    if (b >= total_blocks) return;
+    if (b >= total_blocks) {
+        // blocks past the rows: the fitness of graph b - total_blocks (its one shared word
+        // in the dynamic LDS: the kernel has no static LDS, so the dynamic size may reach
+        // the full 160 KB)
+        if (b - total_blocks < fit_graphs) fitness_graph(gd, b - total_blocks, honor_stop, 0, (int*)ps_sh);
+        return;
+    }
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -928,11 +938,8 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
 // the colour cost sum_l (l + 1) #V_l) as the class-size kernel left it; f = main + added;
 // lowest legal member; stop rule.  Clears f2.  With kFlagReport only the fitness
 // arrays are written.
-__global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd, int G, int honor_stop,
-                                                 int flags, int gsel) {
-    __shared__ int best;
-    const int g = blockIdx.x;
-    if (g >= G || (gsel >= 0 && g != gsel)) return;
+__device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best_sh) {
+    int& best = *best_sh;
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -974,6 +981,14 @@ __global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd
             st->stopped = 1;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_fitness(const GraphDev* __restrict__ gd, int G, int honor_stop,
+                                                 int flags, int gsel) {
+    __shared__ int best;
+    const int g = blockIdx.x;
+    if (g >= G || (gsel >= 0 && g != gsel)) return;
+    fitness_graph(gd, g, honor_stop, flags, &best);
 }
 
 // Separate-kernel path, step 4: softmax along k, straight-through gradient,
@@ -1368,13 +1383,14 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
 }
 
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
-                                 int accumulate, hipStream_t s) {
+                                 int accumulate, int fit_graphs, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
+    const int grid = blocks + fit_graphs;
     if (PM < 8 || (PM & 7) || lds > 160 * 1024) return hipErrorInvalidValue;
     switch (threads) {
-        case 256: k_pen_sparse<256><<<blocks, 256, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
-        case 512: k_pen_sparse<512><<<blocks, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
-        case 1024: k_pen_sparse<1024><<<blocks, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate); break;
+        case 256: k_pen_sparse<256><<<grid, 256, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
+        case 512: k_pen_sparse<512><<<grid, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
+        case 1024: k_pen_sparse<1024><<<grid, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
         default: return hipErrorInvalidValue;
     }
     TCOL_LAUNCH_CHECK();

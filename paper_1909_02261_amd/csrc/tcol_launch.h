@@ -22,9 +22,10 @@ hipError_t penalty_sparse_prepare();
 // time (a multiple of 8)
 size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax);
 // accumulate 0: rows written to G before the contraction (epilogue path); 1: added to the
-// contraction's G (fast path)
+// contraction's G (fast path).  fit_graphs > 0: the same launch also takes the fitness of
+// graphs 0 .. fit_graphs - 1 (as launch_fitness with flags 0), in blocks after the rows
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
-                                 int accumulate, hipStream_t s);
+                                 int accumulate, int fit_graphs, hipStream_t s);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
