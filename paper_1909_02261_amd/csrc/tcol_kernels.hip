@@ -172,12 +172,20 @@ __device__ inline int penalty_choice(const GraphDev& d, long long w) {
 // (penalty_choice).  One block per member.
 // Dynamic LDS: k counts, and with the class lists 4 k per-wave cursors, k class starts
 // and n entries.
+// block b of the S^T expansion (the expansion kernel's body; the fast path runs it in
+// extra blocks of the class-size launch, since both read only the colours)
+__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate);
+
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
-                                              int next, int decide) {
+                                              int next, int decide, int ex_blocks) {
     extern __shared__ int prep_sh[];
     __shared__ int part[257];
     const int mem = blockIdx.x;
-    if (mem >= total_mem) return;
+    if (mem >= total_mem) {
+        // blocks past the members: the expansion of the current colours (gate 1)
+        if (mem - total_mem < ex_blocks) expand_block(gd, G, mem - total_mem, honor_stop, next, 1);
+        return;
+    }
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -659,10 +667,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
 // (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
 // graphs the bf16 copy used by the penalty pass is written as well (the fp4 penalty
 // pass reads the fp4 operand itself).
-__global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                int honor_stop, int next, int gate) {
-    const int b = blockIdx.x;
-    if (b >= total_blocks) return;
+__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate) {
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ex_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -737,6 +742,13 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
             *(uint2*)((uint8_t*)d.Sop[p] + (off >> 1)) = make_uint2(w[0], w[1]);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd, int G, int total_blocks,
+                                                int honor_stop, int next, int gate) {
+    const int b = blockIdx.x;
+    if (b >= total_blocks) return;
+    expand_block(gd, G, b, honor_stop, next, gate);
 }
 
 // ------------------------------------------------------------ step 3 -----------
@@ -1354,10 +1366,11 @@ size_t prep_lds(int kmax, int nmax, int lists) {
 }
 
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, int decide,
-                       hipStream_t s) {
+                       int ex_blocks, hipStream_t s) {
     if (total_mem <= 0) return hipSuccess;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prep, dim3(total_mem), dim3(256), lds, s, gd, G, total_mem, honor_stop, next, decide);
+    hipLaunchKernelGGL(k_prep, dim3(total_mem + ex_blocks), dim3(256), lds, s, gd, G, total_mem, honor_stop, next,
+                       decide, ex_blocks);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }
