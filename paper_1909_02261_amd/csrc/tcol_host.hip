@@ -392,7 +392,7 @@ static hipError_t launch_update_any(tcol_ctx* c, int honor, int mode, int gsel, 
 // one Algorithm-1 iteration for every running graph (plain path)
 static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     HIPRET(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, 0, 0, s));
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 15, 0, s));
@@ -416,7 +416,7 @@ static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
 // class sizes and lists of the current colours, then (fast and epilogue paths) the
 // iteration's penalty choice, which the expansion, penalty and contraction read
 static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
-    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, c->total_ps > 0 ? 1 : 0, 0, s));
+    HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, c->total_ps > 0 ? 1 : 0, 0, 0, s));
     return hipSuccess;
 }
 
@@ -442,16 +442,19 @@ static bool any_split(const tcol_ctx* c) {
 // one iteration on the fast path; c[pS] holds the colours of the current weights.  The
 // expansion reads only the colours, so unless it depends on the penalty choice its
 // blocks ride on the class-size launch
-static hipError_t enqueue_step_fast(tcol_ctx* c, hipStream_t s) {
+// blocks ride on the class-size launch.  In a run of iterations the class-size launch
+// also ends the previous one (advance_prev), and only the last iteration launches its own
+// end (advance_own)
+static hipError_t enqueue_step_fast(tcol_ctx* c, bool advance_prev, bool advance_own, hipStream_t s) {
     const bool merged = !any_split(c);
     HIPRET(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, c->total_ps > 0 ? 1 : 0,
-                       merged ? c->total_ex : 0, s));
+                       merged ? c->total_ex : 0, advance_prev ? 1 : 0, s));
     HIPRET(enqueue_penalty(c, s));
     if (!merged) HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
     HIPRET(enqueue_sparse_add(c, true, s));
     HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
-    HIPRET(launch_advance(c->ddesc, c->G, s));
+    if (advance_own) HIPRET(launch_advance(c->ddesc, c->G, s));
     return hipSuccess;
 }
 
@@ -468,7 +471,8 @@ static hipError_t enqueue_step_fused(tcol_ctx* c, hipStream_t s) {
 static hipError_t enqueue_steps(tcol_ctx* c, int n, hipStream_t s) {
     const int path = path_of(c);
     for (int i = 0; i < n; ++i)
-        HIPRET(path == 2 ? enqueue_step_fused(c, s) : (path == 1 ? enqueue_step_fast(c, s) : enqueue_step_plain(c, s)));
+        HIPRET(path == 2 ? enqueue_step_fused(c, s)
+                         : (path == 1 ? enqueue_step_fast(c, i > 0, i == n - 1, s) : enqueue_step_plain(c, s)));
     return hipSuccess;
 }
 
@@ -812,7 +816,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     // steps 1-2 for all graphs of the context (cheap), reporting only
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, c->stream));
     HIPCHK(launch_fitness(c->ddesc, c->G, 0, kFlagReport, -1, c->stream));
@@ -823,7 +827,7 @@ tcol_status tcol_conflicts(tcol_ctx* c, int32_t g, int16_t* colors_dev, int64_t*
 tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* gradS_dev, float* gradW_dev) {
     if (!c || g < 0 || g >= c->G) return TCOL_EINVAL;
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
-    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_mtilde(c->ddesc, c->G, c->total_mt, 0, kFlagLoss | kFlagForcePen, g, nullptr, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 15, 0, c->stream));
@@ -882,7 +886,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         if (path != 0)
             HIPCHK(enqueue_prep(c, s));
         else
-            HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, 0, s));
+            HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 1, 0, 0, 0, 0, s));
         HIPCHK(hipEventRecord(ev[2], s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, path != 0 ? 1 : 0, s));
         HIPCHK(hipEventRecord(ev[3], s));
@@ -943,7 +947,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     ms[8] = 0.0f;
     if (as_only) {
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
-        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, s));
+        HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
         HIPCHK(hipEventRecord(ev[0], s));
         for (int it = 0; it < steps; ++it) HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, s));

@@ -176,8 +176,20 @@ __device__ inline int penalty_choice(const GraphDev& d, long long w) {
 // extra blocks of the class-size launch, since both read only the colours)
 __device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate);
 
+// end of an iteration for a running graph: t <- t + 1, and a non-finite weight from the
+// update stops the graph with an error
+__device__ inline void advance_graph(GraphState* st) {
+    if (st->stopped) return;
+    st->t += 1;
+    st->steps_done += 1;
+    if (st->next_bad) {
+        st->error = -5;
+        st->stopped = 1;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
-                                              int next, int decide, int ex_blocks) {
+                                              int next, int decide, int ex_blocks, int advance_prev) {
     extern __shared__ int prep_sh[];
     __shared__ int part[257];
     const int mem = blockIdx.x;
@@ -188,6 +200,10 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     }
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
     GraphState* st = d.st;
+    // the previous iteration's end (its own launch otherwise), by the graph's first member
+    // block: nothing in this launch reads t, and a stop it raises only idles the rest of
+    // the iteration
+    if (advance_prev && mem == d.mem_begin && threadIdx.x == 0) advance_graph(st);
     if (honor_stop && st->stopped) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     const int m = mem - d.mem_begin;
@@ -1205,15 +1221,7 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
 __global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G) return;
-    GraphState* st = gd[g].st;
-    if (st->stopped) return;
-    st->t += 1;
-    st->steps_done += 1;
-    if (st->next_bad) {
-        // the update just made produced a non-finite weight
-        st->error = -5;
-        st->stopped = 1;
-    }
+    advance_graph(gd[g].st);
 }
 
 // FP64 loss of one graph: L = sum main fitness + nu t sum added fitness + lambda t kappa
@@ -1366,11 +1374,11 @@ size_t prep_lds(int kmax, int nmax, int lists) {
 }
 
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, int decide,
-                       int ex_blocks, hipStream_t s) {
+                       int ex_blocks, int advance_prev, hipStream_t s) {
     if (total_mem <= 0) return hipSuccess;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_prep, dim3(total_mem + ex_blocks), dim3(256), lds, s, gd, G, total_mem, honor_stop, next,
-                       decide, ex_blocks);
+                       decide, ex_blocks, advance_prev);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -16,9 +16,10 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
 size_t prep_lds(int kmax, int nmax, int lists);
 // decide: graphs on the sparse rows also take the iteration's penalty choice (pdense);
 // ex_blocks > 0: the same launch also runs the expansion's blocks (as launch_expand with
-// gate 1 and the same honor_stop and next), which must then not depend on the choice
+// gate 1 and the same honor_stop and next), which must then not depend on the choice;
+// advance_prev: the launch first ends the previous iteration (as launch_advance)
 hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int honor_stop, int next, int decide,
-                       int ex_blocks, hipStream_t s);
+                       int ex_blocks, int advance_prev, hipStream_t s);
 hipError_t penalty_sparse_prepare();
 // sparse penalty rows: one row per block of `threads` (256, 512 or 1024), members PM at a
 // time (a multiple of 8)
