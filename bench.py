@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 schedule's rate")
+    ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--tile-bm", type=int, default=0)
     ap.add_argument("--tile-ntw", type=int, default=0)
@@ -288,6 +290,8 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cnt0 = s.counters()
+    t_first = s.get_t()
     torch.cuda.synchronize()
     e0.record(stream)
     done, _ = s.step(args.steps)
@@ -295,35 +299,33 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     assert done == args.steps
+    cnt1 = s.counters()
+    routes = {k: cnt1[k] - cnt0[k] for k in cnt0}
+    assert sum(routes.values()) == args.steps, routes
     value = case.D * args.steps / (ms / 1e3)
-    print(f"[bench] timed {args.steps} steps: {ms / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] timed {args.steps} steps (t = {t_first} .. {t_first + args.steps - 1}): "
+          f"{ms / args.steps:.3f} ms/step; penalty routes {routes}", file=sys.stderr, flush=True)
 
     # per-kernel durations (HIP events around each launch on the same stream)
     ph = s.profile(args.profile_steps, as_only=True)
-    t_now = s.get_t()
-    f_as, f_pen = gemm_flops(case, t_now)
-    if opts["penalty"] == 2:
-        f_pen = 0.0          # the sparse rows, not the contraction, compute the penalty term
-    gemm_s = ph["gemm"] / 1e3
-    achieved = (f_as + f_pen) / gemm_s
-    peak = mixed_peak(prec, f_as, f_pen)
-    as_s = ph["gemm_as_only"] / 1e3
-    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
-            "kernel": "k_gemm (A.S pass + penalty pass + fitness gather)" if f_pen else "k_gemm (A.S pass + fitness gather)",
-            "flops_per_launch": f_as + f_pen, "ms_per_launch": ph["gemm"]}
-    roof_as = {"bound": "mfma", "achieved": f_as / as_s / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-               "frac": f_as / as_s / PEAK[prec], "ms_per_launch": ph["gemm_as_only"]}
     print(f"[bench] phases ms {json.dumps({k: round(v, 4) for k, v in ph.items()})}", file=sys.stderr, flush=True)
+    roof, roof_as, f_as, f_pen = contraction_roofline(case, prec, opts, ph, routes)
+
+    parity = None
+    if not args.no_cpu_baseline:
+        print("[bench] one step of each penalty route against the oracle", file=sys.stderr, flush=True)
+        parity = oracle_parity(s, case, A, torch)
     s.close()
     # the same fractions against this device's measured MFMA throughput (register-operand
     # chains on every CU, no memory traffic), beside the published peaks above
     pm_as = max(pk.mfma_peak(PREC[prec]) for _ in range(3)) * 1e12
     pm_pen = max(pk.mfma_peak(tcolgen.BF16) for _ in range(3)) * 1e12 if prec in ("fp8", "fp4") else pm_as
-    mixed_m = (f_as + f_pen) / (f_as / pm_as + f_pen / pm_pen)
+    n_it = args.steps
+    n_d = routes["dense"]
+    mixed_m = (n_it * f_as + n_d * f_pen) / (n_it * f_as / pm_as + n_d * f_pen / pm_pen)
     measured_peak = {"unit": "TFLOP/s", "operand": pm_as / 1e12, "penalty_operand": pm_pen / 1e12,
-                     "k_gemm_peak": mixed_m / 1e12, "k_gemm_frac": achieved / mixed_m,
-                     "as_only_frac": f_as / as_s / pm_as, "method": "tcol_mfma_peak"}
+                     "k_gemm_step_peak": mixed_m / 1e12, "k_gemm_step_frac": roof["achieved"] * 1e12 / mixed_m,
+                     "as_only_frac": roof_as["achieved"] * 1e12 / pm_as, "method": "tcol_mfma_peak"}
     print(f"[bench] measured MFMA peak {json.dumps(measured_peak)}", file=sys.stderr, flush=True)
     if args.calib_copy_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the others
@@ -334,10 +336,16 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
 
+    plain = None
+    if not args.no_plain and case.momentum == 0.0:
+        plain = plain_fp32_rate(case, A, W0, torch, pk, args.plain_steps)
+        print(f"[bench] plain FP32 path {json.dumps(plain)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] oracle baseline ({args.cpu_seconds:.0f} s budget)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(case, A, W0, args.cpu_seconds)
+        cpu["oracle_parity"] = parity
 
     config = {"workload": case.name, "problem": PROBLEM_NAMES[case.problem], "n": case.n,
               "k": case.k, "D": case.D, "p": case.p, "precision": prec, "path": args.path,
@@ -360,13 +368,114 @@ def main():
         "dtype": prec,
         "data": "synthetic (seeded Philox G(n,p) graph and N(0, 0.01^2) weights)",
         "config": config,
+        "timed_iterations": {"t_first": t_first, "t_last": t_first + args.steps - 1, "penalty_route": routes},
         "roofline": roof,
         "roofline_as_only": roof_as,
         "mfma_peak_measured": measured_peak,
+        "plain_fp32": plain,
+        "vs_plain_fp32": (value / plain["value"]) if plain else None,
         "phases_ms": ph,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def contraction_roofline(case, prec, opts, ph, routes):
+    """Roofline of k_gemm over the timed step: every iteration runs the A.S pass (with the
+    fitness gather and the store of G); the iterations whose penalty product took the dense
+    route also run the bf16 penalty pass in the same launch.  achieved = the flops of the
+    timed iterations' launches over their time, each launch form timed back to back
+    (tcol_profile: 'gemm' with the penalty pass, 'gemm_as_store' without); peak = those
+    flops over the time each pass takes at its operand's peak."""
+    f_as, f_pen = gemm_flops(case, 1)
+    if opts["penalty"] == 2:
+        f_pen = 0.0                   # the sparse rows, not the contraction, take the penalty
+    n_d, n_o = routes["dense"], routes["sparse"] + routes["no_penalty"]
+    if f_pen == 0.0:
+        n_o, n_d = n_o + n_d, 0
+    t_d, t_o = ph["gemm"] / 1e3, ph["gemm_as_store"] / 1e3
+    flops = (n_d + n_o) * f_as + n_d * f_pen
+    secs = n_d * t_d + n_o * t_o
+    p_as = PEAK[prec]
+    p_pen = PEAK["bf16"] if prec in ("fp8", "fp4") else PEAK[prec]
+    peak = flops / ((n_d + n_o) * f_as / p_as + n_d * f_pen / p_pen)
+    achieved = flops / secs
+    launches = {
+        "with_penalty_pass": {"count": n_d, "ms": ph["gemm"], "flops": f_as + f_pen,
+                              "frac": (f_as + f_pen) / t_d / mixed_peak(prec, f_as, f_pen)},
+        "as_pass_and_store": {"count": n_o, "ms": ph["gemm_as_store"], "flops": f_as,
+                              "frac": f_as / t_o / p_as},
+    }
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "k_gemm over the timed iterations (A.S pass + fitness gather + G store, and the bf16 "
+                      "penalty pass in the iterations whose penalty took the dense route)",
+            "flops_per_launch": flops / (n_d + n_o), "ms_per_launch": secs * 1e3 / (n_d + n_o),
+            "launches": launches}
+    as_s = ph["gemm_as_only"] / 1e3
+    roof_as = {"bound": "mfma", "achieved": f_as / as_s / 1e12, "peak": p_as / 1e12, "unit": "TFLOP/s",
+               "frac": f_as / as_s / p_as, "ms_per_launch": ph["gemm_as_only"],
+               "kernel": "k_gemm A.S pass + fitness gather alone (no store), back to back"}
+    return roof, roof_as, f_as, f_pen
+
+
+def oracle_parity(s, case, A, torch):
+    """One step of the timed workload from the solver's current W and t with each penalty
+    route forced (1 dense bf16 pass, 2 sparse FP32 rows), against the FP64 oracle's iteration
+    from the same W: norm-wise error of W' (max |diff| / max |ref|) and exactness of the
+    colours and conflict counts after the step.  The solver's W, t and options are restored."""
+    import oracle
+    d = dict(case.params())
+    for key in ("eta", "rho", "alpha", "lam", "beta", "mu", "nu", "momentum"):
+        d[key] = float(np.float32(d[key]))
+    p = oracle.Params.from_dict(d)
+    keep = s.options()
+    W_saved = s.W[0].clone()
+    t = s.get_t()
+    out = {"t": t}
+    for name, pen in (("dense_bf16_penalty", 1), ("sparse_fp32_penalty", 2)):
+        s.set_options(penalty=pen)
+        W0 = s.W[0].cpu().numpy()
+        ref = oracle.iteration(p, t, A, W0, want_grads=False)
+        done, _ = s.step(1)
+        W1 = s.W[0].cpu().numpy()
+        err = float(np.abs(W1.astype(np.float64) - ref.W).max() / np.abs(ref.W).max())
+        c, fc, _ = s.conflicts(0)
+        c_ref = oracle.colors(W1)
+        out[name] = {"W_err_normwise": err, "updated": done == 1 and ref.status == 0,
+                     "colors_exact": bool(np.array_equal(c.cpu().numpy(), c_ref)),
+                     "fcolor_exact": bool(np.array_equal(fc.cpu().numpy(), oracle.fcolor(A, c_ref)))}
+        s.W[0].copy_(W_saved)
+        s.set_t(t)
+    s.set_options(**{k: keep[k] for k in ("penalty",)})
+    torch.cuda.synchronize()
+    return out
+
+
+def plain_fp32_rate(case, A, W0, torch, pk, steps):
+    """Population-iterations/s of the plain schedule (fused = 0: argmax, class sizes, S, dense
+    penalty operand, contraction storing G, fitness, update as separate kernels) with every
+    operand in FP32, on the same graph and initial weights, replayed from a hipGraph."""
+    import copy
+    c = copy.copy(case)
+    c.precision = tcolgen.FP32
+    dev = torch.device("cuda:0")
+    Wt = torch.from_numpy(W0).to(dev)
+    sp = pk.Solver([(torch.from_numpy(A).to(dev), Wt)], [pk.Params.from_dict(c.params())])
+    sp.set_options(fused=0, use_graph=1)
+    sp.step(3)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    done, _ = sp.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    assert done == steps
+    ms = e0.elapsed_time(e1)
+    sp.close()
+    return {"value": case.D * steps / (ms / 1e3), "ms_per_step": ms / steps, "steps": steps,
+            "schedule": "plain (fused = 0), FP32 operands, hipGraph replay, same graph and W0"}
 
 
 if __name__ == "__main__":

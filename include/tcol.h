@@ -85,7 +85,7 @@ enum { TCOL_FP32 = 0, TCOL_BF16 = 1, TCOL_FP8 = 2, TCOL_FP4 = 3 };
  * rho in {1,2,10,100,200}, alpha 2.5, lambda 1e-5, beta 1.2, mu 1e-6 (GCP) or 0
  * (ECP), nu 0 (GCP) or 1e-5 (ECP)). */
 typedef struct {
-    int32_t problem;        /* TCOL_KCOL or TCOL_ECP */
+    int32_t problem;        /* TCOL_KCOL, TCOL_ECP, TCOL_KPART, TCOL_BKPART or TCOL_MSCP */
     int32_t precision;      /* TCOL_FP32, TCOL_BF16, TCOL_FP8 or TCOL_FP4 */
     int32_t n, k, D;        /* vertices (1..32768), colours (1..4096), members (1..1024) */
     float eta, rho;         /* learning rate > 0; smoothing divisor >= 1 */
@@ -211,13 +211,32 @@ tcol_status tcol_get_t(tcol_ctx *ctx, int32_t g, int64_t *t);
 tcol_status tcol_set_t(tcol_ctx *ctx, int32_t g, int64_t t);
 
 /* Clear the "stopped" state of every graph so tcol_step continues (for
- * example after the caller changed k or re-initialised W). */
+ * example after the caller changed k or re-initialised W, or after a
+ * TCOL_ENONFINITE stop once the caller has restored finite weights). */
 tcol_status tcol_reset(tcol_ctx *ctx);
 
-/* Measure each candidate GEMM tile shape for this context's graphs on its
- * stream (a few timed steps each, W restored afterwards) and keep the fastest
- * in the options.  *best_bm / *best_ntw (host, may be NULL) receive it.
- * Errors: TCOL_EHIP. */
+/* Iterations of graph g evaluated since tcol_init (every tcol_step iteration that reached the
+ * fitness, the stopping one included; tcol_profile's iterations count too), split by how
+ * the penalty product of eq. (17) was taken (Section 3.8.2):
+ *   counts[0]  lambda t = mu t = 0, no penalty product (t = 0, or lambda = mu = 0);
+ *   counts[1]  the dense operand pass of the contraction (the plain schedule always);
+ *   counts[2]  the sparse rows (tcol_options.penalty).
+ * counts: host array of 3 int64.  Synchronises the stream.  Errors: TCOL_EINVAL, TCOL_EHIP. */
+tcol_status tcol_get_counters(tcol_ctx *ctx, int32_t g, int64_t *counts);
+
+/* Autotuner of the step for this context's graphs: times a few steps of every
+ * candidate on the context's stream and keeps the fastest in the options.  The
+ * candidates are every instantiated tile shape under the plain schedule (when
+ * the options ask for it, fused = 0), else under the fast and the epilogue
+ * schedules, each with the per-iteration penalty choice and the two fixed
+ * penalty routes (tcol_options.penalty 0, 1, 2).  W and t are restored after
+ * every candidate (the trial iterations count in tcol_get_counters).  The
+ * result is cached for the process per device and per context signature (n, k,
+ * D, precision, problem and momentum of every graph, and whether the plain
+ * schedule was asked for): a later call on a context with the same signature
+ * applies the cached options without timing.  *best_bm / *best_ntw (host, may
+ * be NULL) receive the chosen tile.  Allocates a device copy of each W for the
+ * duration of the call.  Errors: TCOL_EINVAL, TCOL_ENOMEM, TCOL_EHIP. */
 tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
 
 /* Measurement utility.  Runs `steps` iterations of every graph eagerly (no
@@ -233,9 +252,12 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * launches back to back on the operands of the last iteration (one event pair,
  * so launch gaps do not count), with the dense penalty pass unless penalty = 2.  When as_only is non-zero it then also times
  * `steps` back-to-back launches of the contraction restricted to A.S with the
- * gather (W unchanged) into ms[8]; otherwise ms[8] = 0.  Synchronises the stream.
+ * gather (W unchanged) into ms[8], and `steps` launches of A.S with the gather
+ * and the store of G (the form the contraction takes on the fast and plain
+ * schedules in iterations without the dense penalty pass) into ms[9];
+ * otherwise ms[8] = ms[9] = 0.  Synchronises the stream.
  * Errors: TCOL_EINVAL, TCOL_EHIP. */
-#define TCOL_NPHASES 9
+#define TCOL_NPHASES 10
 tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *ms);
 
 /* Measurement utility, no context: the achievable MFMA throughput of the current

@@ -175,6 +175,12 @@ class Solver:
     def reset(self) -> None:
         _lib.check(self._lib.tcol_reset(self._ctx), "tcol_reset")
 
+    def counters(self, g: int = 0) -> dict:
+        """Iterations of graph g evaluated since init, by the route of the penalty product."""
+        out = (ctypes.c_int64 * 3)()
+        _lib.check(self._lib.tcol_get_counters(self._ctx, g, out), "tcol_get_counters")
+        return {"no_penalty": out[0], "dense": out[1], "sparse": out[2]}
+
     def profile(self, steps: int, as_only: bool = False) -> dict:
         """Average ms per iteration of each kernel phase (eager launches, HIP events)."""
         ms = (ctypes.c_float * _lib.NPHASES)()

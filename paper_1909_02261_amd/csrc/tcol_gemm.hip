@@ -536,7 +536,8 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     // epilogue, added to G after the fast path's store); the plain path
     // (passes bit 3) always takes the dense pass
     const bool sparse_pen = pen && d.psparse && !st->pdense && !(passes & 8);
-    const bool dense_pen = pen && !sparse_pen;
+    // passes bit 4: no penalty pass (the form the launch takes in iterations without one)
+    const bool dense_pen = pen && !sparse_pen && !(passes & 16);
     // partitioning: the fitness term is -A.S, and with the operand built over D - Mt the
     // penalty product is negated as well
     const float sgn = prob_partition(d.problem) ? -1.0f : 1.0f;

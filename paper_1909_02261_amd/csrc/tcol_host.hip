@@ -26,6 +26,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 using namespace tcol;
@@ -396,7 +399,7 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
     HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, 0, -1, nullptr, s));
     HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 15, 0, s));
-    HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+    HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagPlainPen, -1, s));
     HIPRET(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
     HIPRET(launch_advance(c->ddesc, c->G, s));
     return hipSuccess;
@@ -862,6 +865,17 @@ tcol_status tcol_set_t(tcol_ctx* c, int32_t g, int64_t t) {
     return TCOL_OK;
 }
 
+tcol_status tcol_get_counters(tcol_ctx* c, int32_t g, int64_t* counts) {
+    if (!c || g < 0 || g >= c->G || !counts) return TCOL_EINVAL;
+    GraphState st;
+    HIPCHK(hipMemcpyAsync(&st, c->dstate + g, sizeof(GraphState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    counts[0] = st.it_nopen;
+    counts[1] = st.it_dense;
+    counts[2] = st.it_sparse;
+    return TCOL_OK;
+}
+
 tcol_status tcol_reset(tcol_ctx* c) {
     if (!c) return TCOL_EINVAL;
     HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
@@ -902,7 +916,7 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(hipEventRecord(ev[5], s));
         if (path == 1) HIPCHK(enqueue_sparse_add(c, false, s));
         HIPCHK(hipEventRecord(ev[6], s));
-        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : 0, -1, s));
+        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : (path == 0 ? kFlagPlainPen : 0), -1, s));
         HIPCHK(hipEventRecord(ev[7], s));
         if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
         HIPCHK(hipEventRecord(ev[8], s));
@@ -944,28 +958,75 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     }
     tcol_status st = settle(c);
     if (st != TCOL_OK) return st;
-    ms[8] = 0.0f;
+    ms[8] = ms[9] = 0.0f;
     if (as_only) {
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
         HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
-        HIPCHK(hipEventRecord(ev[0], s));
-        for (int it = 0; it < steps; ++it) HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1, 0, s));
-        HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(launch_state(c->ddesc, c->G, 4, -1, 0, s));
-        HIPCHK(hipEventSynchronize(ev[1]));
-        float x = 0;
-        HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
-        ms[8] = x / steps;
+        // A.S with the gather alone, then with the G store too (the separate-kernel form of
+        // an iteration without the dense penalty pass; the store is idempotent)
+        const int forms[2] = {1, 1 | 4 | 16};
+        for (int f = 0; f < 2; ++f) {
+            HIPCHK(hipEventRecord(ev[0], s));
+            for (int it = 0; it < steps; ++it)
+                HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, forms[f], 0, s));
+            HIPCHK(hipEventRecord(ev[1], s));
+            HIPCHK(launch_state(c->ddesc, c->G, 4, -1, 0, s));
+            HIPCHK(hipEventSynchronize(ev[1]));
+            float x = 0;
+            HIPCHK(hipEventElapsedTime(&x, ev[0], ev[1]));
+            ms[8 + f] = x / steps;
+        }
     }
     for (int i = 0; i < NE; ++i) hipEventDestroy(ev[i]);
     return TCOL_OK;
 }
 
-// Time a few steps of each candidate tile shape (and penalty mode) and keep the fastest.
-// The weights and counters are restored after every candidate.
+}  // extern "C"
+
+// Autotuner results of this process, per device and per context signature (the shapes,
+// precisions and problems of its graphs and the requested step schedule): a context with
+// the same signature on the same device takes the stored options without timing again.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, tcol_options> g_tune_cache;
+
+std::string tune_key(const tcol_ctx* c) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::string k = "dev" + std::to_string(dev) + "/f" + std::to_string(c->opt.fused ? 1 : 0);
+    for (const auto& p : c->params)
+        k += "/" + std::to_string(p.n) + "x" + std::to_string(p.k) + "x" + std::to_string(p.D) + "p" +
+             std::to_string(p.precision) + "q" + std::to_string(p.problem) + (p.momentum != 0.0f ? "m" : "");
+    return k;
+}
+}  // namespace
+
+extern "C" {
+
+// Time a few steps of each candidate (step schedule, tile shape, penalty mode) and keep the
+// fastest.  The weights and counters are restored after every candidate.
 tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
     if (!c) return TCOL_EINVAL;
+    const std::string key = tune_key(c);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const tcol_options keep = c->opt;
+            c->opt = it->second;
+            tcol_status s = rebuild_schedule(c);
+            if (s != TCOL_OK) {
+                c->opt = keep;
+                rebuild_schedule(c);
+                return s;
+            }
+            const GemmShape& sh = path_of(c) == 2 ? c->fshape : c->shape;
+            if (best_bm) *best_bm = sh.bm;
+            if (best_ntw) *best_ntw = sh.ntw;
+            return TCOL_OK;
+        }
+    }
     // backups of W and t
     std::vector<float*> backup(c->G, nullptr);
     std::vector<long long> t0(c->G);
@@ -1015,7 +1076,8 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
                 cands.push_back(o);
                 continue;
             }
-            for (int pen : {1, 2}) {
+            // the per-iteration choice (0) and the two fixed routes
+            for (int pen : {0, 1, 2}) {
                 o.penalty = pen;
                 cands.push_back(o);
             }
@@ -1048,6 +1110,10 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
     HIPCHK(hipStreamSynchronize(c->stream));
     for (auto b : backup) hipFree(b);
     if (s != TCOL_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = c->opt;
+    }
     const GemmShape& sh = path_of(c) == 2 ? c->fshape : c->shape;
     if (best_bm) *best_bm = sh.bm;
     if (best_ntw) *best_ntw = sh.ntw;

@@ -60,6 +60,9 @@ struct GraphState {
     int pdense;         // sparse penalty graphs: this iteration takes the dense operand pass
     int prep_ticket;    // member blocks of the class-size kernel done this iteration (the
                         // last one takes the penalty choice and sets it back to 0)
+    // iterations evaluated since init, by the route of their penalty product: none (lambda t =
+    // mu t = 0), the dense operand pass, the sparse rows (counted by the fitness kernel)
+    long long it_nopen, it_dense, it_sparse;
 };
 
 // per-graph descriptor, uploaded once at init
@@ -129,6 +132,7 @@ enum : int {
     kFlagReport = 8,      // fitness kernel only reports (no stop, no state change)
     kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty this iteration
     kFlagFused = 32,      // fitness kernel of the fused path: accept the update by flipping buffers
+    kFlagPlainPen = 64,   // fitness kernel of the plain path: the penalty took the dense pass
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

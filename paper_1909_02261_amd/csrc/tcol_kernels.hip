@@ -175,7 +175,10 @@ __device__ inline int penalty_choice(const GraphDev& d, long long w) {
 // and n entries.
 // block b of the S^T expansion (the expansion kernel's body; the fast path runs it in
 // extra blocks of the class-size launch, since both read only the colours)
-__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate);
+// (adv: the launch also ends the previous iteration, so a pending non-finite update counts as
+// a stop)
+__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
+                             int adv);
 
 // end of an iteration for a running graph: t <- t + 1, and a non-finite weight from the
 // update stops the graph with an error
@@ -195,17 +198,24 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     __shared__ int part[257];
     const int mem = blockIdx.x;
     if (mem >= total_mem) {
-        // blocks past the members: the expansion of the current colours (gate 1)
-        if (mem - total_mem < ex_blocks) expand_block(gd, G, mem - total_mem, honor_stop, next, 1);
+        // blocks past the members: the expansion of the current colours (gate 1), with the
+        // same stop decision as the member blocks
+        if (mem - total_mem < ex_blocks) expand_block(gd, G, mem - total_mem, honor_stop, next, 1, advance_prev);
         return;
     }
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
     GraphState* st = d.st;
+    // Whether the graph is stopped for this iteration, read before anything in this launch
+    // writes the state: advance_graph below can only turn `stopped` on, and exactly when
+    // next_bad is set, so every thread of every member block (and of the expansion blocks)
+    // takes the same decision whether it reads `stopped` before or after that write.  A
+    // graph's member blocks therefore all run or all return, and the ticket of the penalty
+    // choice below counts all of them.
+    const bool stop_now = honor_stop && (st->stopped || (advance_prev && st->next_bad));
     // the previous iteration's end (its own launch otherwise), by the graph's first member
-    // block: nothing in this launch reads t, and a stop it raises only idles the rest of
-    // the iteration
+    // block: nothing in this launch reads t
     if (advance_prev && mem == d.mem_begin && threadIdx.x == 0) advance_graph(st);
-    if (honor_stop && st->stopped) return;
+    if (stop_now) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     const int m = mem - d.mem_begin;
     const int k = d.k, n = d.n, tid = threadIdx.x;
@@ -684,10 +694,11 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
 // (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
 // graphs the bf16 copy used by the penalty pass is written as well (the fp4 penalty
 // pass reads the fp4 operand itself).
-__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate) {
+__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
+                             int adv) {
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ex_begin; })];
     GraphState* st = d.st;
-    if (honor_stop && st->stopped) return;
+    if (honor_stop && (st->stopped || (adv && st->next_bad))) return;
     const int p = next ? st->pS ^ 1 : st->pS;
     // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
     const bool want_sp2 = prec_split(d.precision) && (!gate || !d.psparse || st->pdense);
@@ -765,7 +776,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
                                                 int honor_stop, int next, int gate) {
     const int b = blockIdx.x;
     if (b >= total_blocks) return;
-    expand_block(gd, G, b, honor_stop, next, gate);
+    expand_block(gd, G, b, honor_stop, next, gate, 0);
 }
 
 // ------------------------------------------------------------ step 3 -----------
@@ -989,6 +1000,13 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
     }
     __syncthreads();
     if (flags & kFlagReport) return;
+    if (threadIdx.x == 0) {
+        // the route this iteration's penalty product took (the contraction and the sparse
+        // rows read the same state)
+        if (!pen_active(d, st)) st->it_nopen += 1;
+        else if ((flags & kFlagPlainPen) || !d.psparse || st->pdense) st->it_dense += 1;
+        else st->it_sparse += 1;
+    }
     const int ld = best == 0x7FFFFFFF ? -1 : best;
     const bool stop = ld >= 0 && d.stop_on_legal;
     if (stop) {
@@ -1281,8 +1299,9 @@ __global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_on
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G || (g_only >= 0 && g != g_only)) return;
     GraphState* st = gd[g].st;
-    if (op == 0) {            // reset run state (keeps t)
+    if (op == 0) {            // reset run state (keeps t and the route counters)
         st->stopped = 0; st->error = 0; st->legal_d = -1; st->steps_done = 0; st->next_bad = 0;
+        st->prep_ticket = 0;
     } else if (op == 1) {     // set t
         st->t = t;
     } else if (op == 2) {     // clear steps counter only

@@ -50,7 +50,8 @@ hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long
 // MFMA contraction G = A.S (+ P.S) with the conflict gather.
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
 //   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
-//           bit 3 = dense penalty operand even for graphs on the sparse penalty
+//           bit 3 = dense penalty operand even for graphs on the sparse penalty, bit 4 = no
+//           penalty pass at all
 struct GemmShape {
     int prec, bm, ntw, mode;
 };
