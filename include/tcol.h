@@ -271,6 +271,28 @@ tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *m
  * TCOL_EHIP. */
 tcol_status tcol_mfma_peak(int32_t precision, int32_t iters, double *tflops);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tcol_conflicts without a context.  Steps
+ * 1-2 for one graph with parameters p (p->problem selects the fitness; p->precision is
+ * ignored: the contraction A.S runs in fp4 operands, exact for 0/1 in every format):
+ *   A_dev       n x n uint8 row-major 0/1, symmetric, zero diagonal (not checked here:
+ *               nonzero entries count as 1);
+ *   W_dev       D x n x k fp32 weights (read only);
+ *   colors_dev, f_main_dev, f_sec_dev   as tcol_conflicts (each may be NULL).
+ * Every intermediate lives in one static device array of TCOL_NOALLOC_SCRATCH_BYTES that
+ * each device holds from the library's load until the process ends; the call allocates
+ * nothing, launches kernels only on `stream` (hipStream_t as void*, NULL = default) and
+ * does not synchronise, so it may be captured into a graph.  Calls on the same device share
+ * that array and keep its last contents: calls that may overlap on one device (different
+ * streams, or host threads) race and must be ordered by the caller.  The outputs equal
+ * tcol_conflicts' for the same A, W and problem.
+ * Errors: TCOL_EINVAL (NULL A_dev or W_dev, bad parameters), TCOL_ESHAPE, TCOL_ENOMEM (the
+ * graph needs more scratch than the array holds, about n = 4000 with D k = 8960 at most),
+ * TCOL_EHIP. */
+#define TCOL_NOALLOC_SCRATCH_BYTES (32u << 20)
+tcol_status tcol_conflicts_noalloc(const tcol_graph_params *p, const uint8_t *A_dev, const float *W_dev,
+                                   int16_t *colors_dev, int64_t *f_main_dev, int64_t *f_sec_dev, void *stream);
+
 /* Release the context (and the workspace it allocated).  NULL is ignored. */
 void tcol_destroy(tcol_ctx *ctx);
 

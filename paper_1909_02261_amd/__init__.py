@@ -14,7 +14,8 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, BKPART, ECP, FP4, FP8, FP32, KCOL, KPART, MSCP, TcolError
 
-__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "mfma_peak", "KCOL", "ECP", "KPART", "BKPART", "MSCP",
+__all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "mfma_peak", "conflicts_noalloc",
+           "KCOL", "ECP", "KPART", "BKPART", "MSCP",
            "FP32", "BF16", "FP8", "FP4", "TcolError"]
 
 
@@ -200,6 +201,31 @@ def mfma_peak(precision: int, iters: int = 4000) -> float:
     out = ctypes.c_double(0.0)
     _lib.check(lib.tcol_mfma_peak(int(precision), int(iters), ctypes.byref(out)), "tcol_mfma_peak")
     return out.value
+
+
+def conflicts_noalloc(A, W, params: Params, colors=None, f_main=None, f_sec=None, stream=None):
+    """tcol_conflicts_noalloc: colours and fitness of the population W (float32 [D, n, k]) on the
+    graph A (uint8 [n, n]) with no context and no device allocation inside the library.  The
+    output tensors (int16 [D, n], int64 [D], int64 [D]) are the caller's; they are created here
+    when not given.  Asynchronous on `stream`."""
+    torch = _torch()
+    p = params
+    if A.dtype != torch.uint8 or tuple(A.shape) != (p.n, p.n) or not A.is_contiguous() or not A.is_cuda:
+        raise ValueError(f"A must be a contiguous uint8 device tensor [{p.n}, {p.n}]")
+    if W.dtype != torch.float32 or tuple(W.shape) != (p.D, p.n, p.k) or not W.is_contiguous() or not W.is_cuda:
+        raise ValueError(f"W must be a contiguous float32 device tensor [{p.D}, {p.n}, {p.k}]")
+    if colors is None:
+        colors = torch.empty((p.D, p.n), dtype=torch.int16, device=W.device)
+    if f_main is None:
+        f_main = torch.empty(p.D, dtype=torch.int64, device=W.device)
+    if f_sec is None:
+        f_sec = torch.empty(p.D, dtype=torch.int64, device=W.device)
+    lib = _lib.load()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    cp = p.c_struct()
+    _lib.check(lib.tcol_conflicts_noalloc(ctypes.byref(cp), _ptr(A), _ptr(W), _ptr(colors), _ptr(f_main),
+                                          _ptr(f_sec), ctypes.c_void_p(st.cuda_stream)), "tcol_conflicts_noalloc")
+    return colors, f_main, f_sec
 
 
 def init_weights(W, seed: int, sigma0: float = 0.01, stream=None) -> None:

@@ -48,7 +48,7 @@ class TcolError(RuntimeError):
 EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_options",
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
            "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
-           "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters"]
+           "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters", "tcol_conflicts_noalloc"]
 NPHASES = 10
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only",
           "gemm_as_store"]
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_set_t.argtypes = [P, i32, i64]
     lib.tcol_reset.argtypes = [P]
     lib.tcol_get_counters.argtypes = [P, i32, ctypes.POINTER(i64)]
+    lib.tcol_conflicts_noalloc.argtypes = [ctypes.POINTER(GraphParams), P, P, P, P, P, P]
     lib.tcol_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.tcol_profile.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_float)]
     lib.tcol_mfma_peak.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double)]

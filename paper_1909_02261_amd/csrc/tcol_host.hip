@@ -1122,6 +1122,148 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
 
 }  // extern "C"
 
+// ------------------------------------------------ allocation-free conflicts -----
+//
+// tcol_conflicts_noalloc keeps every intermediate in `scratch`, a file-scope device array of
+// kNoAllocScratch bytes that each device holds from the library's load until the process
+// ends.  In host code `scratch` names a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that
+// address is handed to kernels.
+
+namespace {
+
+constexpr size_t kNoAllocScratch = TCOL_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// address of this device's copy of `scratch`, and the one-time set-up of the kernels the call
+// launches (LDS attributes), on first use per device
+tcol_status noalloc_scratch(int dev, uint8_t** out) {
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return TCOL_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fprintf(stderr, "libtcol: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+                    hipGetErrorString(e));
+            return TCOL_EHIP;
+        }
+        for (int ntw : {4, 6}) {
+            const GemmShape sh{kPrecFP4, ntw == 6 ? 128 : 64, ntw, 0};
+            if (gemm_prepare(sh) != hipSuccess) return TCOL_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t*)g_scratch_ptr[dev];
+    return TCOL_OK;
+}
+
+// the conflict pass's buffers inside the scratch array (A.S in fp4 operands, exact for 0/1)
+struct NoAllocLayout {
+    size_t desc, state, ones, aop, sop, c, V, cT, f2, fcol, feq, f, total;
+    int n_pad, rows_S, cs, cTs;
+};
+
+NoAllocLayout noalloc_layout(const tcol_graph_params& p) {
+    NoAllocLayout L{};
+    L.n_pad = round_up(p.n, kPadN);
+    L.rows_S = round_up(p.D * p.k, 16) + kSRowSlack;
+    L.cs = round_up(p.n, 64);
+    L.cTs = round_up(p.D, 8);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o += align_up(bytes); return at; };
+    L.desc = take(sizeof(GraphDev));
+    L.state = take(sizeof(GraphState));
+    L.ones = take(16);
+    L.aop = take((size_t)L.n_pad * op_row_bytes(kPrecFP4, L.n_pad));
+    L.sop = take((size_t)L.rows_S * op_row_bytes(kPrecFP4, L.n_pad));
+    L.c = take(sizeof(int16_t) * ((size_t)p.D * L.cs + 64));
+    L.V = take(sizeof(int32_t) * (size_t)p.D * p.k);
+    L.cT = take(sizeof(int16_t) * (size_t)L.cTs * p.n);
+    L.f2 = take(sizeof(int32_t) * p.D);
+    L.fcol = take(sizeof(int64_t) * p.D);
+    L.feq = take(sizeof(int64_t) * p.D);
+    L.f = take(sizeof(int64_t) * p.D);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" tcol_status tcol_conflicts_noalloc(const tcol_graph_params* p, const uint8_t* A_dev, const float* W_dev,
+                                              int16_t* colors_dev, int64_t* f_main_dev, int64_t* f_sec_dev,
+                                              void* stream) {
+    if (!p || !A_dev || !W_dev) return TCOL_EINVAL;
+    const tcol_status ps = check_params(*p);
+    if (ps != TCOL_OK) return ps;
+    const NoAllocLayout L = noalloc_layout(*p);
+    if (L.total > kNoAllocScratch) {
+        fprintf(stderr, "libtcol: tcol_conflicts_noalloc: n = %d, k = %d, D = %d needs %zu bytes of scratch, "
+                "more than its fixed %zu\n", p->n, p->k, p->D, L.total, kNoAllocScratch);
+        return TCOL_ENOMEM;
+    }
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    uint8_t* base = nullptr;
+    const tcol_status ss = noalloc_scratch(dev, &base);
+    if (ss != TCOL_OK) return ss;
+    hipStream_t s = (hipStream_t)stream;
+
+    GraphDev d;
+    memset(&d, 0, sizeof(d));
+    d.n = p->n;
+    d.k = p->k;
+    d.D = p->D;
+    d.n_pad = L.n_pad;
+    d.cs = L.cs;
+    d.ncols = p->D * p->k;
+    d.rows_S = L.rows_S;
+    d.problem = p->problem;
+    d.precision = kPrecFP4;
+    d.c1 = p->n / p->k;
+    d.c2 = (p->n % p->k == 0) ? p->n / p->k : p->n / p->k + 1;
+    d.ones_dev = (const unsigned long long*)(base + L.ones + 8);
+    d.W[0] = const_cast<float*>(W_dev);
+    d.Aop = base + L.aop;
+    d.Sop[0] = base + L.sop;
+    d.c[0] = (int16_t*)(base + L.c);
+    d.V[0] = (int32_t*)(base + L.V);
+    d.cT = (int16_t*)(base + L.cT);
+    d.cTs = L.cTs;
+    d.f2 = (int32_t*)(base + L.f2);
+    d.fcol = (int64_t*)(base + L.fcol);
+    d.feq = (int64_t*)(base + L.feq);
+    d.f = (int64_t*)(base + L.f);
+    d.st = (GraphState*)(base + L.state);
+    const int total_rows = p->D * p->n;
+    const long long items = (long long)p->D * p->k * (L.n_pad / 16);
+    d.ex_cblocks = (int)((items + 255) / 256);
+    const GemmShape sh{kPrecFP4, L.n_pad >= 2048 ? 128 : 64, L.n_pad >= 2048 ? 6 : 4, 0};
+    d.gm_tm[0] = L.n_pad / sh.bm;
+    d.gm_tn[0] = ceil_div(d.ncols, gemm_bn(sh.ntw));
+    GraphDev* gd = (GraphDev*)(base + L.desc);
+
+    // the previous call's contents: everything from the state on starts at zero (operand
+    // padding, the slack rows of S^T, the conflict accumulators, the edge count)
+    HIPCHK(launch_zero(base + L.state, L.total - L.state, s));
+    HIPCHK(launch_put_desc(d, gd, d.st, s));
+    // A is packed without its check (its flag word is ignored): the caller vouches for it
+    HIPCHK(launch_pack_graph(A_dev, p->n, L.n_pad, kPrecFP4, nullptr, d.Aop, (int*)(base + L.ones),
+                             (unsigned long long*)(base + L.ones + 8), s));
+    HIPCHK(launch_colors(gd, 1, total_rows, 0, s));
+    HIPCHK(launch_prep(gd, 1, p->D, prep_lds(p->k, p->n, 0), 0, 0, 0, 0, 0, s));
+    HIPCHK(launch_expand(gd, 1, d.ex_cblocks, 0, 0, 0, s));
+    HIPCHK(launch_gemm(sh, gd, 1, d.gm_tm[0] * d.gm_tn[0], 0, 1, 0, s));
+    HIPCHK(launch_fitness(gd, 1, 0, kFlagReport, -1, s));
+    HIPCHK(launch_copy_report(gd, 0, colors_dev, f_main_dev, f_sec_dev, s));
+    return TCOL_OK;
+}
+
 // ------------------------------------------------------------- descent driver -
 
 tcol_status tcol_init_weights(float* W_dev, int64_t count, uint64_t seed, double sigma0, void* stream) {

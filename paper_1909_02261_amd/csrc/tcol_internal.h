@@ -77,6 +77,8 @@ struct GraphDev {
     float eta, rho, nu, lambda, mu;
     float momentum;           // heavy-ball coefficient (0: plain step)
     long long edges;          // |E|
+    const unsigned long long* ones_dev;   // when set: the number of ones of A (2 |E|) on the device,
+                                          // read in place of `edges`
     // look-up tables over m = 0..D, with x = m (colouring) or D - m (partitioning)
     const float* lut_pen;     // 2 alpha lambda x^(alpha-1)   (0 at x = 0)
     const float* lut_bon;     // 2 beta mu x^(beta-1)         (0 at x = 0)

@@ -73,8 +73,8 @@ __device__ inline u32x4n gload16(const void* p) { return *(const __attribute__((
 // ------------------------------------------------------ validation, packing --
 
 // Checks A (n x n, row-major 0/1, symmetric, zero diagonal) and writes the
-// zero-padded byte copy A8 and the operand copy Aop ([n_pad][n_pad]; in fp4 two
-// entries per byte, the lower column in the low nibble, 1.0 = 0x2).
+// zero-padded byte copy A8 (unless A8 is null) and the operand copy Aop ([n_pad][n_pad];
+// in fp4 two entries per byte, the lower column in the low nibble, 1.0 = 0x2).
 __global__ __launch_bounds__(256) void k_pack_graph(const uint8_t* __restrict__ A, int n, int n_pad, int prec,
                                                     uint8_t* __restrict__ A8, void* __restrict__ Aop,
                                                     int* __restrict__ bad, unsigned long long* __restrict__ ones) {
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_pack_graph(const uint8_t* __restrict__ 
             a = a ? 1 : 0;
         }
         count += a;
-        A8[e] = a;
+        if (A8) A8[e] = a;
         if (prec == kPrecFP32)
             ((float*)Aop)[e] = a ? 1.0f : 0.0f;
         else if (prec == kPrecBF16)
@@ -990,7 +990,7 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
     const bool added = prob_added(d.problem);
     for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
         long long fc = d.f2[m] / 2;
-        if (prob_partition(d.problem)) fc = d.edges - fc;
+        if (prob_partition(d.problem)) fc = (d.ones_dev ? (long long)(*d.ones_dev / 2) : d.edges) - fc;
         const long long fe = added ? d.feq[m] : 0;
         d.fcol[m] = fc;
         d.feq[m] = fe;
@@ -1358,6 +1358,24 @@ __global__ __launch_bounds__(256) void k_init_weights(float* __restrict__ W, lon
     if (2 * b + 1 < count) W[2 * b + 1] = (float)(r * sin(th) * sigma0);
 }
 
+// ------------------------------------------- descriptors from kernel arguments --
+
+// Writes one graph's descriptor and a fresh state (the values travel as kernel arguments,
+// so a captured launch carries them; no host buffer has to outlive the call).
+__global__ void k_put_desc(GraphDev d, GraphDev* __restrict__ gd, GraphState* __restrict__ st) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    *gd = d;
+    GraphState s{};
+    s.legal_d = -1;
+    *st = s;
+}
+
+// p[0 .. words) = 0 (16-byte stores; p 16-byte aligned)
+__global__ __launch_bounds__(256) void k_zero16(uint4* __restrict__ p, size_t words) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += (size_t)gridDim.x * blockDim.x)
+        p[e] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // ------------------------------------------------------------- launchers -----
 
 #define TCOL_LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
@@ -1524,6 +1542,22 @@ hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipSt
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_copy_report, dim3(256), dim3(256), 0, s, gd, g, colors, fcol, feq);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_put_desc(const GraphDev& d, GraphDev* gd, GraphState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, gd, st);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)p & 15) || (bytes & 15)) return hipErrorInvalidValue;
+    const size_t words = bytes / 16;
+    const int blocks = (int)std::min<size_t>((words + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, s, (uint4*)p, words);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -137,3 +137,16 @@ def test_mfma_peak_rejects_bad_arguments_without_gpu(lib):
     assert lib.tcol_mfma_peak(3, 0, ctypes.byref(out)) == -1
     assert lib.tcol_mfma_peak(4, 10, ctypes.byref(out)) == -1
     assert lib.tcol_mfma_peak(-1, 10, ctypes.byref(out)) == -1
+
+
+def test_noalloc_rejects_what_its_scratch_cannot_hold(lib):
+    """tcol_conflicts_noalloc checks its arguments and the size its fixed scratch array holds
+    before touching any device (the pointers below are never dereferenced)."""
+    dummy = ctypes.c_void_p(16)
+    big = params(n=8000, k=500, D=64)
+    assert lib.tcol_conflicts_noalloc(ctypes.byref(big), dummy, dummy, None, None, None, None) == -6
+    small = params()
+    assert lib.tcol_conflicts_noalloc(ctypes.byref(small), None, dummy, None, None, None, None) == -1
+    assert lib.tcol_conflicts_noalloc(None, dummy, dummy, None, None, None, None) == -1
+    bad = params(k=0)
+    assert lib.tcol_conflicts_noalloc(ctypes.byref(bad), dummy, dummy, None, None, None, None) == -2
