@@ -116,7 +116,7 @@ typedef struct {
     int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */
     int32_t tile_ntw;       /* GEMM 16-column subtiles per wave; the instantiated (tile_bm, tile_ntw)
                                pairs are (64,2) (64,4) (128,4) (128,6) (128,8) (64,9) (128,9)
-                               (256,4; 8 waves) */
+                               and, with 8 waves, (256,4) (256,6) */
     int32_t penalty;        /* fast and epilogue paths, penalty term P.S with
                                P = 2 alpha lambda t A o Mt^(alpha-1) - 2 beta mu t (J-A) o Mt^(beta-1)
                                (eq. 17, Section 3.8.2): 1 = dense operand pass on MFMA (operand

@@ -587,35 +587,41 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     const int dfirst = n0 / d.k;
 
     if (passes & 1) {
+        // gather 2 f_color: sum over rows i of (A.S_d)[i, c_d(i)].  Skipped (passes bit 6) in
+        // iterations whose penalty the sparse rows take, which read those entries of G anyway
+        // and gather them there, and never done with passes bit 7 (timing).  The colours of the
+        // tile's rows for its members go to LDS first (the stage buffers are free once every
+        // wave is past the barrier), in coalesced loads
+        const bool gather = !(passes & 128) && !((passes & 64) && sparse_pen);
         gemm_sweep<PREC, BM, NTW>(acc, (const uint8_t*)d.Aop + (size_t)m0 * ld,
                                   (const uint8_t*)d.Sop[pS] + (size_t)n0 * ld, ld, nst, lds);
-        // gather 2 f_color: sum over rows i of (A.S_d)[i, c_d(i)].  The colours of
-        // the tile's rows for its members go to LDS first (the stage buffers are
-        // free once every wave is past the barrier), in coalesced loads.
-        __syncthreads();
-        const int dlast = (ncol_end - 1) / k;
-        const int nm = dlast - dfirst + 1;
-        int16_t* ct = (int16_t*)lds;   // [nm][BM]
-        for (int e = tid; e < nm * BM; e += T::THREADS) {
-            const int dm = e / BM, r = e - dm * BM;
-            ct[e] = m0 + r < n ? colr[(size_t)(dfirst + dm) * cs + m0 + r] : (int16_t)-1;
-        }
-        for (int e = tid; e < nm; e += T::THREADS) f2l[e] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ri = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
-#pragma unroll
-                for (int nt = 0; nt < NTW; ++nt) {
-                    if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
-                        atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
-                }
+        if (gather) {
+            __syncthreads();
+            const int dlast = (ncol_end - 1) / k;
+            const int nm = dlast - dfirst + 1;
+            int16_t* ct = (int16_t*)lds;   // [nm][BM]
+            for (int e = tid; e < nm * BM; e += T::THREADS) {
+                const int dm = e / BM, r = e - dm * BM;
+                ct[e] = m0 + r < n ? colr[(size_t)(dfirst + dm) * cs + m0 + r] : (int16_t)-1;
             }
-        __syncthreads();
-        for (int e = tid; e < nm; e += T::THREADS)
-            if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);
+            // per element, through LDS counters of the tile's members
+            for (int e = tid; e < nm; e += T::THREADS) f2l[e] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ri = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt) {
+                        if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
+                            atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
+                    }
+                }
+            __syncthreads();
+            for (int e = tid; e < nm; e += T::THREADS)
+                if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);
+        }
     }
     if ((passes & 2) && dense_pen) {
         __syncthreads();
@@ -802,7 +808,7 @@ static hipError_t launch_one(const GraphDev* gd, int G, int total_tiles, int hon
 // instantiated tile shapes: (BM, NTW)
 #define TCOL_GEMM_SHAPES(X, PREC, MODE) \
     X(PREC, 64, 2, MODE) X(PREC, 64, 4, MODE) X(PREC, 128, 4, MODE) X(PREC, 128, 6, MODE) X(PREC, 128, 8, MODE) \
-    X(PREC, 64, 9, MODE) X(PREC, 128, 9, MODE) X(PREC, 256, 4, MODE)
+    X(PREC, 64, 9, MODE) X(PREC, 128, 9, MODE) X(PREC, 256, 4, MODE) X(PREC, 256, 6, MODE)
 
 #define TCOL_GEMM_CASE(PREC, BM, NTW, MODE)                                                             \
     if (s.prec == PREC && s.bm == BM && s.ntw == NTW && s.mode == MODE) {                               \

@@ -41,7 +41,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
     B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
-    B_V0, B_V1, B_G, B_F2, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_CINFO, B_SQ, B_VEL, B_COUNT
+    B_V0, B_V1, B_G, B_F2, B_F2P, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_CINFO, B_SQ, B_VEL, B_COUNT
 };
 
 struct Layout {
@@ -76,6 +76,7 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_V0] = sz[B_V1] = sizeof(int32_t) * (size_t)p.D * p.k;
     sz[B_G] = sizeof(float) * dnk;
     sz[B_F2] = sizeof(int32_t) * p.D;
+    sz[B_F2P] = sizeof(int32_t) * (size_t)p.D * kF2Slots;
     sz[B_FCOL] = sz[B_FEQ] = sz[B_F] = sizeof(int64_t) * p.D;
     sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
     sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
@@ -114,7 +115,7 @@ tcol_status check_params(const tcol_graph_params& p) {
 double pow0(double x, double p) { return x == 0.0 ? 0.0 : pow(x, p); }
 
 // shapes the contraction kernel is instantiated for: (rows per block, 16-column subtiles per wave)
-const int kShapes[][2] = {{64, 2}, {64, 4}, {128, 4}, {128, 6}, {128, 8}, {64, 9}, {128, 9}, {256, 4}};
+const int kShapes[][2] = {{64, 2}, {64, 4}, {128, 4}, {128, 6}, {128, 8}, {64, 9}, {128, 9}, {256, 4}, {256, 6}};
 
 }  // namespace
 
@@ -423,14 +424,13 @@ static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
     return hipSuccess;
 }
 
-// fast path: the sparse rows added to the contraction's G; with `fitness` the same launch
-// takes every graph's fitness too (one launch fewer), else the caller launches it
+// fast path: the sparse rows added to the contraction's G (they also gather f_color for the
+// graphs that take them, into slots the fitness folds); with `fitness` the fitness launch
+// follows, else the caller launches it
 static hipError_t enqueue_sparse_add(tcol_ctx* c, bool fitness, hipStream_t s) {
     if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1,
-                                     fitness ? c->G : 0, s));
-    else if (fitness)
-        HIPRET(launch_fitness(c->ddesc, c->G, 1, 0, -1, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1, 0, s));
+    if (fitness) HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFoldSparse, -1, s));
     return hipSuccess;
 }
 
@@ -454,7 +454,7 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, bool advance_prev, bool advance
                        merged ? c->total_ex : 0, advance_prev ? 1 : 0, s));
     HIPRET(enqueue_penalty(c, s));
     if (!merged) HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
-    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7, 0, s));
+    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7 | 64, 0, s));
     HIPRET(enqueue_sparse_add(c, true, s));
     HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
     if (advance_own) HIPRET(launch_advance(c->ddesc, c->G, s));
@@ -700,6 +700,7 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.V[1] = (int32_t*)(b + L.off[B_V1]);
         d.G = (float*)(b + L.off[B_G]);
         d.f2 = (int32_t*)(b + L.off[B_F2]);
+        d.f2p = (int32_t*)(b + L.off[B_F2P]);
         d.fcol = (int64_t*)(b + L.off[B_FCOL]);
         d.feq = (int64_t*)(b + L.off[B_FEQ]);
         d.f = (int64_t*)(b + L.off[B_F]);
@@ -912,11 +913,12 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         if (path == 2)
             HIPCHK(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
         else
-            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7, 0, s));
+            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7 | 64, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
         if (path == 1) HIPCHK(enqueue_sparse_add(c, false, s));
         HIPCHK(hipEventRecord(ev[6], s));
-        HIPCHK(launch_fitness(c->ddesc, c->G, 1, path == 2 ? kFlagFused : (path == 0 ? kFlagPlainPen : 0), -1, s));
+        HIPCHK(launch_fitness(c->ddesc, c->G, 1,
+                              path == 2 ? kFlagFused : (path == 0 ? kFlagPlainPen : kFlagFoldSparse), -1, s));
         HIPCHK(hipEventRecord(ev[7], s));
         if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
         HIPCHK(hipEventRecord(ev[8], s));
@@ -963,9 +965,10 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
         HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
-        // A.S with the gather alone, then with the G store too (the separate-kernel form of
-        // an iteration without the dense penalty pass; the store is idempotent)
-        const int forms[2] = {1, 1 | 4 | 16};
+        // A.S alone, then with the G store too (the form of an iteration without the dense
+        // penalty pass: on the fast path the sparse rows take the gather; the store is
+        // idempotent)
+        const int forms[2] = {1 | 128, 1 | 4 | 16 | 128};
         for (int f = 0; f < 2; ++f) {
             HIPCHK(hipEventRecord(ev[0], s));
             for (int it = 0; it < steps; ++it)

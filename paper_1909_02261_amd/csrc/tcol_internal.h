@@ -36,6 +36,8 @@ __host__ __device__ inline size_t op_row_bytes(int prec, int n_pad) {
                              : (prec == kPrecBF16 ? 2 * (size_t)n_pad : (prec == kPrecFP8 ? (size_t)n_pad : (size_t)n_pad / 2));
 }
 
+constexpr int kF2Slots = 64;
+
 constexpr int kMaxN = 32768;
 constexpr int kMaxK = 4096;
 constexpr int kMaxD = 1024;
@@ -96,6 +98,9 @@ struct GraphDev {
     float* G;                 // [D][n][k] gradient with respect to S (separate-kernel path)
     float* vel;               // [D][n][k] momentum velocity (null when momentum is 0)
     int32_t* f2;              // [D] 2 * f_color accumulated by the GEMM
+    int32_t* f2p;             // [D][kF2Slots] 2 * f_color gathered by the sparse rows, spread over
+                              // slots (row i adds to slot i mod kF2Slots) so their atomics do not
+                              // pile onto one address; folded into f2 by the rows' last block
     int64_t* fcol;            // [D] main fitness: f_color, or the cut for partitioning
     int64_t* feq;             // [D] added fitness: f_eq, the colour cost, or 0
     int64_t* f;               // [D] fcol + feq
@@ -135,6 +140,10 @@ enum : int {
     kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty this iteration
     kFlagFused = 32,      // fitness kernel of the fused path: accept the update by flipping buffers
     kFlagPlainPen = 64,   // fitness kernel of the plain path: the penalty took the dense pass
+    kFlagSkipSparse = 128,  // fitness blocks of the sparse-rows launch: leave the graphs whose
+                            // iteration takes the sparse rows to the fitness launch that follows
+    kFlagFoldSparse = 256,  // fitness kernel of the fast path: graphs whose iteration took the
+                            // sparse rows have their f_color in the rows' slots (f2p)
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

@@ -421,8 +421,10 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     if (b >= total_blocks) {
         // blocks past the rows: the fitness of graph b - total_blocks (its one shared word
         // in the dynamic LDS: the kernel has no static LDS, so the dynamic size may reach
-        // the full 160 KB)
-        if (b - total_blocks < fit_graphs) fitness_graph(gd, b - total_blocks, honor_stop, 0, (int*)ps_sh);
+        // the full 160 KB), unless (accumulate) this iteration's rows of that graph gather
+        // f_color, when the fitness follows in a launch of its own
+        if (b - total_blocks < fit_graphs)
+            fitness_graph(gd, b - total_blocks, honor_stop, accumulate ? kFlagSkipSparse : 0, (int*)ps_sh);
         return;
     }
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
@@ -630,6 +632,11 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     const double inv = ldexp(1.0, -sc);
     for (int d0 = 0; d0 < D; d0 += PM) {
         const int pm = min(PM, D - d0);
+        // f_color (fast path): thread dd < pm loads the contraction's sgn (A.S)[i, c_d(i)] of member
+        // d0 + dd now, behind the accumulation below, and adds it to the slots before the barrier
+        // that precedes this group's read-modify-write of G
+        float own = 0.0f;
+        if (accumulate && tid < pm) own = Gg[((size_t)(d0 + tid) * n + i) * k + ci[d0 + tid]];
         for (int e = tid; e < pm * k / 2; e += NT) ((u32x4n*)acc)[e] = u32x4n{0u, 0u, 0u, 0u};
         if ((pm * k) & 1)
             if (tid == 0) acc[pm * k - 1] = 0ull;
@@ -664,6 +671,9 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
                 if (cdv[u] >= 0)
                     atomicAdd(&acc[(cdv[u] & 0xFFFF) * k + ccol[u]], (unsigned long long)tab[cdv[u] >> 16]);
         }
+        // the number of row i's neighbours sharing its colour (the gather of 2 f_color)
+        if (accumulate && tid < pm)
+            atomicAdd(&d.f2p[(size_t)(d0 + tid) * kF2Slots + (i & (kF2Slots - 1))], (int)(sgn * own));
         __syncthreads();
         for (int e0 = tid; e0 < pm * k; e0 += 4 * NT) {
             float prev[4];
@@ -983,8 +993,21 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
+    const bool sparse_now = d.psparse && !st->pdense && pen_active(d, st);
+    if ((flags & kFlagSkipSparse) && sparse_now) return;
     const int p = st->pS;
     if (threadIdx.x == 0) best = 0x7FFFFFFF;
+    if ((flags & kFlagFoldSparse) && sparse_now) {
+        // this iteration's sparse rows gathered 2 f_color into slots: fold and clear them
+        for (int m = threadIdx.x; m < d.D; m += blockDim.x) {
+            int sum = 0;
+            for (int sl = 0; sl < kF2Slots; ++sl) {
+                sum += d.f2p[(size_t)m * kF2Slots + sl];
+                d.f2p[(size_t)m * kF2Slots + sl] = 0;
+            }
+            d.f2[m] = sum;
+        }
+    }
     __syncthreads();
     // the added fitness (equity or colour cost) was reduced by the class-size kernel
     const bool added = prob_added(d.problem);

@@ -55,7 +55,8 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
 //   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
 //           bit 3 = dense penalty operand even for graphs on the sparse penalty, bit 4 = no
-//           penalty pass at all
+//           penalty pass at all, bit 6 = no f_color gather for graphs whose iteration takes
+//           the sparse rows (the sparse kernel gathers it from G), bit 7 = no gather at all
 struct GemmShape {
     int prec, bm, ntw, mode;
 };

@@ -54,7 +54,7 @@ def test_conflicts_bit_exact(case):
     s.close()
 
 
-SHAPES = [(64, 2), (64, 4), (128, 4), (128, 6), (128, 8), (64, 9), (128, 9), (256, 4)]
+SHAPES = [(64, 2), (64, 4), (128, 4), (128, 6), (128, 8), (64, 9), (128, 9), (256, 4), (256, 6)]
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16, FP8, FP4])
