@@ -250,12 +250,14 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
  * 7 counter advance.  Phase 4 is timed separately as `steps` contraction
  * launches back to back on the operands of the last iteration (one event pair,
- * so launch gaps do not count), with the dense penalty pass unless penalty = 2.  When as_only is non-zero it then also times
- * `steps` back-to-back launches of the contraction restricted to A.S with the
- * gather (W unchanged) into ms[8], and `steps` launches of A.S with the gather
- * and the store of G (the form the contraction takes on the fast and plain
- * schedules in iterations without the dense penalty pass) into ms[9];
- * otherwise ms[8] = ms[9] = 0.  Synchronises the stream.
+ * so launch gaps do not count), with the f_color gather and the dense penalty
+ * pass unless penalty = 2.  When as_only is non-zero it then also times `steps`
+ * back-to-back launches of the contraction restricted to the A.S pass (no
+ * gather, no store; W unchanged) into ms[8], and `steps` launches of the A.S
+ * pass with the store of G (the form the contraction takes on the fast
+ * schedule in iterations whose penalty the sparse rows take, which then gather
+ * f_color themselves) into ms[9]; otherwise ms[8] = ms[9] = 0.  Synchronises
+ * the stream.
  * Errors: TCOL_EINVAL, TCOL_EHIP. */
 #define TCOL_NPHASES 10
 tcol_status tcol_profile(tcol_ctx *ctx, int32_t steps, int32_t as_only, float *ms);
