@@ -53,6 +53,7 @@ def lib():
         _lib.orc_fmscp.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
         _lib.orc_fitness.argtypes = [P, P, P, P, P, P, P]
         _lib.orc_mtilde.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
+        _lib.orc_class_conflicts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
         _lib.orc_grad_s.argtypes = [P, i64, P, P, P, P, P]
         _lib.orc_grad_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
         _lib.orc_update.argtypes = [P, i64, P, P, P]
@@ -180,6 +181,17 @@ def mtilde(c: np.ndarray) -> np.ndarray:
     M = np.zeros((n, n), dtype=np.int32)
     lib().orc_mtilde(D, n, _ptr(c), _ptr(M))
     return M
+
+
+def class_conflicts(A: np.ndarray, c: np.ndarray, k: int) -> np.ndarray:
+    """S_d^T A S_d for every member: int32 [D, k, k], entry (l, l') the ordered edges from
+    colour class l to class l' of member d."""
+    A = _c(A, np.uint8)
+    c = _c(c, np.int16)
+    D, n = c.shape
+    C = np.zeros((D, k, k), dtype=np.int32)
+    lib().orc_class_conflicts(D, n, k, _ptr(A), _ptr(c), _ptr(C))
+    return C
 
 
 def grad_s(p: Params, t: int, A, c, Mt, V) -> np.ndarray:

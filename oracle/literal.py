@@ -73,6 +73,11 @@ def equity_fitness(S: np.ndarray) -> np.ndarray:
     return np.minimum(np.abs(V - c1), np.abs(V - c2)).sum(axis=1)
 
 
+def class_conflicts(A: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """S_d' A S_d for each member (k x k), by matrix products."""
+    return np.transpose(S, (0, 2, 1)) @ (A[None] @ S)
+
+
 def group_concentration(S: np.ndarray) -> np.ndarray:
     """Eq. (tilde M): sum of the association tensor along the population axis."""
     return association(S).sum(axis=0)

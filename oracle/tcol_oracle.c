@@ -96,6 +96,23 @@ void orc_fcolor(int D, int n, const uint8_t *A, const int16_t *c, int64_t *fcol)
     }
 }
 
+/* Class-conflict matrix of each member, S_d^T A S_d (k x k): entry (l, l') counts the ordered
+ * pairs (i, j) with a_ij = 1, c_d(i) = l and c_d(j) = l', i.e. the edges between colour classes
+ * l and l' (twice the edges inside class l on the diagonal), so its trace is 2 f_color(S_d).
+ * Counted by brute force over the ordered edges.  C is [D][k][k]. */
+void orc_class_conflicts(int D, int n, int k, const uint8_t *A, const int16_t *c, int32_t *C)
+{
+    memset(C, 0, sizeof(int32_t) * (size_t)D * k * k);
+    for (int d = 0; d < D; ++d) {
+        const int16_t *cd = c + (size_t)d * n;
+        int32_t *Cd = C + (size_t)d * k * k;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                if (A[(size_t)i * n + j])
+                    Cd[(size_t)cd[i] * k + cd[j]] += 1;
+    }
+}
+
 /* Bounds of the equity constraint: c1 = floor(n/k); c2 = floor(n/k)+1, equal
  * to c1 when k divides n. */
 void orc_equity_bounds(int n, int k, int32_t *c1, int32_t *c2)

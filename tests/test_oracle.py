@@ -553,3 +553,28 @@ def test_momentum_zero_is_plain_and_row_sums_kept():
         Wi, t = r.W, r.t
     assert np.abs(vel.sum(axis=2)).max() < 1e-12
     np.testing.assert_allclose(Wi.sum(axis=2), W.sum(axis=2), atol=1e-12)
+
+
+def test_class_conflicts_pins():
+    """S_d^T A S_d: trace = 2 f_color (itself pinned by exhaustive enumeration), symmetric,
+    entries summing to 2 |E|, equal to the literal matrix product, and on a complete bipartite
+    graph coloured by its sides every edge between the two classes."""
+    rng = np.random.default_rng(11)
+    for n, k, D, p in ((9, 3, 4, 0.5), (30, 5, 3, 0.3), (1, 2, 2, 0.5)):
+        A = tcolgen.gnp(n, p, seed=n)
+        c = rng.integers(0, k, size=(D, n)).astype(np.int16)
+        C = oracle.class_conflicts(A, c, k)
+        assert C.shape == (D, k, k)
+        assert np.array_equal(np.trace(C, axis1=1, axis2=2), 2 * oracle.fcolor(A, c))
+        assert np.array_equal(C, np.transpose(C, (0, 2, 1)))
+        assert np.all(C.sum(axis=(1, 2)) == A.sum())
+        assert np.array_equal(C, np.rint(literal.class_conflicts(A.astype(float), onehot(c, k))).astype(np.int32))
+    # a bipartite graph coloured by its sides: every edge runs between classes 0 and 1
+    n = 10
+    A = np.zeros((n, n), np.uint8)
+    for i in range(5):
+        for j in range(5, 10):
+            A[i, j] = A[j, i] = 1
+    c = np.array([[0] * 5 + [1] * 5], np.int16)
+    C = oracle.class_conflicts(A, c, 3)[0]
+    assert C[0, 1] == C[1, 0] == 25 and C.sum() == 50
