@@ -200,6 +200,16 @@ tcol_status tcol_conflicts(tcol_ctx *ctx, int32_t g, int16_t *colors_dev, int64_
 tcol_status tcol_loss_grad(tcol_ctx *ctx, int32_t g, double *loss_dev, float *gradS_dev,
                            float *gradW_dev);
 
+/* Class-conflict matrices of graph g at its current W: C_dev (D*k*k int32, [d][l][l'])
+ * receives S_d^T A S_d, the number of ordered pairs (i, j) with a_ij = 1, c_d(i) = l and
+ * c_d(j) = l' (the edges between colour classes l and l', twice the edges inside class l
+ * on the diagonal; its trace is 2 f_color(S_d), Section 3.5 eq. (1) with M_d = S_d S_d^T).
+ * Computed as S_d^T (A.S_d): the contraction A.S (stored to G), then an FP32 MFMA
+ * contraction over the vertices with the one-hot S_d^T; exact (integers below 2^24).  For
+ * partitioning the same matrix of the member's groups.  Asynchronous; overwrites the
+ * context's G (the next tcol_step recomputes it).  Errors: TCOL_EINVAL, TCOL_EHIP. */
+tcol_status tcol_class_conflicts(tcol_ctx *ctx, int32_t g, int32_t *C_dev);
+
 /* Group concentration matrix Mt (n*n int32, row-major) of graph g at its
  * current W (eq. tildeM).  Asynchronous.  Errors: TCOL_EINVAL. */
 tcol_status tcol_mtilde(tcol_ctx *ctx, int32_t g, int32_t *mt_dev);

@@ -158,6 +158,14 @@ class Solver:
         _lib.check(self._lib.tcol_loss_grad(self._ctx, g, _ptr(loss), _ptr(gs), _ptr(gw)), "tcol_loss_grad")
         return loss, gs, gw
 
+    def class_conflicts(self, g: int = 0):
+        """S_d^T A S_d of every member (int32 [D, k, k]): edges between colour classes."""
+        torch = _torch()
+        p = self.params[g]
+        C = torch.empty((p.D, p.k, p.k), dtype=torch.int32, device=self.W[g].device)
+        _lib.check(self._lib.tcol_class_conflicts(self._ctx, g, _ptr(C)), "tcol_class_conflicts")
+        return C
+
     def mtilde(self, g: int = 0):
         torch = _torch()
         p = self.params[g]

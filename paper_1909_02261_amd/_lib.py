@@ -48,7 +48,8 @@ class TcolError(RuntimeError):
 EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_options",
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
            "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
-           "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters", "tcol_conflicts_noalloc"]
+           "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters", "tcol_conflicts_noalloc",
+           "tcol_class_conflicts"]
 NPHASES = 10
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only",
           "gemm_as_store"]
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_conflicts.argtypes = [P, i32, P, P, P]
     lib.tcol_loss_grad.argtypes = [P, i32, P, P, P]
     lib.tcol_mtilde.argtypes = [P, i32, P]
+    lib.tcol_class_conflicts.argtypes = [P, i32, P]
     lib.tcol_get_t.argtypes = [P, i32, ctypes.POINTER(i64)]
     lib.tcol_set_t.argtypes = [P, i32, i64]
     lib.tcol_reset.argtypes = [P]

@@ -841,6 +841,17 @@ tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* grad
     return TCOL_OK;
 }
 
+tcol_status tcol_class_conflicts(tcol_ctx* c, int32_t g, int32_t* C_dev) {
+    if (!c || g < 0 || g >= c->G || !C_dev) return TCOL_EINVAL;
+    // colours and S of the current W, then A.S stored to G (no penalty pass, no gather)
+    HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
+    HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, c->stream));
+    HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
+    HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1 | 4 | 16 | 128, 0, c->stream));
+    HIPCHK(launch_class_conflicts(c->ddesc, g, c->params[g].D, c->params[g].k, C_dev, c->stream));
+    return TCOL_OK;
+}
+
 tcol_status tcol_mtilde(tcol_ctx* c, int32_t g, int32_t* mt_dev) {
     if (!c || g < 0 || g >= c->G || !mt_dev) return TCOL_EINVAL;
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));

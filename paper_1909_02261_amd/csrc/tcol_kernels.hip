@@ -1381,6 +1381,55 @@ __global__ __launch_bounds__(256) void k_init_weights(float* __restrict__ W, lon
     if (2 * b + 1 < count) W[2 * b + 1] = (float)(r * sin(th) * sigma0);
 }
 
+// ------------------------------------------------ class-conflict matrix ---------
+
+// C_d = S_d^T (A.S_d) for one graph on fp32 MFMA (16x16x4; the integer entries stay below
+// 2^24, so the FP32 accumulation is exact): the A operand is the one-hot S_d^T, made in
+// registers from the colours (row l, column i: 1 when c_d(i) = l), the B operand the
+// contraction's A.S_d from G ([D][n][k], rows i, columns l').  A block of 4 waves takes
+// member d = blockIdx.z, rows l0 .. l0 + 15 (blockIdx.y) and columns 64 blockIdx.x .. + 63,
+// one 16 x 16 tile per wave; out is [D][k][k] int32.
+typedef float f32x4k __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_class_conflicts(const GraphDev* __restrict__ gd, int g,
+                                                         int32_t* __restrict__ out) {
+    const GraphDev& d = gd[g];
+    const int k = d.k, n = d.n;
+    const int dm = blockIdx.z;
+    const int l0 = blockIdx.y * 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c0 = blockIdx.x * 64 + wave * 16;
+    if (c0 >= k) return;
+    const int16_t* __restrict__ col = d.c[d.st->pS] + (size_t)dm * d.cs;
+    const float* __restrict__ Gd = d.G + (size_t)dm * n * k;
+    const int lrow = l0 + (lane & 15);          // A operand row (colour l)
+    const int ccol = c0 + (lane & 15);          // B operand column (colour l')
+    const int kk = lane >> 4;                   // K index within the step
+    f32x4k acc = {0.f, 0.f, 0.f, 0.f};
+    constexpr int U = 8;                        // K-steps of 4 per round of loads
+    for (int i0 = 0; i0 < n; i0 += 4 * U) {
+        float a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + 4 * u + kk;
+            const bool in = i < n;
+            const int ci = in ? (int)gview(col)[i] : -1;
+            a[u] = ci == lrow ? 1.0f : 0.0f;
+            b[u] = (in && ccol < k) ? gview(Gd)[(size_t)i * k + ccol] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+    }
+    // lane holds rows 4 (lane / 16) + r, column lane mod 16 of the tile; G holds -A.S for
+    // partitioning
+    const float sg = prob_partition(d.problem) ? -1.0f : 1.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int l = l0 + (lane >> 4) * 4 + r, lp = c0 + (lane & 15);
+        if (l < k && lp < k) out[((size_t)dm * k + l) * k + lp] = (int32_t)(sg * acc[r]);
+    }
+}
+
 // ------------------------------------------- descriptors from kernel arguments --
 
 // Writes one graph's descriptor and a fresh state (the values travel as kernel arguments,
@@ -1565,6 +1614,13 @@ hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipSt
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_copy_report, dim3(256), dim3(256), 0, s, gd, g, colors, fcol, feq);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_class_conflicts(const GraphDev* gd, int g, int D, int k, int32_t* out, hipStream_t s) {
+    if (D <= 0 || k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_class_conflicts, dim3(ceil_div(k, 64), ceil_div(k, 16), D), dim3(256), 0, s, gd, g, out);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -46,6 +46,8 @@ hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipSt
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
                               hipStream_t s);
 hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long t, hipStream_t s);
+// class-conflict matrices S_d^T (A.S_d) of graph g ([D][k][k] int32) from G = A.S and the colours
+hipError_t launch_class_conflicts(const GraphDev* gd, int g, int D, int k, int32_t* out, hipStream_t s);
 // one graph's descriptor and a fresh state written on the device from kernel arguments
 hipError_t launch_put_desc(const GraphDev& d, GraphDev* gd, GraphState* st, hipStream_t s);
 // bytes (a multiple of 16) of 16-byte aligned device memory set to zero by a kernel

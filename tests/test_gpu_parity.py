@@ -697,6 +697,40 @@ def test_c5b_batch_steps_every_graph(penalty, prec):
     s.close()
 
 
+@pytest.mark.parametrize("case", [GraphCase("cc_ragged", KCOL, 77, 7, 5, FP4, "gnp", 0.4, graph_seed=7),
+                                  GraphCase("cc_k90", ECP, 300, 90, 6, BF16, "gnp", 0.5, graph_seed=9, mu=0.0, nu=1e-5),
+                                  GraphCase("cc_kpart", tcolgen.KPART, 150, 5, 4, FP8, "gnp", 0.3, graph_seed=10),
+                                  GraphCase("cc_fp32_k130", KCOL, 500, 130, 3, FP32, "gnp", 0.5, graph_seed=11)],
+                         ids=lambda c: c.name)
+def test_class_conflicts_exact(case):
+    """S_d^T A S_d on MFMA (one-hot S^T against the contraction's A.S) equals the oracle's edge
+    count between colour classes, for ragged n, k not a multiple of the 16 x 16 tiles and every
+    operand precision; its trace is twice the conflict count tcol_conflicts reports (for
+    partitioning: the same matrix of the groups)."""
+    s, (A,) = make_solver([case])
+    C = host(s.class_conflicts(0))
+    c_ref = oracle.colors(host(s.W[0]))
+    assert np.array_equal(C, oracle.class_conflicts(A, c_ref, case.k))
+    _, fc, _ = s.conflicts(0)
+    trace = np.trace(C, axis1=1, axis2=2)
+    if case.problem == tcolgen.KPART:
+        assert np.array_equal(host(fc), A.sum() // 2 - trace // 2)
+    else:
+        assert np.array_equal(host(fc), trace // 2)
+    s.close()
+
+
+def test_class_conflicts_c5():
+    """The class-conflict matrices at n = 4000, k = 280, D = 32 (fp4 A.S), bit-exact."""
+    case = tcolgen.case_c5(FP4)
+    s, (A,) = make_solver([case])
+    s.set_t(30)
+    s.step(3)
+    C = host(s.class_conflicts(0))
+    assert np.array_equal(C, oracle.class_conflicts(A, oracle.colors(host(s.W[0])), case.k))
+    s.close()
+
+
 @pytest.mark.parametrize("prec,published", [(FP4, 10100.0), (FP8, 5000.0), (BF16, 2500.0), (FP32, 157.3)],
                          ids=["fp4", "fp8", "bf16", "fp32"])
 def test_mfma_peak_measurement_is_plausible(prec, published):
