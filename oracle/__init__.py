@@ -61,6 +61,14 @@ def lib():
         _lib.orc_iteration.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         _lib.orc_iteration.restype = ctypes.c_int
         _lib.orc_run.argtypes = [P, P, P, P, ctypes.c_int, P, P]
+        _lib.orc_select.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib.orc_select.restype = ctypes.c_int
+        _lib.orc_fcolor_multi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+        _lib.orc_mtilde_multi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.orc_class_sizes_multi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.orc_grad_s_multi.argtypes = [P, i64, P, P, P, P]
+        _lib.orc_iteration_multi.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        _lib.orc_iteration_multi.restype = ctypes.c_int
         _lib.orc_run.restype = ctypes.c_int
     return _lib
 
@@ -282,3 +290,89 @@ def run(p: Params, t: int, A: np.ndarray, W: np.ndarray, max_steps: int):
     if done < 0:
         raise RuntimeError(f"oracle run failed: {done}")
     return Wd, int(tt[0]), done, int(ld[0]), (col if ld[0] >= 0 else None)
+
+
+# ---- multicolouring (problem 5): vertex i takes demand[i] colours ----
+
+MCOL = 5
+
+
+def select(W: np.ndarray, demand: Optional[np.ndarray] = None) -> np.ndarray:
+    """Step 1 of multicolouring: in each row the demand[i] colours of largest weight (lower
+    colour first on ties); multi-hot uint8 [D, n, k]."""
+    W = _c(W, np.float64)
+    D, n, k = W.shape
+    S = np.zeros((D, n, k), dtype=np.uint8)
+    dem = None if demand is None else _c(demand, np.int32)
+    rc = lib().orc_select(D, n, k, _ptr(W), _ptr(dem), _ptr(S))
+    if rc == -5:
+        raise FloatingPointError("non-finite weight")
+    if rc:
+        raise ValueError("demand outside 1..k")
+    return S
+
+
+def fcolor_multi(A: np.ndarray, S: np.ndarray) -> np.ndarray:
+    A = _c(A, np.uint8)
+    S = _c(S, np.uint8)
+    D, n, k = S.shape
+    f = np.zeros(D, dtype=np.int64)
+    lib().orc_fcolor_multi(D, n, k, _ptr(A), _ptr(S), _ptr(f))
+    return f
+
+
+def mtilde_multi(S: np.ndarray) -> np.ndarray:
+    S = _c(S, np.uint8)
+    D, n, k = S.shape
+    M = np.zeros((n, n), dtype=np.int32)
+    lib().orc_mtilde_multi(D, n, k, _ptr(S), _ptr(M))
+    return M
+
+
+def class_sizes_multi(S: np.ndarray) -> np.ndarray:
+    S = _c(S, np.uint8)
+    D, n, k = S.shape
+    V = np.zeros((D, k), dtype=np.int32)
+    lib().orc_class_sizes_multi(D, n, k, _ptr(S), _ptr(V))
+    return V
+
+
+def grad_s_multi(p: Params, t: int, A, S, Mt) -> np.ndarray:
+    A = _c(A, np.uint8); S = _c(S, np.uint8); Mt = _c(Mt, np.int32)
+    g = np.zeros((p.D, p.n, p.k), dtype=np.float64)
+    ps = p.c_struct()
+    lib().orc_grad_s_multi(ctypes.byref(ps), int(t), _ptr(A), _ptr(S), _ptr(Mt), _ptr(g))
+    return g
+
+
+@dataclass
+class MultiIterResult:
+    status: int                 # 1 = legal member found (no update), 0 = updated
+    W: np.ndarray
+    t: int
+    S: np.ndarray               # the selection of step 1
+    f_color: np.ndarray
+    gS: Optional[np.ndarray]
+    gW: Optional[np.ndarray]
+    legal_d: int
+
+
+def iteration_multi(p: Params, t: int, A: np.ndarray, W: np.ndarray, demand: Optional[np.ndarray] = None,
+                    want_grads: bool = True) -> MultiIterResult:
+    """One multicolouring iteration (steps 1-4) from W (upcast to FP64)."""
+    A = _c(A, np.uint8)
+    Wd = np.array(W, dtype=np.float64, copy=True)
+    D, n, k = Wd.shape
+    dem = None if demand is None else _c(demand, np.int32)
+    tt = np.array([t], dtype=np.int64)
+    S = np.zeros((D, n, k), np.uint8)
+    f = np.zeros(D, np.int64)
+    gS = np.zeros((D, n, k)) if want_grads else None
+    gW = np.zeros((D, n, k)) if want_grads else None
+    ld = np.zeros(1, np.int32)
+    ps = p.c_struct()
+    rc = lib().orc_iteration_multi(ctypes.byref(ps), _ptr(tt), _ptr(A), _ptr(dem), _ptr(Wd), _ptr(S), _ptr(f),
+                                   _ptr(gS), _ptr(gW), _ptr(ld))
+    if rc < 0:
+        raise RuntimeError(f"oracle multicolouring iteration failed: {rc}")
+    return MultiIterResult(rc, Wd, int(tt[0]), S, f, gS if rc == 0 else None, gW if rc == 0 else None, int(ld[0]))

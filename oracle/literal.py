@@ -25,6 +25,18 @@ def one_hot_argmax(W: np.ndarray) -> np.ndarray:
     return S
 
 
+def top_c(W: np.ndarray, demand: np.ndarray) -> np.ndarray:
+    """Section 6, multicolouring: S marks the demand[i] largest weights of each row (a stable
+    sort of the negated weights, so equal weights go to the lower colour first)."""
+    D, n, k = W.shape
+    S = np.zeros((D, n, k))
+    order = np.argsort(-W, axis=2, kind="stable")
+    for d in range(D):
+        for i in range(n):
+            S[d, i, order[d, i, :demand[i]]] = 1.0
+    return S
+
+
 def association(S: np.ndarray) -> np.ndarray:
     """M = S . S' (product over the colour axis), [D, n, n]."""
     return S @ np.transpose(S, (0, 2, 1))

@@ -32,7 +32,8 @@
  * penalty and bonus as D - mt; the balanced variant adds the equity fitness.
  * For minimum sum colouring the equity fitness is replaced by the colour cost
  * sum_i z_{c(i)} with z_l = l + 1.  With momentum gamma > 0 the update is the
- * heavy-ball step v <- gamma v + gW, W <- W - eta v (v starts at zero).
+ * heavy-ball step v <- gamma v + gW, W <- W - eta v (v starts at zero).  Problem 5,
+ * multicolouring, selects c_i colours per vertex (orc_select and the *_multi functions).
  */
 #include <math.h>
 #include <stdint.h>
@@ -355,6 +356,154 @@ void orc_loss(const orc_params *p, int64_t t, const uint8_t *A, const int32_t *M
     out[2] = se;
     out[3] = kappa;
     out[4] = varpi;
+}
+
+/* ---- multicolouring (Section 6) ----
+ * Vertex i has a demand c_i >= 1 and takes c_i different colours: step 1 selects, in each
+ * member, the c_i colour groups of largest weight in w_{d,i} (ties go to the lower colour,
+ * as for the argmax, which is the case c_i = 1).  S_d is then multi-hot ([D][n][k] bytes),
+ * the association m_dij = (S_d S_d^T)_ij counts the colours i and j share, and the fitness,
+ * group concentration, loss and gradient keep their tensor forms. */
+
+/* Selection of step 1.  demand[n] (NULL: every c_i = 1).  Returns 0, -5 for a non-finite
+ * weight, -1 for a demand outside 1..k. */
+int orc_select(int D, int n, int k, const double *W, const int32_t *demand, uint8_t *S)
+{
+    memset(S, 0, (size_t)D * n * k);
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < n; ++i) {
+            const double *w = W + ((size_t)d * n + i) * k;
+            uint8_t *srow = S + ((size_t)d * n + i) * k;
+            const int ci = demand ? demand[i] : 1;
+            if (ci < 1 || ci > k)
+                return -1;
+            for (int l = 0; l < k; ++l)
+                if (!isfinite(w[l]))
+                    return -5;
+            for (int sel = 0; sel < ci; ++sel) {
+                int best = -1;
+                for (int l = 0; l < k; ++l)
+                    if (!srow[l] && (best < 0 || w[l] > w[best]))
+                        best = l;
+                srow[best] = 1;
+            }
+        }
+    return 0;
+}
+
+/* f_color(S_d) = 1/2 sum_ij a_ij m_dij: over the edges {i, j}, the colours their ends share. */
+void orc_fcolor_multi(int D, int n, int k, const uint8_t *A, const uint8_t *S, int64_t *fcol)
+{
+    for (int d = 0; d < D; ++d) {
+        int64_t f = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (A[(size_t)i * n + j]) {
+                    const uint8_t *si = S + ((size_t)d * n + i) * k, *sj = S + ((size_t)d * n + j) * k;
+                    for (int l = 0; l < k; ++l)
+                        f += si[l] & sj[l];
+                }
+        fcol[d] = f;
+    }
+}
+
+/* mt_ij = sum_d m_dij, the colours i and j share summed over the members. */
+void orc_mtilde_multi(int D, int n, int k, const uint8_t *S, int32_t *Mt)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            int32_t m = 0;
+            for (int d = 0; d < D; ++d) {
+                const uint8_t *si = S + ((size_t)d * n + i) * k, *sj = S + ((size_t)d * n + j) * k;
+                for (int l = 0; l < k; ++l)
+                    m += si[l] & sj[l];
+            }
+            Mt[(size_t)i * n + j] = m;
+        }
+}
+
+/* #V_{d,l}: the vertices of member d holding colour l. */
+void orc_class_sizes_multi(int D, int n, int k, const uint8_t *S, int32_t *V)
+{
+    memset(V, 0, sizeof(int32_t) * (size_t)D * k);
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < n; ++i)
+            for (int l = 0; l < k; ++l)
+                V[(size_t)d * k + l] += S[((size_t)d * n + i) * k + l];
+}
+
+/* Gradient of the global loss with respect to S (colouring form, no added term):
+ *   gS = A.S + 2 alpha lambda t (A o Mt^(alpha-1)).S - 2 beta mu t ((J - A) o Mt^(beta-1)).S
+ * with the products taken over the selected colours of every j. */
+void orc_grad_s_multi(const orc_params *p, int64_t t, const uint8_t *A, const uint8_t *S,
+                      const int32_t *Mt, double *gS)
+{
+    const int n = p->n, k = p->k, D = p->D;
+    const double tt = (double)t;
+    const double cpen = 2.0 * p->alpha * p->lambda * tt;
+    const double cbon = 2.0 * p->beta * p->mu * tt;
+    memset(gS, 0, sizeof(double) * (size_t)D * n * k);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const size_t e = (size_t)i * n + j;
+            const double m = (double)Mt[e];
+            double w = 0.0;
+            if (A[e])
+                w = 1.0 + cpen * pow0(m, p->alpha - 1.0);
+            else if (j != i || p->bonus_diag)
+                w = -cbon * pow0(m, p->beta - 1.0);
+            if (w == 0.0)
+                continue;
+            for (int d = 0; d < D; ++d) {
+                const uint8_t *sj = S + ((size_t)d * n + j) * k;
+                double *g = gS + ((size_t)d * n + i) * k;
+                for (int l = 0; l < k; ++l)
+                    if (sj[l])
+                        g[l] += w;
+            }
+        }
+}
+
+/* One multicolouring iteration (steps 1-4) on W (updated in place); outputs may be NULL.
+ * Returns 1 if a member is legal (f_color = 0: no update, *legal_d the lowest such member
+ * when stop_on_legal), 0 after an update, or a negative error. */
+int orc_iteration_multi(const orc_params *p, int64_t *t, const uint8_t *A, const int32_t *demand, double *W,
+                        uint8_t *S_out, int64_t *f_out, double *gS_out, double *gW_out, int32_t *legal_d)
+{
+    const int n = p->n, k = p->k, D = p->D;
+    const size_t dnk = (size_t)D * n * k;
+    if (p->momentum != 0.0)
+        return -1;
+    uint8_t *S = (uint8_t *)malloc(dnk);
+    int32_t *Mt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * n);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * D);
+    double *gS = (double *)malloc(sizeof(double) * dnk);
+    double *gW = (double *)malloc(sizeof(double) * dnk);
+    int rc = (S && Mt && f && gS && gW) ? 0 : -6;
+    if (!rc)
+        rc = orc_select(D, n, k, W, demand, S);
+    if (!rc) {
+        orc_fcolor_multi(D, n, k, A, S, f);
+        int best = -1;
+        for (int d = 0; d < D; ++d)
+            if (f[d] == 0 && best < 0) best = d;
+        if (S_out) memcpy(S_out, S, dnk);
+        if (f_out) memcpy(f_out, f, sizeof(int64_t) * D);
+        if (legal_d) *legal_d = best;
+        if (best >= 0 && p->stop_on_legal) {
+            rc = 1;
+        } else {
+            orc_mtilde_multi(D, n, k, S, Mt);
+            orc_grad_s_multi(p, *t, A, S, Mt, gS);
+            orc_grad_w(D, n, k, W, gS, gW);
+            if (gS_out) memcpy(gS_out, gS, sizeof(double) * dnk);
+            if (gW_out) memcpy(gW_out, gW, sizeof(double) * dnk);
+            orc_update(p, *t, W, gW, NULL);
+            *t += 1;
+        }
+    }
+    free(S); free(Mt); free(f); free(gS); free(gW);
+    return rc;
 }
 
 /* Work arrays for one iteration. */

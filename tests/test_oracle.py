@@ -578,3 +578,172 @@ def test_class_conflicts_pins():
     c = np.array([[0] * 5 + [1] * 5], np.int16)
     C = oracle.class_conflicts(A, c, 3)[0]
     assert C[0, 1] == C[1, 0] == 25 and C.sum() == 50
+
+
+# ------------------------------------------------------------ multicolouring -----
+
+def rand_demand(n, k, rng, cmax=3):
+    return rng.integers(1, min(cmax, k) + 1, size=n).astype(np.int32)
+
+
+def test_select_matches_literal_top_c():
+    """Step 1 of multicolouring against a stable sort of the negated weights; integer weights
+    make ties common, and ties go to the lower colour."""
+    rng = np.random.default_rng(51)
+    D, n, k = 3, 40, 7
+    W = rng.integers(-2, 3, size=(D, n, k)).astype(np.float64)
+    dem = rand_demand(n, k, rng, cmax=5)
+    S = oracle.select(W, dem)
+    assert np.array_equal(S, literal.top_c(W, dem).astype(np.uint8))
+    assert np.array_equal(S.sum(axis=2), np.broadcast_to(dem, (D, n)))
+    with pytest.raises(ValueError):
+        oracle.select(W, np.full(n, k + 1, np.int32))
+    W[1, 2, 3] = np.nan
+    with pytest.raises(FloatingPointError):
+        oracle.select(W, dem)
+
+
+def test_multi_with_unit_demand_is_k_colouring():
+    """With every c_i = 1 the selection is the argmax and every quantity, and a whole
+    iteration, is the k-colouring one (problem 0, whose pins are above)."""
+    rng = np.random.default_rng(52)
+    D, n, k = 4, 30, 6
+    A = tcolgen.gnp(n, 0.5, 52)
+    W = rng.normal(size=(D, n, k))
+    one = np.ones(n, np.int32)
+    S = oracle.select(W, one)
+    c = oracle.colors(W)
+    assert np.array_equal(S, onehot(c, k).astype(np.uint8))
+    assert np.array_equal(oracle.fcolor_multi(A, S), oracle.fcolor(A, c))
+    Mt = oracle.mtilde_multi(S)
+    assert np.array_equal(Mt, oracle.mtilde(c))
+    p0 = rand_params(0, n, k, D, stop_on_legal=0)
+    p5 = rand_params(5, n, k, D, stop_on_legal=0, nu=0.0)
+    # the same sums, grouped differently (the multi form adds a_ij and the penalty per pair first)
+    np.testing.assert_allclose(oracle.grad_s_multi(p5, 9, A, S, Mt),
+                               oracle.grad_s(p0, 9, A, c, Mt, oracle.class_sizes(c, k)), rtol=1e-13, atol=1e-13)
+    for t in (0, 4):
+        r5 = oracle.iteration_multi(p5, t, A, W, one)
+        r0 = oracle.iteration(p0, t, A, W)
+        assert r5.status == r0.status == 0
+        np.testing.assert_allclose(r5.W, r0.W, rtol=1e-13, atol=1e-16)
+
+
+def _subset_members(n, k, demand):
+    """Every assignment of demand[i] different colours to each vertex, as multi-hot members."""
+    choices = [list(itertools.combinations(range(k), int(c))) for c in demand]
+    out = []
+    for combo in itertools.product(*choices):
+        S = np.zeros((n, k), np.uint8)
+        for i, cols in enumerate(combo):
+            S[i, list(cols)] = 1
+        out.append(S)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("name,n,edges,demand,k_no,k_yes", [
+    # the 5-cycle needs 5 colours when every vertex takes 2 (its 2-fold chromatic number)
+    ("C5 x2", 5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)], [2, 2, 2, 2, 2], 4, 5),
+    # a triangle whose vertices take 1, 2 and 3 colours needs 6
+    ("K3 1,2,3", 3, [(0, 1), (1, 2), (0, 2)], [1, 2, 3], 5, 6),
+])
+def test_multicolouring_exhaustive(name, n, edges, demand, k_no, k_yes):
+    """f_color of multicolourings against facts about the graphs: enumerating every assignment,
+    no legal one exists with k_no colours and one does with k_yes; and on each assignment the
+    value is the number of (edge, shared colour) pairs, counted with Python sets."""
+    A = adj_from_edges(n, edges)
+    for k, want_legal in ((k_no, False), (k_yes, True)):
+        S = _subset_members(n, k, demand)
+        f = oracle.fcolor_multi(A, S)
+        assert (f.min() == 0) == want_legal, (name, k)
+        for d in range(0, len(S), max(1, len(S) // 50)):
+            sets = [set(np.nonzero(S[d, i])[0]) for i in range(n)]
+            assert f[d] == sum(len(sets[i] & sets[j]) for i, j in edges)
+
+
+def test_mtilde_multi_properties():
+    rng = np.random.default_rng(53)
+    D, n, k = 5, 25, 6
+    W = rng.normal(size=(D, n, k))
+    dem = rand_demand(n, k, rng)
+    S = oracle.select(W, dem)
+    Mt = oracle.mtilde_multi(S)
+    assert np.array_equal(Mt, Mt.T)
+    assert np.array_equal(np.diag(Mt), D * dem)
+    V = oracle.class_sizes_multi(S)
+    assert np.array_equal(V, S.sum(axis=1))
+    assert Mt.sum() == int((V.astype(np.int64) ** 2).sum())
+    assert np.array_equal(Mt, np.rint(literal.group_concentration(S.astype(float))).astype(np.int32))
+
+
+@pytest.mark.parametrize("diag", [1, 0])
+def test_grad_s_multi_literal_and_finite_differences(diag):
+    """The gradient with multi-hot S against the literal tensor form, and against central
+    differences (h = 1e-3) of the paper's loss as a polynomial in S at the selected S."""
+    rng = np.random.default_rng(54 + diag)
+    D, n, k = 3, 14, 5
+    A = tcolgen.gnp(n, 0.5, 54)
+    W = rng.normal(size=(D, n, k))
+    dem = rand_demand(n, k, rng)
+    S = oracle.select(W, dem)
+    p = rand_params(5, n, k, D, bonus_diag=diag, nu=0.0)
+    t = 6
+    gS = oracle.grad_s_multi(p, t, A, S, oracle.mtilde_multi(S))
+    Sf = S.astype(float)
+    Af = A.astype(float)
+    lit = literal.grad_s(Af, Sf, t, p.alpha, p.lam, p.beta, p.mu, p.nu, 5, diag)
+    np.testing.assert_allclose(gS, lit, rtol=1e-12, atol=1e-12)
+    h = 1e-3
+
+    def L(Sx):
+        return literal.global_loss(Af, Sx, t, p.alpha, p.lam, p.beta, p.mu, p.nu, 5, diag)
+
+    for (d, i, l) in tcolgen.fd_entries(32, D, n, k, seed=5):
+        Sp = Sf.copy(); Sp[d, i, l] += h
+        Sm = Sf.copy(); Sm[d, i, l] -= h
+        fd = (L(Sp) - L(Sm)) / (2 * h)
+        assert fd == pytest.approx(gS[d, i, l], rel=1e-4, abs=1e-6), (d, i, l)
+
+
+def test_loss_multi_matches_literal():
+    rng = np.random.default_rng(56)
+    D, n, k = 4, 20, 6
+    A = tcolgen.gnp(n, 0.4, 56)
+    W = rng.normal(size=(D, n, k))
+    dem = rand_demand(n, k, rng)
+    S = oracle.select(W, dem)
+    p = rand_params(5, n, k, D, nu=0.0)
+    Mt = oracle.mtilde_multi(S)
+    f = oracle.fcolor_multi(A, S)
+    out = oracle.loss(p, 7, A, Mt, f, np.zeros(D, np.int64))
+    lit = literal.global_loss(A.astype(float), S.astype(float), 7, p.alpha, p.lam, p.beta, p.mu, p.nu, 5, 1)
+    assert out[0] == pytest.approx(lit, rel=1e-12)
+    assert out[1] == pytest.approx(literal.fitness_color(A.astype(float), S.astype(float)).sum())
+
+
+def test_iteration_multi_composes_literal_steps():
+    """One iteration: literal selection, gradient, straight-through backward, update and
+    smoothing give the oracle's W; a member holding a legal multicolouring stops it."""
+    rng = np.random.default_rng(57)
+    D, n, k = 3, 18, 6
+    A = tcolgen.gnp(n, 0.3, 57)
+    W = rng.normal(size=(D, n, k))
+    dem = rand_demand(n, k, rng)
+    p = rand_params(5, n, k, D, nu=0.0, stop_on_legal=0)
+    for t in (3, 4):          # t = 4 smooths (nb_iter 5)
+        r = oracle.iteration_multi(p, t, A, W, dem)
+        S = literal.top_c(W, dem)
+        gS = literal.grad_s(A.astype(float), S, t, p.alpha, p.lam, p.beta, p.mu, p.nu, 5, 1)
+        Wn = W - p.eta * literal.grad_w(W, gS)
+        if (t + 1) % p.nb_iter == 0:
+            Wn = Wn / p.rho
+        np.testing.assert_allclose(r.W, Wn, rtol=1e-12, atol=1e-15)
+        assert r.t == t + 1
+    # a legal member: the triangle with demands 1, 2, 3 and 6 colours, member 1 coloured legally
+    A3 = adj_from_edges(3, [(0, 1), (1, 2), (0, 2)])
+    dem3 = np.array([1, 2, 3], np.int32)
+    W3 = rng.normal(size=(2, 3, 6)) * 0.01
+    W3[1, 0, 0] = W3[1, 1, [1, 2]] = W3[1, 2, [3, 4, 5]] = 1.0
+    p3 = rand_params(5, 3, 6, 2, nu=0.0)
+    r = oracle.iteration_multi(p3, 2, A3, W3, dem3)
+    assert r.status == 1 and r.legal_d == 1 and r.f_color[1] == 0
