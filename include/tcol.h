@@ -71,7 +71,17 @@ enum {
  * counted from 0), whose gradient is nu t z_l.  "Main" fitness below means
  * f_color (colouring problems) or the cut (partitioning), "added" fitness f_eq,
  * the colour cost or 0; a member is legal when their sum is 0. */
-enum { TCOL_KCOL = 0, TCOL_ECP = 1, TCOL_KPART = 2, TCOL_BKPART = 3, TCOL_MSCP = 4 };
+enum { TCOL_KCOL = 0, TCOL_ECP = 1, TCOL_KPART = 2, TCOL_BKPART = 3, TCOL_MSCP = 4, TCOL_MCOL = 5 };
+
+/* TCOL_MCOL, multicolouring (Section 6): vertex i has a demand c_i (tcol_set_demand; 1 until
+ * set) and takes c_i different colours, adjacent vertices sharing none.  Step 1 selects, in
+ * each member, the c_i colours of largest weight in w_{d,i} (equal weights: the lower colour
+ * first, so c_i = 1 is the argmax); S_d is then multi-hot, M_d = S_d S_d^T counts the colours
+ * two vertices share, and f_color = 1/2 sum(A o M_d) (the (edge, shared colour) pairs), Mt,
+ * the loss and its gradient keep their tensor forms (eqs. (1), (4)-(7), (17)).  A member is
+ * legal when f_color = 0.  Such graphs run the plain step schedule with the dense penalty
+ * operand, without momentum, with k <= 1024 and max_demand (below) colours per vertex at
+ * most. */
 
 /* Operand precision of the contractions A.S and (penalty).S.  The 0/1
  * operands A and S are exact in every format and accumulate in FP32, so the
@@ -99,6 +109,8 @@ typedef struct {
                                variants): v <- gamma v + gW, W <- W - eta v, v from zero;
                                0 = the paper's plain step.  With gamma > 0 the epilogue
                                step schedule is not used (the fast one runs instead) */
+    int32_t max_demand;     /* TCOL_MCOL: the largest demand c_i (1..8, at most k); other
+                               problems: 0 or 1 */
 } tcol_graph_params;
 
 /* Execution options of a context. */
@@ -161,6 +173,17 @@ tcol_status tcol_init(tcol_ctx **ctx, int32_t G, const tcol_graph_params *p,
                       const uint8_t *const *A_dev, float *const *W_dev,
                       void *ws_dev, size_t ws_bytes, void *stream);
 
+/* Multicolouring demands of graph g (a TCOL_MCOL graph): demand (host, n int32) c_i in
+ * 1..max_demand.  Copied; takes effect from the next call.  Synchronises the stream.
+ * Errors: TCOL_EINVAL (not a TCOL_MCOL graph, NULL, a demand out of range), TCOL_EHIP. */
+tcol_status tcol_set_demand(tcol_ctx *ctx, int32_t g, const int32_t *demand);
+
+/* The selection of step 1 for graph g at its current W: sel_dev (device, D*n*max_demand int16,
+ * [d][i][s]) receives the s-th colour of vertex i in member d in decreasing weight (ties: lower
+ * colour first), -1 past the vertex's demand; for other problems max_demand is 1 and this is
+ * the argmax colouring.  Asynchronous.  Errors: TCOL_EINVAL, TCOL_EHIP. */
+tcol_status tcol_selection(tcol_ctx *ctx, int32_t g, int16_t *sel_dev);
+
 /* Change execution options (before or between tcol_step calls). */
 tcol_status tcol_set_options(tcol_ctx *ctx, const tcol_options *opt);
 tcol_status tcol_get_options(tcol_ctx *ctx, tcol_options *opt);
@@ -177,6 +200,7 @@ tcol_status tcol_get_options(tcol_ctx *ctx, tcol_options *opt);
  * finite; the affected graph stops without updating), TCOL_EHIP, TCOL_EINVAL. */
 tcol_status tcol_step(tcol_ctx *ctx, int32_t max_steps, int32_t *steps_done, int32_t *legal_d,
                       int16_t *const *colors_out_dev);
+/* (For a TCOL_MCOL graph colors_out_dev[g] receives n * max_demand int16, [i][s], -1 padded.) */
 
 /* Steps 1-2 only, on the current W of graph g (W unchanged, t unchanged):
  *   colors_dev (D*n int16, may be NULL) argmax colours c_d(i);
@@ -209,6 +233,7 @@ tcol_status tcol_loss_grad(tcol_ctx *ctx, int32_t g, double *loss_dev, float *gr
  * partitioning the same matrix of the member's groups.  Asynchronous; overwrites the
  * context's G (the next tcol_step recomputes it).  Errors: TCOL_EINVAL, TCOL_EHIP. */
 tcol_status tcol_class_conflicts(tcol_ctx *ctx, int32_t g, int32_t *C_dev);
+/* (TCOL_MCOL graphs: TCOL_EINVAL.) */
 
 /* Group concentration matrix Mt (n*n int32, row-major) of graph g at its
  * current W (eq. tildeM).  Asynchronous.  Errors: TCOL_EINVAL. */
@@ -298,7 +323,7 @@ tcol_status tcol_mfma_peak(int32_t precision, int32_t iters, double *tflops);
  * that array and keep its last contents: calls that may overlap on one device (different
  * streams, or host threads) race and must be ordered by the caller.  The outputs equal
  * tcol_conflicts' for the same A, W and problem.
- * Errors: TCOL_EINVAL (NULL A_dev or W_dev, bad parameters), TCOL_ESHAPE, TCOL_ENOMEM (the
+ * Errors: TCOL_EINVAL (NULL A_dev or W_dev, bad parameters, TCOL_MCOL), TCOL_ESHAPE, TCOL_ENOMEM (the
  * graph needs more scratch than the array holds, about n = 4000 with D k = 8960 at most),
  * TCOL_EHIP. */
 #define TCOL_NOALLOC_SCRATCH_BYTES (32u << 20)

@@ -12,10 +12,10 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 from . import _lib
-from ._lib import BF16, BKPART, ECP, FP4, FP8, FP32, KCOL, KPART, MSCP, TcolError
+from ._lib import BF16, BKPART, ECP, FP4, FP8, FP32, KCOL, KPART, MCOL, MSCP, TcolError
 
 __all__ = ["Params", "Solver", "TensColLoss", "init_weights", "descent", "mfma_peak", "conflicts_noalloc",
-           "KCOL", "ECP", "KPART", "BKPART", "MSCP",
+           "KCOL", "ECP", "KPART", "BKPART", "MSCP", "MCOL",
            "FP32", "BF16", "FP8", "FP4", "TcolError"]
 
 
@@ -38,11 +38,12 @@ class Params:
     bonus_diag: int = 1
     stop_on_legal: int = 1
     momentum: float = 0.0
+    max_demand: int = 0      # multicolouring (MCOL): the largest number of colours of a vertex
 
     def c_struct(self) -> _lib.GraphParams:
         return _lib.GraphParams(self.problem, self.precision, self.n, self.k, self.D, self.eta, self.rho,
                                 self.nb_iter, self.alpha, self.lam, self.beta, self.mu, self.nu,
-                                self.bonus_diag, self.stop_on_legal, self.momentum)
+                                self.bonus_diag, self.stop_on_legal, self.momentum, self.max_demand)
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
@@ -157,6 +158,24 @@ class Solver:
         gw = torch.empty((p.D, p.n, p.k), dtype=torch.float32, device=dev) if want_gw else None
         _lib.check(self._lib.tcol_loss_grad(self._ctx, g, _ptr(loss), _ptr(gs), _ptr(gw)), "tcol_loss_grad")
         return loss, gs, gw
+
+    def set_demand(self, demand, g: int = 0) -> None:
+        """Multicolouring demands c_i (n ints in 1..max_demand) of graph g (an MCOL graph)."""
+        import numpy as np
+        d = np.ascontiguousarray(np.asarray(demand, dtype=np.int32))
+        if d.shape != (self.params[g].n,):
+            raise ValueError(f"demand must have {self.params[g].n} entries")
+        _lib.check(self._lib.tcol_set_demand(self._ctx, g, d.ctypes.data_as(ctypes.c_void_p)), "tcol_set_demand")
+
+    def selection(self, g: int = 0):
+        """int16 [D, n, max(1, max_demand)]: each vertex's selected colours in decreasing weight, -1
+        past its demand (the argmax colouring for one colour per vertex)."""
+        torch = _torch()
+        p = self.params[g]
+        cm = max(1, p.max_demand) if p.problem == MCOL else 1
+        out = torch.empty((p.D, p.n, cm), dtype=torch.int16, device=self.W[g].device)
+        _lib.check(self._lib.tcol_selection(self._ctx, g, _ptr(out)), "tcol_selection")
+        return out
 
     def class_conflicts(self, g: int = 0):
         """S_d^T A S_d of every member (int32 [D, k, k]): edges between colour classes."""

@@ -11,7 +11,7 @@ TCOL_OK = 0
 STATUS = {0: "TCOL_OK", -1: "TCOL_EINVAL", -2: "TCOL_ESHAPE", -3: "TCOL_EGRAPH", -4: "TCOL_EHIP",
           -5: "TCOL_ENONFINITE", -6: "TCOL_ENOMEM", -7: "TCOL_ESTATE"}
 
-KCOL, ECP, KPART, BKPART, MSCP = 0, 1, 2, 3, 4
+KCOL, ECP, KPART, BKPART, MSCP, MCOL = 0, 1, 2, 3, 4, 5
 FP32, BF16, FP8, FP4 = 0, 1, 2, 3
 
 
@@ -21,7 +21,7 @@ class GraphParams(ctypes.Structure):
                 ("rho", ctypes.c_float), ("nb_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("lambda_", ctypes.c_float), ("beta", ctypes.c_float), ("mu", ctypes.c_float),
                 ("nu", ctypes.c_float), ("bonus_diag", ctypes.c_int32), ("stop_on_legal", ctypes.c_int32),
-                ("momentum", ctypes.c_float)]
+                ("momentum", ctypes.c_float), ("max_demand", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -49,7 +49,7 @@ EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_o
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
            "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
            "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters", "tcol_conflicts_noalloc",
-           "tcol_class_conflicts"]
+           "tcol_class_conflicts", "tcol_set_demand", "tcol_selection"]
 NPHASES = 10
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only",
           "gemm_as_store"]
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_loss_grad.argtypes = [P, i32, P, P, P]
     lib.tcol_mtilde.argtypes = [P, i32, P]
     lib.tcol_class_conflicts.argtypes = [P, i32, P]
+    lib.tcol_set_demand.argtypes = [P, i32, P]
+    lib.tcol_selection.argtypes = [P, i32, P]
     lib.tcol_get_t.argtypes = [P, i32, ctypes.POINTER(i64)]
     lib.tcol_set_t.argtypes = [P, i32, i64]
     lib.tcol_reset.argtypes = [P]

@@ -596,28 +596,35 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
         gemm_sweep<PREC, BM, NTW>(acc, (const uint8_t*)d.Aop + (size_t)m0 * ld,
                                   (const uint8_t*)d.Sop[pS] + (size_t)n0 * ld, ld, nst, lds);
         if (gather) {
-            __syncthreads();
             const int dlast = (ncol_end - 1) / k;
             const int nm = dlast - dfirst + 1;
             int16_t* ct = (int16_t*)lds;   // [nm][BM]
-            for (int e = tid; e < nm * BM; e += T::THREADS) {
-                const int dm = e / BM, r = e - dm * BM;
-                ct[e] = m0 + r < n ? colr[(size_t)(dfirst + dm) * cs + m0 + r] : (int16_t)-1;
-            }
-            // per element, through LDS counters of the tile's members
-            for (int e = tid; e < nm; e += T::THREADS) f2l[e] = 0;
-            __syncthreads();
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int ri = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
-#pragma unroll
-                    for (int nt = 0; nt < NTW; ++nt) {
-                        if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
-                            atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
-                    }
+            // multicolouring: each selected colour of a vertex in turn (slot sl of the selection)
+            const int CM = d.cmax;
+            for (int sl = 0; sl < CM; ++sl) {
+                __syncthreads();
+                const int16_t* __restrict__ src = CM > 1 ? d.sel + (size_t)sl * cs : colr;
+                const size_t rs = (size_t)CM * cs;   // row stride of a member
+                for (int e = tid; e < nm * BM; e += T::THREADS) {
+                    const int dm = e / BM, r = e - dm * BM;
+                    ct[e] = m0 + r < n ? src[(size_t)(dfirst + dm) * rs + m0 + r] : (int16_t)-1;
                 }
+                // per element, through LDS counters of the tile's members
+                if (sl == 0)
+                    for (int e = tid; e < nm; e += T::THREADS) f2l[e] = 0;
+                __syncthreads();
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ri = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
+#pragma unroll
+                        for (int nt = 0; nt < NTW; ++nt) {
+                            if (cm[nt] >= 0 && ct[(cm[nt] - dfirst) * BM + ri] == cl[nt])
+                                atomicAdd(&f2l[cm[nt] - dfirst], (int)acc[mt][nt][r]);
+                        }
+                    }
+            }
             __syncthreads();
             for (int e = tid; e < nm; e += T::THREADS)
                 if (f2l[e]) atomicAdd(&d.f2[dfirst + e], f2l[e]);

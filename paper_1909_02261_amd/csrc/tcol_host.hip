@@ -40,7 +40,7 @@ constexpr int kMaxLdsBytes = 160 * 1024;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum Buf {
-    B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
+    B_LUT_PEN, B_LUT_BON, B_LUT_KA, B_LUT_VB, B_DEM, B_SEL, B_W2, B_A8, B_AOP, B_POP, B_S0, B_S1, B_SP0, B_SP1, B_C0, B_C1,
     B_V0, B_V1, B_G, B_F2, B_F2P, B_FCOL, B_FEQ, B_F, B_PART, B_SNAP, B_CT, B_CLSV, B_CLSOFF, B_CINFO, B_SQ, B_VEL, B_COUNT
 };
 
@@ -50,6 +50,9 @@ struct Layout {
     int n_pad, rows_S, mt_ts, mt_T, mt_tiles;
 };
 
+
+// colours per vertex of a graph (its multicolouring demands' maximum, else 1)
+int cmax_of(const tcol_graph_params& p) { return p.problem == TCOL_MCOL ? std::max(1, (int)p.max_demand) : 1; }
 
 Layout make_layout(const tcol_graph_params& p) {
     Layout L{};
@@ -62,10 +65,15 @@ Layout make_layout(const tcol_graph_params& p) {
     const size_t n2 = (size_t)L.n_pad * L.n_pad;
     const size_t dnk = (size_t)p.D * p.n * p.k;
     size_t sz[B_COUNT];
-    sz[B_LUT_PEN] = sizeof(float) * (p.D + 1);
-    sz[B_LUT_BON] = sizeof(float) * (p.D + 1);
-    sz[B_LUT_KA] = sizeof(double) * (p.D + 1);
-    sz[B_LUT_VB] = sizeof(double) * (p.D + 1);
+    // tables over the group concentration 0 .. D cmax (cmax colours per vertex: multicolouring)
+    const int cm = cmax_of(p);
+    const size_t nlut = (size_t)p.D * cm + 1;
+    sz[B_LUT_PEN] = sizeof(float) * nlut;
+    sz[B_LUT_BON] = sizeof(float) * nlut;
+    sz[B_LUT_KA] = sizeof(double) * nlut;
+    sz[B_LUT_VB] = sizeof(double) * nlut;
+    sz[B_DEM] = sizeof(int32_t) * (size_t)p.n;
+    sz[B_SEL] = cm > 1 ? sizeof(int16_t) * ((size_t)p.D * cm * round_up(p.n, 64) + 64) : 0;
     sz[B_W2] = sizeof(float) * dnk;
     sz[B_A8] = n2;
     sz[B_AOP] = (size_t)L.n_pad * op_row_bytes(p.precision, L.n_pad);
@@ -79,7 +87,7 @@ Layout make_layout(const tcol_graph_params& p) {
     sz[B_F2P] = sizeof(int32_t) * (size_t)p.D * kF2Slots;
     sz[B_FCOL] = sz[B_FEQ] = sz[B_F] = sizeof(int64_t) * p.D;
     sz[B_PART] = sizeof(double) * 2 * (size_t)L.mt_tiles;
-    sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n;
+    sz[B_SNAP] = sizeof(int16_t) * (size_t)p.n * cm;
     sz[B_CT] = sizeof(int16_t) * (size_t)round_up(p.D, 8) * p.n;
     sz[B_CLSV] = sizeof(int16_t) * (size_t)p.D * round_up(p.n, 64);
     sz[B_CLSOFF] = sizeof(int32_t) * (size_t)p.D * (p.k + 1);
@@ -100,7 +108,14 @@ size_t head_bytes(int G) { return align_up(sizeof(GraphDev) * G) + align_up(size
 tcol_status check_params(const tcol_graph_params& p) {
     if (p.n < 1 || p.n > kMaxN || p.k < 1 || p.k > kMaxK || p.D < 1 || p.D > kMaxD) return TCOL_ESHAPE;
     if ((long long)p.D * p.k > (1LL << 26)) return TCOL_ESHAPE;
-    if (p.problem < TCOL_KCOL || p.problem > TCOL_MSCP) return TCOL_EINVAL;
+    if (p.problem < TCOL_KCOL || p.problem > TCOL_MCOL) return TCOL_EINVAL;
+    if (p.problem == TCOL_MCOL) {
+        if (p.max_demand < 1 || p.max_demand > kMaxDemand || p.max_demand > p.k) return TCOL_EINVAL;
+        if (p.momentum != 0.0f) return TCOL_EINVAL;
+        if (p.k > 1024) return TCOL_ESHAPE;
+    } else if (p.max_demand < 0 || p.max_demand > 1) {
+        return TCOL_EINVAL;
+    }
     if (!(p.momentum >= 0.0f && p.momentum < 1.0f)) return TCOL_EINVAL;
     if (p.precision < TCOL_FP32 || p.precision > TCOL_FP4) return TCOL_EINVAL;
     if (!(p.eta > 0.0f) || !(p.rho >= 1.0f) || p.nb_iter < 1) return TCOL_EINVAL;
@@ -137,6 +152,7 @@ struct tcol_ctx {
     GemmShape fshape{};             // fused-path tiling
     bool fused_ok = false;          // the fused path is available for these graphs
     bool any_momentum = false;      // some graph takes heavy-ball steps (no epilogue path)
+    bool any_mcol = false;          // some graph is a multicolouring (plain path only)
     int update_var = 0;             // row-update variant: bit 0 added fitness term, bit 1 momentum
     int ps_PM = 0, ps_threads = 0;  // sparse penalty: members per accumulator group, block size
     size_t ps_lds = 0;              // dynamic LDS of the sparse penalty kernel
@@ -276,6 +292,7 @@ static void pick_shapes(tcol_ctx* c) {
 // (D = 32, fp4; 15 % faster at n = 1000).  Penalty 3 drops the floors.
 constexpr int kSparseMinN = 2750, kSparseMinNPartition = 2048;
 static bool sparse_preferred(const tcol_graph_params& p, bool size_floor) {
+    if (p.problem == TCOL_MCOL) return false;
     if (p.problem == TCOL_KPART || p.problem == TCOL_BKPART) return !size_floor || p.n >= kSparseMinNPartition;
     return 4LL * p.D <= p.k && (!size_floor || p.n >= kSparseMinN);
 }
@@ -311,7 +328,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const int pen = c->opt.penalty;
-        c->hdesc[g].psparse = (pen == 2 || ((pen == 0 || pen == 3) && sparse_preferred(p, pen == 0))) ? 1 : 0;
+        c->hdesc[g].psparse =
+            p.problem != TCOL_MCOL && (pen == 2 || ((pen == 0 || pen == 3) && sparse_preferred(p, pen == 0))) ? 1 : 0;
         c->hdesc[g].ps_mode = pen == 2 ? 1 : 2;
         if (c->hdesc[g].psparse) {
             ps_k = std::max(ps_k, p.k);
@@ -379,6 +397,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
 
 // step schedule actually used: 2 needs the epilogue tiling, 1 needs the row-update kernel
 static int path_of(const tcol_ctx* c) {
+    if (c->any_mcol) return 0;
     if (c->opt.fused == 2 && c->fused_ok && !c->any_momentum) return 2;
     if (c->opt.fused >= 1 && update_rows_kpl(c->kmax)) return 1;
     return 0;
@@ -607,6 +626,7 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         c->nmax = std::max(c->nmax, q.n);
         if (q.momentum != 0.0f) c->any_momentum = true;
         if (q.momentum != 0.0f) c->update_var |= 2;
+        if (q.problem == TCOL_MCOL) c->any_mcol = true;
         if (prob_added(q.problem) && q.nu != 0.0f) c->update_var |= 1;
     }
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -709,15 +729,19 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         d.st = c->dstate + g;
         d.cT = (int16_t*)(b + L.off[B_CT]);
         d.cTs = round_up(q.D, 8);
+        d.cmax = cmax_of(q);
+        d.dem = (const int32_t*)(b + L.off[B_DEM]);
+        d.sel = d.cmax > 1 ? (int16_t*)(b + L.off[B_SEL]) : nullptr;
         d.cls_v = (int16_t*)(b + L.off[B_CLSV]);
         d.cls_off = (int32_t*)(b + L.off[B_CLSOFF]);
         d.cinfo = (int2*)(b + L.off[B_CINFO]);
         d.sq = (long long*)(b + L.off[B_SQ]);
         // look-up tables over the group concentration m = 0..D (host libm, FP64); for
         // partitioning the powers are of D - m (M replaced by J - M)
-        std::vector<float> lp(q.D + 1), lb(q.D + 1);
-        std::vector<double> lka(q.D + 1), lvb(q.D + 1);
-        for (int m = 0; m <= q.D; ++m) {
+        const int nlut = q.D * d.cmax + 1;
+        std::vector<float> lp(nlut), lb(nlut);
+        std::vector<double> lka(nlut), lvb(nlut);
+        for (int m = 0; m < nlut; ++m) {
             const double x = prob_partition(q.problem) ? (double)(q.D - m) : (double)m;
             lp[m] = (float)(2.0 * q.alpha * q.lambda * pow0(x, (double)q.alpha - 1.0));
             lb[m] = (float)(2.0 * q.beta * q.mu * pow0(x, (double)q.beta - 1.0));
@@ -729,6 +753,12 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
             hipMemcpy(b + L.off[B_LUT_KA], lka.data(), sizeof(double) * lka.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(b + L.off[B_LUT_VB], lvb.data(), sizeof(double) * lvb.size(), hipMemcpyHostToDevice) != hipSuccess)
             rc = init_fail("look-up table upload");
+        if (rc == TCOL_OK) {
+            // every demand 1 until tcol_set_demand
+            std::vector<int32_t> one(q.n, 1);
+            if (hipMemcpy(b + L.off[B_DEM], one.data(), sizeof(int32_t) * q.n, hipMemcpyHostToDevice) != hipSuccess)
+                rc = init_fail("demand upload");
+        }
         if (rc == TCOL_OK &&
             launch_pack_graph(A_dev[g], q.n, L.n_pad, q.precision, (uint8_t*)d.A8, d.Aop, dbad,
                               (unsigned long long*)(dbad + 2) + g, c->stream) != hipSuccess)
@@ -809,8 +839,9 @@ tcol_status tcol_step(tcol_ctx* c, int32_t max_steps, int32_t* steps_done, int32
         if (legal_d) legal_d[g] = st.legal_d;
         if (st.error) rc = st.error;
         if (colors_out_dev && colors_out_dev[g] && st.legal_d >= 0)
-            HIPCHK(hipMemcpyAsync(colors_out_dev[g], c->hdesc[g].snap, sizeof(int16_t) * c->params[g].n,
-                                  hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(colors_out_dev[g], c->hdesc[g].snap,
+                                  sizeof(int16_t) * c->params[g].n * c->hdesc[g].cmax, hipMemcpyDeviceToDevice,
+                                  c->stream));
     }
     if (steps_done) *steps_done = done;
     return rc;
@@ -843,12 +874,32 @@ tcol_status tcol_loss_grad(tcol_ctx* c, int32_t g, double* loss_dev, float* grad
 
 tcol_status tcol_class_conflicts(tcol_ctx* c, int32_t g, int32_t* C_dev) {
     if (!c || g < 0 || g >= c->G || !C_dev) return TCOL_EINVAL;
+    if (c->params[g].problem == TCOL_MCOL) return TCOL_EINVAL;
     // colours and S of the current W, then A.S stored to G (no penalty pass, no gather)
     HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
     HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, c->stream));
     HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, c->stream));
     HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 0, 1 | 4 | 16 | 128, 0, c->stream));
     HIPCHK(launch_class_conflicts(c->ddesc, g, c->params[g].D, c->params[g].k, C_dev, c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_set_demand(tcol_ctx* c, int32_t g, const int32_t* demand) {
+    if (!c || g < 0 || g >= c->G || !demand) return TCOL_EINVAL;
+    const tcol_graph_params& p = c->params[g];
+    if (p.problem != TCOL_MCOL) return TCOL_EINVAL;
+    for (int i = 0; i < p.n; ++i)
+        if (demand[i] < 1 || demand[i] > c->hdesc[g].cmax) return TCOL_EINVAL;
+    HIPCHK(hipMemcpyAsync(const_cast<int32_t*>(c->hdesc[g].dem), demand, sizeof(int32_t) * p.n, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TCOL_OK;
+}
+
+tcol_status tcol_selection(tcol_ctx* c, int32_t g, int16_t* sel_dev) {
+    if (!c || g < 0 || g >= c->G || !sel_dev) return TCOL_EINVAL;
+    HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, c->stream));
+    HIPCHK(launch_copy_selection(c->ddesc, g, sel_dev, c->stream));
     return TCOL_OK;
 }
 
@@ -1215,6 +1266,7 @@ extern "C" tcol_status tcol_conflicts_noalloc(const tcol_graph_params* p, const 
     if (!p || !A_dev || !W_dev) return TCOL_EINVAL;
     const tcol_status ps = check_params(*p);
     if (ps != TCOL_OK) return ps;
+    if (p->problem == TCOL_MCOL) return TCOL_EINVAL;
     const NoAllocLayout L = noalloc_layout(*p);
     if (L.total > kNoAllocScratch) {
         fprintf(stderr, "libtcol: tcol_conflicts_noalloc: n = %d, k = %d, D = %d needs %zu bytes of scratch, "
@@ -1239,6 +1291,7 @@ extern "C" tcol_status tcol_conflicts_noalloc(const tcol_graph_params* p, const 
     d.rows_S = L.rows_S;
     d.problem = p->problem;
     d.precision = kPrecFP4;
+    d.cmax = 1;   // one colour per vertex (multicolouring is rejected above)
     d.c1 = p->n / p->k;
     d.c2 = (p->n % p->k == 0) ? p->n / p->k : p->n / p->k + 1;
     d.ones_dev = (const unsigned long long*)(base + L.ones + 8);

@@ -12,7 +12,9 @@ constexpr int kPrecFP8 = 2;
 constexpr int kPrecFP4 = 3;
 
 // problems (the public enum's values)
-constexpr int kProbKCOL = 0, kProbECP = 1, kProbKPART = 2, kProbBKPART = 3, kProbMSCP = 4;
+constexpr int kProbKCOL = 0, kProbECP = 1, kProbKPART = 2, kProbBKPART = 3, kProbMSCP = 4, kProbMCOL = 5;
+// multicolouring: at most this many colours per vertex
+constexpr int kMaxDemand = 8;
 // partitioning: the fitness term is -A.S and the group concentration enters as D - Mt
 __host__ __device__ inline bool prob_partition(int p) { return p == kProbKPART || p == kProbBKPART; }
 // problems whose fitness and loss carry an added term (equity or colour cost)
@@ -105,7 +107,13 @@ struct GraphDev {
     int64_t* feq;             // [D] added fitness: f_eq, the colour cost, or 0
     int64_t* f;               // [D] fcol + feq
     double* part;             // [mt_tiles][2] kappa / varpi partial sums
-    int16_t* snap;            // [n] colouring of the legal member
+    int16_t* snap;            // [n] colouring of the legal member ([n][cmax] for multicolouring)
+    // multicolouring (cmax > 1, or problem kProbMCOL): vertex i takes dem[i] <= cmax colours;
+    // sel[d][s][i] (s < cmax, rows of cs) is the s-th colour of vertex i in member d, in
+    // decreasing weight, -1 past dem[i]; c[p] holds slot 0 (the argmax)
+    int cmax;
+    const int32_t* dem;
+    int16_t* sel;
     GraphState* st;
     int16_t* cT;              // [n][cTs] colours of the current iteration, vertex-major
     int cTs;                  // row stride of cT (D rounded up to 8)

@@ -116,6 +116,53 @@ __global__ __launch_bounds__(256) void k_pack_graph(const uint8_t* __restrict__ 
 
 // ------------------------------------------------------------ step 1 -----------
 
+// Multicolouring, step 1 for row r = (member m, vertex i): the dem[i] colours of largest weight,
+// one after the other (each the argmax of the colours not yet taken, lowest l on ties), into
+// sel[m][s][i] for s < dem[i] and -1 for the other slots; slot 0 also into c[pS].  16 lanes per
+// row; lane l16 keeps a bit per colour l16 + 16 q it holds that has been taken (k <= 1024).
+__device__ inline void select_row(const GraphDev& d, GraphState* st, int r, const float* w, int l16) {
+    const int k = d.k, n = d.n, CM = d.cmax;
+    const int m = r / n, i = r - m * n;
+    const int ci = d.dem[i];
+    int bad = 0;
+    for (int l = l16; l < k; l += 16)
+        if (!finite_f(w[l])) bad = 1;
+    for (int sh = 8; sh >= 1; sh >>= 1) bad |= __shfl_xor(bad, sh, 16);
+    if (bad) {
+        if (l16 == 0) {
+            atomicExch(&st->error, -5);
+            atomicExch(&st->stopped, 1);
+            d.c[st->pS][(size_t)m * d.cs + i] = 0;
+        }
+        return;
+    }
+    unsigned long long taken = 0;
+    for (int sl = 0; sl < CM; ++sl) {
+        float best = -INFINITY;
+        int bi = 0x7FFFFFFF;
+        int q = 0;
+        for (int l = l16; l < k; l += 16, ++q)
+            if (!((taken >> q) & 1ull) && w[l] > best) {
+                best = w[l];
+                bi = l;
+            }
+        for (int sh = 8; sh >= 1; sh >>= 1) {
+            const float ob = __shfl_xor(best, sh, 16);
+            const int oi = __shfl_xor(bi, sh, 16);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        const int pick = (sl < ci && bi < k) ? bi : -1;
+        if (pick >= 0 && (pick & 15) == l16) taken |= 1ull << (pick >> 4);
+        if (l16 == 0) {
+            d.sel[((size_t)m * CM + sl) * d.cs + i] = (int16_t)pick;
+            if (sl == 0) d.c[st->pS][(size_t)m * d.cs + i] = (int16_t)pick;
+        }
+    }
+}
+
 // c_d(i) = argmax_l W[d,i,l], lowest l on ties; 16 lanes per row.
 __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd, int G, int total_rows,
                                                 int honor_stop) {
@@ -127,6 +174,10 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
     if (honor_stop && st->stopped) return;
     const int r = row - d.row_begin;
     const float* w = d.W[st->pW] + (size_t)r * d.k;
+    if (d.cmax > 1) {
+        select_row(d, st, r, w, l16);
+        return;
+    }
     float best = -INFINITY;
     int bi = 0x7FFFFFFF;
     int bad = 0;
@@ -240,6 +291,15 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
             atomicAdd(&cnt[x], 1);
             atomicAdd(&cw[wv * k + x], 1);
             cT[(size_t)i * cTs + m] = x;
+        }
+    } else if (d.cmax > 1) {
+        // multicolouring: every selected colour of the vertex counts in its class
+        for (int i = tid; i < n; i += 256) {
+            for (int sl = 0; sl < d.cmax; ++sl) {
+                const int16_t x = d.sel[((size_t)m * d.cmax + sl) * d.cs + i];
+                if (x >= 0) atomicAdd(&cnt[x], 1);
+            }
+            cT[(size_t)i * cTs + m] = gview(c)[i];
         }
     } else {
         for (int i = tid; i < n; i += 256) {
@@ -719,18 +779,21 @@ __device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int 
     if (row >= d.ncols) return;
     const int dm = row / d.k;
     const int l = row - dm * d.k;
-    const int16_t* c = d.c[p] + (size_t)dm * d.cs;
     const int j0 = cg * 16;
-    uint32_t mask = 0;   // bit q set when column j0+q has colour l
+    uint32_t mask = 0;   // bit q set when column j0+q has colour l (one of its colours: multicolouring)
+    const int CM = d.cmax;
     if (j0 < d.n) {
-        // 16 colours in two 16-byte loads (rows are padded to 64 entries)
-        const uint4 a = *(const uint4*)(c + j0);
-        const uint4 b = *(const uint4*)(c + j0 + 8);
-        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        for (int sl = 0; sl < CM; ++sl) {
+            const int16_t* c = CM > 1 ? d.sel + ((size_t)dm * CM + sl) * d.cs : d.c[p] + (size_t)dm * d.cs;
+            // 16 colours in two 16-byte loads (rows are padded to 64 entries)
+            const uint4 a = *(const uint4*)(c + j0);
+            const uint4 b = *(const uint4*)(c + j0 + 8);
+            const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int col = (int)((w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
-            if (j0 + q < d.n && col == l) mask |= 1u << q;
+            for (int q = 0; q < 16; ++q) {
+                const int col = (int)((w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
+                if (j0 + q < d.n && col == l) mask |= 1u << q;
+            }
         }
     }
     const size_t off = (size_t)row * d.n_pad + j0;
@@ -817,28 +880,55 @@ __device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags,
     for (int a = 0; a < PT; ++a)
 #pragma unroll
         for (int q = 0; q < PT; ++q) cnt[a][q] = 0;
-    for (int dbase = 0; dbase < d.D; dbase += kMtChunk) {
-        const int dn = min(kMtChunk, d.D - dbase);
+    // rows of colours: members (one colour per vertex), or for multicolouring (member, slot)
+    // pairs of the selection, whose slots of a member must meet in one chunk
+    const int CM = d.cmax;
+    const int16_t* base = CM > 1 ? d.sel : d.c[p];
+    const int vrows = d.D * CM;
+    const int chunk = (kMtChunk / CM) * CM;
+    for (int dbase = 0; dbase < vrows; dbase += chunk) {
+        const int dn = min(chunk, vrows - dbase);
         __syncthreads();
         for (int e = threadIdx.x; e < dn * TS; e += 256) {
             const int dm = e / TS, x = e - dm * TS;
-            const int16_t* cr = d.c[p] + (size_t)(dbase + dm) * d.cs;
-            // out-of-range vertices get distinct sentinels so they never match
-            ci[dm][x] = (i0 + x < d.n) ? cr[i0 + x] : (int16_t)-1;
-            cj[dm][x] = (j0 + x < d.n) ? cr[j0 + x] : (int16_t)-2;
+            const int16_t* cr = base + (size_t)(dbase + dm) * d.cs;
+            // out-of-range vertices and unselected slots get distinct sentinels so they never match
+            const int16_t a = (i0 + x < d.n) ? cr[i0 + x] : (int16_t)-1;
+            const int16_t b = (j0 + x < d.n) ? cr[j0 + x] : (int16_t)-2;
+            ci[dm][x] = a < 0 ? (int16_t)-1 : a;
+            cj[dm][x] = b < 0 ? (int16_t)-2 : b;
         }
         __syncthreads();
-        for (int dm = 0; dm < dn; ++dm) {
-            int16_t av[PT], bv[PT];
+        if (CM == 1) {
+            for (int dm = 0; dm < dn; ++dm) {
+                int16_t av[PT], bv[PT];
 #pragma unroll
-            for (int a = 0; a < PT; ++a) {
-                av[a] = ci[dm][ty * PT + a];
-                bv[a] = cj[dm][tx * PT + a];
+                for (int a = 0; a < PT; ++a) {
+                    av[a] = ci[dm][ty * PT + a];
+                    bv[a] = cj[dm][tx * PT + a];
+                }
+#pragma unroll
+                for (int a = 0; a < PT; ++a)
+#pragma unroll
+                    for (int q = 0; q < PT; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
             }
+        } else {
+            // the colours i and j share within each member: every slot against every slot
+            for (int mm = 0; mm < dn; mm += CM)
+                for (int s1 = 0; s1 < CM; ++s1) {
+                    int16_t av[PT];
 #pragma unroll
-            for (int a = 0; a < PT; ++a)
+                    for (int a = 0; a < PT; ++a) av[a] = ci[mm + s1][ty * PT + a];
+                    for (int s2 = 0; s2 < CM; ++s2) {
+                        int16_t bv[PT];
 #pragma unroll
-                for (int q = 0; q < PT; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
+                        for (int q = 0; q < PT; ++q) bv[q] = cj[mm + s2][tx * PT + q];
+#pragma unroll
+                        for (int a = 0; a < PT; ++a)
+#pragma unroll
+                            for (int q = 0; q < PT; ++q) cnt[a][q] += (av[a] == bv[q]) ? 1 : 0;
+                    }
+                }
         }
     }
     const bool mirror = ti != tj;
@@ -1033,8 +1123,16 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
     const int ld = best == 0x7FFFFFFF ? -1 : best;
     const bool stop = ld >= 0 && d.stop_on_legal;
     if (stop) {
-        const int16_t* c = d.c[p] + (size_t)ld * d.cs;
-        for (int i = threadIdx.x; i < d.n; i += blockDim.x) d.snap[i] = c[i];
+        if (d.cmax > 1) {
+            // multicolouring: the legal member's selection as [i][s]
+            for (int e = threadIdx.x; e < d.n * d.cmax; e += blockDim.x) {
+                const int i = e / d.cmax, sl = e - i * d.cmax;
+                d.snap[e] = d.sel[((size_t)ld * d.cmax + sl) * d.cs + i];
+            }
+        } else {
+            const int16_t* c = d.c[p] + (size_t)ld * d.cs;
+            for (int i = threadIdx.x; i < d.n; i += blockDim.x) d.snap[i] = c[i];
+        }
         if (threadIdx.x == 0) {
             st->legal_d = ld;
             st->stopped = 1;
@@ -1315,6 +1413,21 @@ __global__ void k_copy_report(const GraphDev* __restrict__ gd, int g, int16_t* c
             if (fcol) fcol[e] = d.fcol[e];
             if (feq) feq[e] = d.feq[e];
         }
+    }
+}
+
+// graph g's selection as [d][i][s]: the cmax colours of each vertex (slot 0 the argmax, -1 past
+// the demand), or the argmax colouring when cmax = 1
+__global__ void k_copy_selection(const GraphDev* __restrict__ gd, int g, int16_t* __restrict__ out) {
+    const GraphDev& d = gd[g];
+    const int CM = d.cmax, n = d.n;
+    const int16_t* c = d.c[d.st->pS];
+    const size_t total = (size_t)d.D * n * CM;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t mi = e / CM;
+        const int sl = (int)(e - mi * CM);
+        const size_t m = mi / n, i = mi - m * n;
+        out[e] = CM > 1 ? d.sel[((size_t)m * CM + sl) * d.cs + i] : c[m * d.cs + i];
     }
 }
 
@@ -1637,6 +1750,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     const size_t words = bytes / 16;
     const int blocks = (int)std::min<size_t>((words + 255) / 256, 2048);
     hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, s, (uint4*)p, words);
+    TCOL_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_copy_selection(const GraphDev* gd, int g, int16_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_selection, dim3(512), dim3(256), 0, s, gd, g, out);
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

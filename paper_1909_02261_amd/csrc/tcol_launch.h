@@ -45,6 +45,8 @@ hipError_t launch_advance(const GraphDev* gd, int G, hipStream_t s);
 hipError_t launch_loss(const GraphDev* gd, int g, int ntiles, double* out, hipStream_t s);
 hipError_t launch_copy_report(const GraphDev* gd, int g, int16_t* colors, int64_t* fcol, int64_t* feq,
                               hipStream_t s);
+// graph g's selection as [d][i][s] (s < cmax), -1 past a vertex's demand
+hipError_t launch_copy_selection(const GraphDev* gd, int g, int16_t* out, hipStream_t s);
 hipError_t launch_state(const GraphDev* gd, int G, int op, int g_only, long long t, hipStream_t s);
 // class-conflict matrices S_d^T (A.S_d) of graph g ([D][k][k] int32) from G = A.S and the colours
 hipError_t launch_class_conflicts(const GraphDev* gd, int g, int D, int k, int32_t* out, hipStream_t s);

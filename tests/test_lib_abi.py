@@ -150,3 +150,18 @@ def test_noalloc_rejects_what_its_scratch_cannot_hold(lib):
     assert lib.tcol_conflicts_noalloc(None, dummy, dummy, None, None, None, None) == -1
     bad = params(k=0)
     assert lib.tcol_conflicts_noalloc(ctypes.byref(bad), dummy, dummy, None, None, None, None) == -2
+
+
+def test_multicolouring_parameters(lib):
+    """Multicolouring (problem 5) needs 1 <= max_demand <= min(8, k) and no momentum; other
+    problems take max_demand 0 or 1."""
+    assert ws(lib, params(problem=5, max_demand=3))[0] == 0
+    assert ws(lib, params(problem=5, max_demand=1))[0] == 0
+    assert ws(lib, params(problem=5, max_demand=0))[0] == -1
+    assert ws(lib, params(problem=5, max_demand=9, k=20))[0] == -1
+    assert ws(lib, params(problem=5, max_demand=4, k=3))[0] == -1
+    assert ws(lib, params(problem=5, max_demand=2, momentum=0.5))[0] == -1
+    assert ws(lib, params(problem=0, max_demand=2))[0] == -1
+    assert ws(lib, params(problem=6))[0] == -1
+    # the selection slots make the workspace grow with max_demand
+    assert ws(lib, params(problem=5, max_demand=4))[1] > ws(lib, params(problem=5, max_demand=1))[1]
