@@ -496,9 +496,31 @@ __device__ inline int xcd_remap(int b, int nb) {
     return x * q + min(x, r) + i;
 }
 
+// Block -> tile of a batch of graphs (G > 1): the tiles, in decreasing cost, are dealt to the
+// XCDs in chunks of 16 consecutive tiles (in the main 4 row tiles by 4 column tiles of one graph), so every
+// XCD starts on the longest tiles and the short ones fill the end; a single graph keeps
+// xcd_remap's contiguous range per XCD
+__device__ inline int batch_remap(int b, int nb, int G) {
+    if (G == 1) return xcd_remap(b, nb);
+    constexpr int C = 16;
+    const int full = nb / (8 * C) * (8 * C);
+    if (b >= full) return b;
+    const int x = b & 7, i = b >> 3;
+    return ((i / C) * 8 + x) * C + (i % C);
+}
+
 template <int MODE>
 __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, int& tm, int& tn) {
-    g = find_graph(gd, G, tile, [](const GraphDev& x) { return x.gm_begin[MODE]; });
+    // the graphs' tile ranges follow one another in decreasing tile cost (K = n_pad), not in
+    // graph order, so the longest tiles of a batch are dispatched first
+    g = 0;
+    for (int x = 0; x < G; ++x) {
+        const int b = gd[x].gm_begin[MODE];
+        if (tile >= b && tile < b + gd[x].gm_tm[MODE] * gd[x].gm_tn[MODE]) {
+            g = x;
+            break;
+        }
+    }
     const GraphDev& d = gd[g];
     const int local = tile - d.gm_begin[MODE];
     const int TM = d.gm_tm[MODE], TN = d.gm_tn[MODE];
@@ -522,7 +544,7 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int* f2l = (int*)(lds + T::CT_BYTES);            // BN + 2 gather counters (after the colours)
 
-    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    const int tile = batch_remap(blockIdx.x, total_tiles, G);
     int g, tm, tn;
     decode_tile<MODE>(gd, G, tile, g, tm, tn);
     const GraphDev& d = gd[g];

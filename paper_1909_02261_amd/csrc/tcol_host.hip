@@ -352,7 +352,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         }
     }
     c->prep_lds = prep_lds(c->kmax, c->nmax, ps_k > 0);
-    int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0, gm0 = 0, gm1 = 0;
+    int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0;
     for (int g = 0; g < c->G; ++g) {
         const tcol_graph_params& p = c->params[g];
         const Layout& L = c->layouts[g];
@@ -371,15 +371,27 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         const long long items = (long long)p.D * p.k * (L.n_pad / 16);
         d.ex_cblocks = (int)((items + 255) / 256);
         ex += d.ex_cblocks;
-        d.gm_begin[0] = gm0;
         d.gm_tm[0] = L.n_pad / c->shape.bm;
         d.gm_tn[0] = ceil_div(p.D * p.k, BN0);
-        gm0 += d.gm_tm[0] * d.gm_tn[0];
         if (c->fused_ok) {
             d.gm_mpb = BN1 / p.k;
-            d.gm_begin[1] = gm1;
             d.gm_tm[1] = L.n_pad / c->fshape.bm;
             d.gm_tn[1] = ceil_div(p.D, d.gm_mpb);
+        }
+    }
+    // contraction tiles: the graphs' ranges in decreasing K (= n_pad, the length of a tile's
+    // sweep), so a batch's longest tiles start first and short ones fill the end
+    std::vector<int> order(c->G);
+    for (int g = 0; g < c->G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return c->layouts[a].n_pad > c->layouts[b].n_pad; });
+    int gm0 = 0, gm1 = 0;
+    for (int g : order) {
+        GraphDev& d = c->hdesc[g];
+        d.gm_begin[0] = gm0;
+        gm0 += d.gm_tm[0] * d.gm_tn[0];
+        if (c->fused_ok) {
+            d.gm_begin[1] = gm1;
             gm1 += d.gm_tm[1] * d.gm_tn[1];
         }
     }
