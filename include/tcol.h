@@ -119,7 +119,12 @@ typedef struct {
                                contraction, update as separate kernels every iteration);
                                1 = fast path (default): the update kernel also colours the
                                updated rows, no separate argmax pass (k <= 576, else the plain
-                               order); the penalty term as `penalty` selects;
+                               order); the penalty term as `penalty` selects; a graph whose
+                               penalty may take the sparse rows (and takes no heavy-ball steps)
+                               gets its row update from the sparse-rows kernel in every
+                               iteration, into a second weight buffer that the stop rule
+                               accepts or discards, and its A.S counts of the sparse
+                               iterations are stored as uint16;
                                2 = epilogue path: the contraction kernel itself applies softmax,
                                gradient, update and the next argmax, into a second weight
                                buffer (k <= 576) */
@@ -279,11 +284,13 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * and writes the average milliseconds per iteration of each phase to
  * ms[TCOL_NPHASES]: 0 argmax colours, 1 class sizes, 2 one-hot S expansion,
  * 3 penalty (group concentration + dense operand, or the sparse rows, which on
- * the fast path run after the contraction and add their rows to G),
+ * the fast path run after the contraction and add their rows to G, or for the
+ * graphs whose row update rides on them, update the rows themselves),
  * 4 contraction A.S (+ dense penalty pass)
  * with fitness gather and, on the fused path, the update epilogue,
- * 5 fitness / stop rule, 6 softmax straight-through update (separate path),
- * 7 counter advance.  Phase 4 is timed separately as `steps` contraction
+ * 5 fitness / stop rule, 6 softmax straight-through update (the separate row
+ * update kernel; near zero on the fast path when every graph's update rides on
+ * the sparse rows), 7 counter advance.  Phase 4 is timed separately as `steps` contraction
  * launches back to back on the operands of the last iteration (one event pair,
  * so launch gaps do not count), with the f_color gather and the dense penalty
  * pass unless penalty = 2.  When as_only is non-zero it then also times `steps`
@@ -291,7 +298,8 @@ tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
  * gather, no store; W unchanged) into ms[8], and `steps` launches of the A.S
  * pass with the store of G (the form the contraction takes on the fast
  * schedule in iterations whose penalty the sparse rows take, which then gather
- * f_color themselves) into ms[9]; otherwise ms[8] = ms[9] = 0.  Synchronises
+ * f_color themselves: the uint16 counts for graphs whose row update rides on
+ * the sparse rows) into ms[9]; otherwise ms[8] = ms[9] = 0.  Synchronises
  * the stream.
  * Errors: TCOL_EINVAL, TCOL_EHIP. */
 #define TCOL_NPHASES 10

@@ -509,20 +509,9 @@ __device__ inline int batch_remap(int b, int nb, int G) {
     return ((i / C) * 8 + x) * C + (i % C);
 }
 
+// tile `local` of one graph's contraction -> (row tile, column tile)
 template <int MODE>
-__device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, int& tm, int& tn) {
-    // the graphs' tile ranges follow one another in decreasing tile cost (K = n_pad), not in
-    // graph order, so the longest tiles of a batch are dispatched first
-    g = 0;
-    for (int x = 0; x < G; ++x) {
-        const int b = gd[x].gm_begin[MODE];
-        if (tile >= b && tile < b + gd[x].gm_tm[MODE] * gd[x].gm_tn[MODE]) {
-            g = x;
-            break;
-        }
-    }
-    const GraphDev& d = gd[g];
-    const int local = tile - d.gm_begin[MODE];
+__device__ inline void local_tile(const GraphDev& d, int local, int& tm, int& tn) {
     const int TM = d.gm_tm[MODE], TN = d.gm_tn[MODE];
     // groups of 4 row tiles sweep the column tiles together (measured faster than
     // groups of 8, which cut the L2 misses by a third but not the time)
@@ -535,8 +524,24 @@ __device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, 
     tn = w / rows_in;
 }
 
+template <int MODE>
+__device__ inline void decode_tile(const GraphDev* gd, int G, int tile, int& g, int& tm, int& tn) {
+    // the graphs' tile ranges follow one another in decreasing tile cost (K = n_pad), not in
+    // graph order, so the longest tiles of a batch are dispatched first
+    g = 0;
+    for (int x = 0; x < G; ++x) {
+        const int b = gd[x].gm_begin[MODE];
+        if (tile >= b && tile < b + gd[x].gm_tm[MODE] * gd[x].gm_tn[MODE]) {
+            g = x;
+            break;
+        }
+    }
+    local_tile<MODE>(gd[g], tile - gd[g].gm_begin[MODE], tm, tn);
+}
+
+// One block tile (row tile tm, column tile tn) of graph g's contraction.
 template <int PREC, int BM, int NTW, int MODE>
-__device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G, int total_tiles, int honor_stop,
+__device__ __forceinline__ void gemm_tile(const GraphDev* __restrict__ gd, int g, int tm, int tn, int honor_stop,
                                           int passes, int cstage) {
     using T = Tile<BM, NTW>;
     constexpr int MT = T::MT;
@@ -544,9 +549,6 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     int* f2l = (int*)(lds + T::CT_BYTES);            // BN + 2 gather counters (after the colours)
 
-    const int tile = batch_remap(blockIdx.x, total_tiles, G);
-    int g, tm, tn;
-    decode_tile<MODE>(gd, G, tile, g, tm, tn);
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -671,6 +673,23 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
     }
     if (!(passes & 4)) return;
     if constexpr (MODE == 0) {
+        if (sparse_pen && d.pfuse && (passes & 32)) {
+            // the sparse-rows launch takes this iteration's penalty and row update: it reads the
+            // A.S counts (integers below n <= 32768) as uint16, half the bytes of fp32
+            uint16_t* __restrict__ G16 = (uint16_t*)Gg;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = m0 + wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
+                    if (i < n) {
+#pragma unroll
+                        for (int nt = 0; nt < NTW; ++nt)
+                            if (cm[nt] >= 0) G16[((size_t)cm[nt] * n + i) * k + cl[nt]] = (uint16_t)acc[mt][nt][r];
+                    }
+                }
+            return;
+        }
         // G[d][i][l] = acc (sparse penalty rows, when present, are added afterwards)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -775,6 +794,15 @@ __device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G
             }
         }
     }
+}
+
+template <int PREC, int BM, int NTW, int MODE>
+__device__ __forceinline__ void gemm_body(const GraphDev* __restrict__ gd, int G, int total_tiles, int honor_stop,
+                                          int passes, int cstage) {
+    const int tile = batch_remap(blockIdx.x, total_tiles, G);
+    int g, tm, tn;
+    decode_tile<MODE>(gd, G, tile, g, tm, tn);
+    gemm_tile<PREC, BM, NTW, MODE>(gd, g, tm, tn, honor_stop, passes, cstage);
 }
 
 // ------------------------------------------------------------- dispatch ------

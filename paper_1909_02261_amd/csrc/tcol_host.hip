@@ -155,6 +155,8 @@ struct tcol_ctx {
     bool any_mcol = false;          // some graph is a multicolouring (plain path only)
     int update_var = 0;             // row-update variant: bit 0 added fitness term, bit 1 momentum
     int ps_PM = 0, ps_threads = 0;  // sparse penalty: members per accumulator group, block size
+    int ps_kw = 0;                  // sparse penalty: values per lane of the fused row update (0: none)
+    bool all_pfuse = false;         // every graph's row update rides on the sparse-rows launch
     size_t ps_lds = 0;              // dynamic LDS of the sparse penalty kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
     int total_ps = 0;               // blocks of the sparse penalty kernel (0: no graph uses it)
@@ -314,6 +316,8 @@ static bool pick_sparse(int kmax, int dmax, int nmax, int& PM, int& threads) {
     return false;
 }
 
+static int path_of(const tcol_ctx* c);
+
 // recompute flattened work offsets for the tile shapes and upload the descriptors
 static tcol_status rebuild_schedule(tcol_ctx* c) {
     pick_shapes(c);
@@ -337,12 +341,24 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
             ps_n = std::max(ps_n, p.n);
         }
     }
-    c->ps_PM = c->ps_threads = 0;
+    c->ps_PM = c->ps_threads = c->ps_kw = 0;
     c->ps_lds = 0;
+    for (int g = 0; g < c->G; ++g) c->hdesc[g].pfuse = 0;
     if (ps_k > 0) {
         // graphs too large for the kernel's LDS take the dense pass
         int PM = 0, threads = 0;
         if (pick_sparse(ps_k, ps_D, ps_n, PM, threads)) {
+            // on the fast path the sparse rows also take the row update of their graphs (one
+            // wave per member of a group, so at most threads / 64 members per group), in every
+            // iteration, unless a graph takes heavy-ball steps (its velocity is updated in place,
+            // which an update discarded by the stop rule could not undo)
+            const int kw = penalty_sparse_kw(ps_k);
+            if (path_of(c) == 1 && kw > 0) {
+                for (int g = 0; g < c->G; ++g)
+                    if (c->hdesc[g].psparse && c->params[g].momentum == 0.0f) c->hdesc[g].pfuse = 1;
+                c->ps_kw = kw;
+                PM = std::min(PM, threads / 64 / 8 * 8);
+            }
             c->ps_PM = PM;
             c->ps_threads = threads;
             c->ps_lds = penalty_sparse_lds(PM, ps_k, ps_D, ps_n);
@@ -351,6 +367,9 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
             ps_k = 0;
         }
     }
+    c->all_pfuse = true;
+    for (int g = 0; g < c->G; ++g)
+        if (!c->hdesc[g].pfuse) c->all_pfuse = false;
     c->prep_lds = prep_lds(c->kmax, c->nmax, ps_k > 0);
     int rows = 0, mem = 0, pg = 0, mt = 0, ex = 0;
     for (int g = 0; g < c->G; ++g) {
@@ -443,7 +462,7 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 // them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
     if (c->total_ps > 0 && path_of(c) == 2)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 0, 0, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, 0, c->ps_lds, 1, 0, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
@@ -456,12 +475,15 @@ static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
 }
 
 // fast path: the sparse rows added to the contraction's G (they also gather f_color for the
-// graphs that take them, into slots the fitness folds); with `fitness` the fitness launch
-// follows, else the caller launches it
+// graphs that take them, into slots the fitness folds), and for graphs with pfuse the row
+// update, in every iteration, into the other W and colour buffers; with `fitness` the fitness
+// launch follows (which accepts those updates unless the graph stops), else the caller
+// launches it
 static hipError_t enqueue_sparse_add(tcol_ctx* c, bool fitness, hipStream_t s) {
     if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_lds, 1, 1, 0, s));
-    if (fitness) HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFoldSparse, -1, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_kw, c->ps_lds, 1, 1, 0,
+                                     s));
+    if (fitness) HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFoldSparse | kFlagFlipFused, -1, s));
     return hipSuccess;
 }
 
@@ -485,9 +507,11 @@ static hipError_t enqueue_step_fast(tcol_ctx* c, bool advance_prev, bool advance
                        merged ? c->total_ex : 0, advance_prev ? 1 : 0, s));
     HIPRET(enqueue_penalty(c, s));
     if (!merged) HIPRET(launch_expand(c->ddesc, c->G, c->total_ex, 1, 0, 1, s));
-    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7 | 64, 0, s));
+    HIPRET(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, 7 | 32 | 64, 0, s));
     HIPRET(enqueue_sparse_add(c, true, s));
-    HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
+    // the row update of the graphs whose update did not ride on the sparse rows
+    if (!c->all_pfuse)
+        HIPRET(launch_update_rows(c->ddesc, c->G, c->total_rows, c->kmax, c->update_var, 1, 0, -1, nullptr, nullptr, s));
     if (advance_own) HIPRET(launch_advance(c->ddesc, c->G, s));
     return hipSuccess;
 }
@@ -987,14 +1011,15 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         if (path == 2)
             HIPCHK(launch_gemm(c->fshape, c->ddesc, c->G, c->total_gm[1], 1, 7, 0, s));
         else
-            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7 | 64, 0, s));
+            HIPCHK(launch_gemm(c->shape, c->ddesc, c->G, c->total_gm[0], 1, path == 0 ? 15 : 7 | 32 | 64, 0, s));
         HIPCHK(hipEventRecord(ev[5], s));
         if (path == 1) HIPCHK(enqueue_sparse_add(c, false, s));
         HIPCHK(hipEventRecord(ev[6], s));
         HIPCHK(launch_fitness(c->ddesc, c->G, 1,
-                              path == 2 ? kFlagFused : (path == 0 ? kFlagPlainPen : kFlagFoldSparse), -1, s));
+                              path == 2 ? kFlagFused : (path == 0 ? kFlagPlainPen : kFlagFoldSparse | kFlagFlipFused),
+                              -1, s));
         HIPCHK(hipEventRecord(ev[7], s));
-        if (path != 2) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
+        if (path != 2 && !(path == 1 && c->all_pfuse)) HIPCHK(launch_update_any(c, 1, 0, -1, nullptr, nullptr, s));
         HIPCHK(hipEventRecord(ev[8], s));
         if (path != 2) HIPCHK(launch_advance(c->ddesc, c->G, s));
         HIPCHK(hipEventRecord(ev[9], s));
@@ -1039,10 +1064,13 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
         HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 0, s));
         HIPCHK(launch_prep(c->ddesc, c->G, c->total_mem, c->prep_lds, 0, 0, 0, 0, 0, s));
         HIPCHK(launch_expand(c->ddesc, c->G, c->total_ex, 0, 0, 0, s));
-        // A.S alone, then with the G store too (the form of an iteration without the dense
-        // penalty pass: on the fast path the sparse rows take the gather; the store is
-        // idempotent)
-        const int forms[2] = {1 | 128, 1 | 4 | 16 | 128};
+        // A.S alone, then with the G store too (the form of an iteration on the sparse rows: they
+        // take the gather, and on the fast path the store is the uint16 counts for the graphs
+        // whose row update rides on them; the store is idempotent).  The state is set to an
+        // iteration on the sparse rows for this timing (the next iteration's class-size kernel
+        // takes the choice again)
+        HIPCHK(launch_state(c->ddesc, c->G, 5, -1, 0, s));
+        const int forms[2] = {1 | 128, 1 | 4 | 16 | 128 | (path == 1 ? 32 : 0)};
         for (int f = 0; f < 2; ++f) {
             HIPCHK(hipEventRecord(ev[0], s));
             for (int it = 0; it < steps; ++it)

@@ -125,6 +125,10 @@ struct GraphDev {
     int2* cinfo;              // [D][cs] start in cls_v and size of the class of vertex i in member d
     long long* sq;            // [D] sum over colours of the squared class sizes of each member
     int ps_mode;              // sparse penalty: 1 every iteration, 2 when the classes are small
+    int pfuse;                // fast path: the sparse-rows launch also takes this graph's row update
+                              // (softmax, straight-through gradient, update, next colours) in
+                              // every iteration, writing the other W and colour buffers, and the
+                              // A.S counts of its sparse iterations are stored as uint16 in G
     // flattened work offsets (prefix sums over graphs)
     int row_begin;            // rows (d, i) for row kernels
     int mem_begin;            // members d for per-member kernels
@@ -152,6 +156,9 @@ enum : int {
                             // iteration takes the sparse rows to the fitness launch that follows
     kFlagFoldSparse = 256,  // fitness kernel of the fast path: graphs whose iteration took the
                             // sparse rows have their f_color in the rows' slots (f2p)
+    kFlagFlipFused = 512,   // fitness kernel of the fast path: graphs whose row update rode on the
+                            // sparse-rows launch (pfuse) accept it by flipping their W and colour
+                            // buffers, unless they stop
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

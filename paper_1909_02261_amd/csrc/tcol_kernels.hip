@@ -243,17 +243,19 @@ __device__ inline void advance_graph(GraphState* st) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
-                                              int next, int decide, int ex_blocks, int advance_prev) {
-    extern __shared__ int prep_sh[];
-    __shared__ int part[257];
-    const int mem = blockIdx.x;
-    if (mem >= total_mem) {
-        // blocks past the members: the expansion of the current colours (gate 1), with the
-        // same stop decision as the member blocks
-        if (mem - total_mem < ex_blocks) expand_block(gd, G, mem - total_mem, honor_stop, next, 1, advance_prev);
-        return;
-    }
+constexpr int kPrepScratch = 288;   // words of the class-size block's LDS scratch
+
+// the class-size kernel's block for member `mem` (flattened over the graphs)
+__device__ void prep_member(const GraphDev* __restrict__ gd, int G, int mem, int honor_stop, int next, int decide,
+                            int advance_prev) {
+    // dynamic LDS (prep_lds): a scratch of kPrepScratch words (the scan's run sums, two
+    // four-wave reductions, the ticket result), then the counts and class lists
+    extern __shared__ int prep_dyn[];
+    int* part = prep_dyn;                                     // [257]
+    long long* fsum = (long long*)(prep_dyn + 260);           // [4]
+    long long* qsum = fsum + 4;                               // [4]
+    int* last_block_p = prep_dyn + 276;
+    int* prep_sh = prep_dyn + kPrepScratch;
     const GraphDev& d = gd[find_graph(gd, G, mem, [](const GraphDev& x) { return x.mem_begin; })];
     GraphState* st = d.st;
     // Whether the graph is stopped for this iteration, read before anything in this launch
@@ -327,7 +329,6 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
             }
         }
         for (int sh = 32; sh >= 1; sh >>= 1) fe += __shfl_xor(fe, sh);
-        __shared__ long long fsum[4];
         if ((tid & 63) == 0) fsum[tid >> 6] = fe;
         __syncthreads();
         if (tid == 0) d.feq[m] = fsum[0] + fsum[1] + fsum[2] + fsum[3];
@@ -338,7 +339,6 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
         long long q2 = 0;
         for (int l = tid; l < k; l += 256) q2 += (long long)cnt[l] * cnt[l];
         for (int sh = 32; sh >= 1; sh >>= 1) q2 += __shfl_xor(q2, sh);
-        __shared__ long long qsum[4];
         if ((tid & 63) == 0) qsum[tid >> 6] = q2;
         __syncthreads();
         if (tid == 0) d.sq[m] = qsum[0] + qsum[1] + qsum[2] + qsum[3];
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
             // the last member block to get here sums every member's value (a ticket
             // counter after a release fence; the last block reads the others' values
             // with atomic loads after an acquire fence) and resets the counter
-            __shared__ int last_block;
+            int& last_block = *last_block_p;
             if (tid == 0) {
                 __threadfence();
                 last_block = atomicAdd(&st->prep_ticket, 1) == d.D - 1;
@@ -426,6 +426,18 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
     for (int i = tid; i < n; i += 256) cv[i] = lst[i];
 }
 
+__global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, int G, int total_mem, int honor_stop,
+                                              int next, int decide, int ex_blocks, int advance_prev) {
+    const int mem = blockIdx.x;
+    if (mem >= total_mem) {
+        // blocks past the members: the expansion of the current colours (gate 1), with the
+        // same stop decision as the member blocks
+        if (mem - total_mem < ex_blocks) expand_block(gd, G, mem - total_mem, honor_stop, next, 1, advance_prev);
+        return;
+    }
+    prep_member(gd, G, mem, honor_stop, next, decide, advance_prev);
+}
+
 // -------------------------------------------------------- sparse penalty rows ----
 
 // Penalty rows from the nonzeros of P.  The penalty operand
@@ -472,11 +484,143 @@ __host__ __device__ inline size_t ps_int_words(int D) { return ((size_t)D + 1 + 
 constexpr int kPsBatch = 4;     // entries per thread per batch in steps 1 and 3 (48 registers: eight waves per SIMD)
 constexpr int kPsA8 = 2;        // adjacency words per thread loaded at the start
 
-template <int NT>
+// ---- the row update on the sparse-rows launch (fast path, graphs with pfuse) ----
+//
+// One wave per (member d, vertex i) row, lane j holding colours j, j + 64, ... (KW of them):
+// the added-fitness term, softmax along k (max subtracted), the straight-through gradient
+// gW = s^ (gS - sum_l s^_l gS_l), W' = W - eta gW (divided by rho in the smoothing
+// iterations) written to the other weight buffer, and the argmax of W' (lowest colour on
+// ties) to the other colour buffer.  The arithmetic of the row-update kernel, with the row's
+// sums taken over 64 lanes.  The fitness launch that follows accepts the update by flipping
+// the buffers, unless the graph stops in this iteration (the stop rule comes before the update).
+struct FuseCtx {
+    const float* Wc;          // current weights
+    float* Wn;                // the other buffer, written
+    int16_t* cn;              // the other colour buffer, written
+    const int32_t* V;         // class sizes of this iteration (added fitness term)
+    float nut, eta, rho;
+    bool smooth;
+};
+
+__device__ inline FuseCtx fuse_ctx(const GraphDev& d, GraphState* st) {
+    FuseCtx f;
+    const int pW = st->pW, pS = st->pS;
+    const long long t = st->t;
+    f.Wc = d.W[pW];
+    f.Wn = d.W[pW ^ 1];
+    f.cn = d.c[pS ^ 1];
+    f.V = d.V[pS];
+    f.nut = prob_added(d.problem) ? d.nu * (float)t : 0.0f;
+    f.eta = d.eta;
+    f.rho = d.rho;
+    f.smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
+    return f;
+}
+
+// loads of row (dd, i): weights and the raw G entries (fp32 bits, or the uint16 A.S count) of
+// the lane's colours below k; one base address per row, so the loads take immediate offsets
+template <int KW>
+__device__ inline void fuse_row_load(const GraphDev& d, const FuseCtx& f, int dd, int i, int lane, bool g16,
+                                     float (&wv)[KW], uint32_t (&gr)[KW]) {
+    const int k = d.k;
+    const size_t row = ((size_t)dd * d.n + i) * k + lane;
+    const auto* __restrict__ w = gview(f.Wc) + row;
+    const auto* __restrict__ g32 = gview((const float*)d.G) + row;
+    const auto* __restrict__ g16p = gview((const uint16_t*)d.G) + row;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        wv[q] = 0.0f;
+        gr[q] = 0u;
+        if (lane + 64 * q < k) {
+            wv[q] = w[64 * q];
+            gr[q] = g16 ? (uint32_t)g16p[64 * q] : __float_as_uint(g32[64 * q]);
+        }
+    }
+}
+
+// gv: the lane's entries of gS without the added-fitness term (entries past k are ignored)
+template <int KW>
+__device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const FuseCtx& f, int dd, int i, int lane,
+                                       const float (&wv)[KW], float (&gv)[KW]) {
+    const int k = d.k;
+    if (f.nut != 0.0f) {
+        const auto* __restrict__ V = gview(f.V) + (size_t)dd * k + lane;
+#pragma unroll
+        for (int q = 0; q < KW; ++q)
+            if (lane + 64 * q < k) gv[q] += f.nut * added_grad(d.problem, V[64 * q], lane + 64 * q, d.c1, d.c2);
+    }
+    float mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < KW; ++q)
+        if (lane + 64 * q < k) mx = fmaxf(mx, wv[q]);
+    for (int s = 32; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+    float z = 0.0f, qs = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        const float e = (lane + 64 * q < k) ? expf(wv[q] - mx) : 0.0f;
+        z += e;
+        qs += e * gv[q];
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        z += __shfl_xor(z, s);
+        qs += __shfl_xor(qs, s);
+    }
+    const float rz = 1.0f / z;
+    const float rq = qs * rz;
+    float* __restrict__ wo = f.Wn + ((size_t)dd * d.n + i) * k + lane;
+    float best = -INFINITY;
+    int bi = 0x7FFFFFFF, bad = 0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+        const int l = lane + 64 * q;
+        if (l < k) {
+            const float e = expf(wv[q] - mx);
+            const float step = e * rz * (gv[q] - rq);
+            float nw = wv[q] - f.eta * step;
+            if (f.smooth) nw = nw / f.rho;
+            wo[64 * q] = nw;
+            if (!finite_f(nw)) bad = 1;
+            if (nw > best) { best = nw; bi = l; }
+        }
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        const float ob = __shfl_xor(best, s);
+        const int oi = __shfl_xor(bi, s);
+        bad |= __shfl_xor(bad, s);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) {
+        if (bad || bi >= k) {
+            bi = 0;
+            atomicExch(&st->next_bad, 1);
+        }
+        f.cn[(size_t)dd * d.cs + i] = (int16_t)bi;
+    }
+}
+
+// the row update alone for every member of vertex i (iterations of a pfuse graph whose penalty
+// took the dense pass, or without a penalty): G holds the whole fp32 gradient; each wave takes
+// members wave, wave + NT/64, ... (the launch's blocks per CU keep enough rows in flight)
+template <int NT, int KW>
+__device__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const FuseCtx f = fuse_ctx(d, st);
+    for (int dd = wave; dd < d.D; dd += NW) {
+        float wv[KW], gv[KW];
+        uint32_t gr[KW];
+        fuse_row_load<KW>(d, f, dd, i, lane, false, wv, gr);
+#pragma unroll
+        for (int q = 0; q < KW; ++q) gv[q] = __uint_as_float(gr[q]);
+        fuse_row_update<KW>(d, st, f, dd, i, lane, wv, gv);
+    }
+}
+
+template <int NT, int KW>
 __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                    int honor_stop, int PM, int accumulate, int fit_graphs) {
     extern __shared__ __attribute__((aligned(16))) uint8_t ps_sh[];
-    constexpr int B = kPsBatch;
+    constexpr int B = KW > 0 ? 2 : kPsBatch;
     const int b = blockIdx.x;
     if (b >= total_blocks) {
         // blocks past the rows: the fitness of graph b - total_blocks (its one shared word
@@ -490,7 +634,16 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
-    if (!d.psparse || st->pdense || !pen_active(d, st)) return;
+    const bool sparse_now = d.psparse && !st->pdense && pen_active(d, st);
+    // graphs whose row update rides on this launch (the fast path's sparse graphs)
+    const bool fuse = KW > 0 && d.pfuse && accumulate;
+    if constexpr (KW > 0) {
+        if (fuse && !sparse_now) {
+            fuse_update_only<NT, KW>(d, st, b - d.ps_begin);
+            return;
+        }
+    }
+    if (!sparse_now) return;
     const int n = d.n, k = d.k, D = d.D, cs = d.cs;
     const int n_pad = d.n_pad;
     const size_t cTs = d.cTs;
@@ -690,13 +843,27 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     // by NT per entry
     __attribute__((address_space(1))) float* Gg = (__attribute__((address_space(1))) float*)d.G;
     const double inv = ldexp(1.0, -sc);
+    constexpr int KWF = KW > 0 ? KW : 1;
+    FuseCtx fc{};
+    if constexpr (KW > 0)
+        if (fuse) fc = fuse_ctx(d, st);
+    const int wave = tid >> 6;
     for (int d0 = 0; d0 < D; d0 += PM) {
         const int pm = min(PM, D - d0);
-        // f_color (fast path): thread dd < pm loads the contraction's sgn (A.S)[i, c_d(i)] of member
+        // fused: wave w < pm loads row (d0 + w, i) of the weights and of the uint16 A.S counts
+        // now, behind the accumulation below (PM is at most the block's wave count)
+        float wv[KWF];
+        uint32_t gr[KWF];
+        if constexpr (KW > 0)
+            if (fuse && wave < pm) fuse_row_load<KW>(d, fc, d0 + wave, i, lane, true, wv, gr);
+        // f_color (fast path): thread dd < pm loads the contraction's (A.S)[i, c_d(i)] of member
         // d0 + dd now, behind the accumulation below, and adds it to the slots before the barrier
-        // that precedes this group's read-modify-write of G
+        // that precedes this group's read-modify-write of G (or its row updates)
         float own = 0.0f;
-        if (accumulate && tid < pm) own = Gg[((size_t)(d0 + tid) * n + i) * k + ci[d0 + tid]];
+        if (accumulate && tid < pm) {
+            const size_t o = ((size_t)(d0 + tid) * n + i) * k + ci[d0 + tid];
+            own = fuse ? (float)gview((const uint16_t*)d.G)[o] : sgn * Gg[o];
+        }
         for (int e = tid; e < pm * k / 2; e += NT) ((u32x4n*)acc)[e] = u32x4n{0u, 0u, 0u, 0u};
         if ((pm * k) & 1)
             if (tid == 0) acc[pm * k - 1] = 0ull;
@@ -733,8 +900,46 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
         }
         // the number of row i's neighbours sharing its colour (the gather of 2 f_color)
         if (accumulate && tid < pm)
-            atomicAdd(&d.f2p[(size_t)(d0 + tid) * kF2Slots + (i & (kF2Slots - 1))], (int)(sgn * own));
+            atomicAdd(&d.f2p[(size_t)(d0 + tid) * kF2Slots + (i & (kF2Slots - 1))], (int)own);
         __syncthreads();
+        if constexpr (KW > 0) {
+            if (fuse) {
+                // the group's sums as FP32 (sgn P.S), in place, U NT entries per pass: every thread
+                // converts its entries of the pass, and after a barrier stores them as floats over
+                // the accumulators (the floats of pass p end at byte 16 U NT (p + 1), where the
+                // 64-bit entries of pass p + 1 begin at twice that)
+                float* pf = (float*)acc;
+                {
+                    constexpr int U = 8;
+                    float v[U];
+                    for (int e0 = 0; e0 < pm * k; e0 += U * NT) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int e = e0 + tid + u * NT;
+                            v[u] = e < pm * k ? sgn * (float)((double)(long long)acc[e] * inv) : 0.0f;
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int e = e0 + tid + u * NT;
+                            if (e < pm * k) pf[e] = v[u];
+                        }
+                    }
+                }
+                __syncthreads();
+                // gS = sgn (A.S + P.S) for row (d0 + wave, i), rounded as the unfused path rounds
+                // the stored G, then the row update
+                if (wave < pm) {
+                    float gv[KW];
+                    const float* __restrict__ pr = pf + wave * k + lane;
+#pragma unroll
+                    for (int q = 0; q < KW; ++q) gv[q] = lane + 64 * q < k ? sgn * (float)gr[q] + pr[64 * q] : 0.0f;
+                    fuse_row_update<KW>(d, st, fc, d0 + wave, i, lane, wv, gv);
+                }
+                __syncthreads();
+                continue;
+            }
+        }
         for (int e0 = tid; e0 < pm * k; e0 += 4 * NT) {
             float prev[4];
             size_t off[4];
@@ -1049,13 +1254,9 @@ __device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags,
     }
 }
 
-__global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd, int G, int total_tiles,
-                                                int honor_stop, int flags, int gsel, int32_t* __restrict__ mt_out) {
-    __shared__ int16_t ci[kMtChunk][64];
-    __shared__ int16_t cj[kMtChunk][64];
-    __shared__ double red[2][256];
-    const int b = blockIdx.x;
-    if (b >= total_tiles) return;
+// tile b (flattened over the graphs) of the group-concentration kernel; ci, cj, red: its LDS
+__device__ void mtilde_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int flags, int gsel,
+                             int32_t* __restrict__ mt_out, int16_t (*ci)[64], int16_t (*cj)[64], double (*red)[256]) {
     const int g = find_graph(gd, G, b, [](const GraphDev& x) { return x.mt_begin; });
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
@@ -1069,6 +1270,15 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
         mtilde_tile<2>(d, st, b, flags, mt_out, ci, cj, red);
     else
         mtilde_tile<4>(d, st, b, flags, mt_out, ci, cj, red);
+}
+__global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd, int G, int total_tiles,
+                                                int honor_stop, int flags, int gsel, int32_t* __restrict__ mt_out) {
+    __shared__ int16_t ci[kMtChunk][64];
+    __shared__ int16_t cj[kMtChunk][64];
+    __shared__ double red[2][256];
+    const int b = blockIdx.x;
+    if (b >= total_tiles) return;
+    mtilde_block(gd, G, b, honor_stop, flags, gsel, mt_out, ci, cj, red);
 }
 
 // ------------------------------------------------------- step 2, stop rule -----
@@ -1137,6 +1347,11 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
             st->legal_d = ld;
             st->stopped = 1;
         }
+    }
+    if ((flags & kFlagFlipFused) && d.pfuse && threadIdx.x == 0 && !stop) {
+        // the sparse-rows launch wrote this iteration's update into the other buffers
+        st->pW ^= 1;
+        st->pS ^= 1;
     }
     if ((flags & kFlagFused) && threadIdx.x == 0 && !stop) {
         // fused path: the contraction kernel wrote the update into the other buffers
@@ -1232,17 +1447,16 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
 // cost), bit 1: some graph takes heavy-ball steps; the plain variant carries neither
 // stream's registers.
 template <int KPL, int VAR>
-__global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict__ gd, int G, int total_rows,
-                                                     int honor_stop, int mode, int gsel, float* __restrict__ gS_out,
-                                                     float* __restrict__ gW_out) {
+__device__ __forceinline__ void update_row(const GraphDev* __restrict__ gd, int G, int row, int honor_stop, int mode,
+                                           int gsel, float* __restrict__ gS_out, float* __restrict__ gW_out) {
     const int l16 = threadIdx.x & 15;
-    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
-    if (row >= total_rows) return;
     const int g = graph_of_row(gd, G, row);
     if (gsel >= 0 && g != gsel) return;
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
+    // the fast path's sparse graphs take their row update in the sparse-rows launch
+    if (mode == 0 && d.pfuse) return;
     const int r = row - d.row_begin;
     const int k = d.k;
     const int m = r / d.n, i = r - m * d.n;
@@ -1357,6 +1571,15 @@ __global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict_
     }
 }
 
+template <int KPL, int VAR>
+__global__ __launch_bounds__(256) void k_update_rows(const GraphDev* __restrict__ gd, int G, int total_rows,
+                                                     int honor_stop, int mode, int gsel, float* __restrict__ gS_out,
+                                                     float* __restrict__ gW_out) {
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (row >= total_rows) return;
+    update_row<KPL, VAR>(gd, G, row, honor_stop, mode, gsel, gS_out, gW_out);
+}
+
 // t <- t + 1 for every graph still running.
 __global__ void k_advance(const GraphDev* __restrict__ gd, int G) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1446,6 +1669,8 @@ __global__ void k_state(const GraphDev* __restrict__ gd, int G, int op, int g_on
         st->pW = 0;
     } else if (op == 4) {     // clear the conflict accumulators (after timing repeated contractions)
         for (int m = 0; m < gd[g].D; ++m) gd[g].f2[m] = 0;
+    } else if (op == 5) {     // the sparse rows' route for this iteration (timing of its contraction form)
+        st->pdense = 0;
     }
 }
 
@@ -1591,7 +1816,7 @@ hipError_t launch_colors(const GraphDev* gd, int G, int total_rows, int honor_st
 }
 
 size_t prep_lds(int kmax, int nmax, int lists) {
-    size_t b = sizeof(int) * (size_t)kmax;
+    size_t b = sizeof(int) * ((size_t)kPrepScratch + (size_t)kmax);
     if (lists) b += sizeof(int) * 5 * (size_t)kmax + sizeof(int16_t) * (size_t)nmax;
     return (b + 15) / 16 * 16;
 }
@@ -1606,13 +1831,27 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int
     return hipSuccess;
 }
 
+// instantiations of the sparse rows: KW = 0 (no row update), or the row update's values per lane
+// (k <= 64 KW) for graphs whose update rides on the launch
+#define TCOL_PS_KERNELS(X) \
+    X(256, 0) X(512, 0) X(1024, 0) X(512, 2) X(512, 3) X(512, 5) X(512, 7) X(512, 9) \
+    X(1024, 2) X(1024, 3) X(1024, 5) X(1024, 7) X(1024, 9)
+
+int penalty_sparse_kw(int kmax) {
+    for (int kw : {2, 3, 5, 7, 9})
+        if (64 * kw >= kmax) return kw;
+    return -1;
+}
+
 hipError_t penalty_sparse_prepare() {
-    const void* fns[] = {(const void*)k_pen_sparse<256>, (const void*)k_pen_sparse<512>,
-                         (const void*)k_pen_sparse<1024>};
-    for (const void* f : fns) {
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
+#define TCOL_PS_ATTR(NT, KW)                                                                                 \
+    {                                                                                                        \
+        const hipError_t e = hipFuncSetAttribute((const void*)k_pen_sparse<NT, KW>,                          \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);    \
+        if (e != hipSuccess) return e;                                                                       \
     }
+    TCOL_PS_KERNELS(TCOL_PS_ATTR)
+#undef TCOL_PS_ATTR
     // k_prep also holds 1 KB of static LDS
     return hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
@@ -1626,17 +1865,22 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
     return (b + 15) / 16 * 16;
 }
 
-hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
-                                 int accumulate, int fit_graphs, hipStream_t s) {
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, size_t lds,
+                                 int honor_stop, int accumulate, int fit_graphs, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     const int grid = blocks + fit_graphs;
     if (PM < 8 || (PM & 7) || lds > 160 * 1024) return hipErrorInvalidValue;
-    switch (threads) {
-        case 256: k_pen_sparse<256><<<grid, 256, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
-        case 512: k_pen_sparse<512><<<grid, 512, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
-        case 1024: k_pen_sparse<1024><<<grid, 1024, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs); break;
-        default: return hipErrorInvalidValue;
+    // the fused row update takes one wave per member of a group
+    if (kw > 0 && PM > threads / 64) return hipErrorInvalidValue;
+    bool done = false;
+#define TCOL_PS_LAUNCH(NT, KW)                                                                              \
+    if (!done && threads == NT && kw == KW) {                                                               \
+        k_pen_sparse<NT, KW><<<grid, NT, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs);   \
+        done = true;                                                                                        \
     }
+    TCOL_PS_KERNELS(TCOL_PS_LAUNCH)
+#undef TCOL_PS_LAUNCH
+    if (!done) return hipErrorInvalidValue;
     TCOL_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -26,9 +26,13 @@ hipError_t penalty_sparse_prepare();
 size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax);
 // accumulate 0: rows written to G before the contraction (epilogue path); 1: added to the
 // contraction's G (fast path).  fit_graphs > 0: the same launch also takes the fitness of
-// graphs 0 .. fit_graphs - 1 (as launch_fitness with flags 0), in blocks after the rows
-hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, size_t lds, int honor_stop,
-                                 int accumulate, int fit_graphs, hipStream_t s);
+// graphs 0 .. fit_graphs - 1 (as launch_fitness with flags 0), in blocks after the rows.
+// kw > 0 (penalty_sparse_kw of the largest k of those graphs; PM at most threads / 64): graphs
+// with pfuse take their row update in this launch as well, in every iteration (accumulate 1)
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, size_t lds,
+                                 int honor_stop, int accumulate, int fit_graphs, hipStream_t s);
+// values per lane of the fused row update for k <= kmax (2, 3, 5, 7 or 9), or -1 past k = 576
+int penalty_sparse_kw(int kmax);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
                          hipStream_t s);
 hipError_t launch_mtilde(const GraphDev* gd, int G, int total_tiles, int honor_stop, int flags, int gsel,
@@ -59,7 +63,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 //   mode 0: store G [D][n][k] (separate-kernel path); 1: fused softmax/update/argmax epilogue
 //   passes: bit 0 = A.S with gather, bit 1 = penalty pass when active, bit 2 = store / epilogue,
 //           bit 3 = dense penalty operand even for graphs on the sparse penalty, bit 4 = no
-//           penalty pass at all, bit 6 = no f_color gather for graphs whose iteration takes
+//           penalty pass at all, bit 5 = A.S counts as uint16 for graphs whose sparse rows take
+//           the row update (pfuse) in iterations on the sparse rows (mode 0; the fast path's step),
+//           bit 6 = no f_color gather for graphs whose iteration takes
 //           the sparse rows (the sparse kernel gathers it from G), bit 7 = no gather at all
 struct GemmShape {
     int prec, bm, ntw, mode;
@@ -71,5 +77,29 @@ hipError_t launch_gemm(const GemmShape& s, const GraphDev* gd, int G, int total_
 // dynamic LDS of a GEMM launch (cstage: bytes of member colours staged by the fused epilogue)
 size_t gemm_lds_bytes(const GemmShape& s, int cstage);
 int gemm_bn(int ntw);
+
+// Persistent launch of a run of iterations over all graphs (fast schedule, dense penalty
+// pass, no heavy-ball steps, one operand precision): a queue of items in segments, one per
+// (iteration, phase, graph) in that order, phases 0 class sizes + expansion, 1 group
+// concentration, 2 contraction tiles, 3 fitness, 4 row update.  Segment s holds tickets
+// [start, next start) of graph g; its items wait until `need` items of graph g are done.
+struct BatchSeg {
+    int start, g, phase, iter, need;
+    int pad[3];
+};
+// contraction tile of the persistent launch (rows per block, 16-column subtiles per wave)
+constexpr int kBatchBM = 128, kBatchNTW = 4;
+// control words before the per-graph done counts: ticket, abort flag, tickets past the end, spare
+constexpr int kBatchCtl = 4;
+// the row update's values per 16-lane group (8 or 36; 0: k too large)
+int batch_kpl(int kmax);
+// dynamic LDS of the launch (prep_bytes: the class-size block's, prep_lds)
+size_t batch_lds_bytes(int prec, size_t prep_bytes);
+// LDS attribute; resident blocks per CU of the instantiation
+hipError_t batch_prepare(int prec, int kpl, int* blocks_per_cu);
+// nseg segments of `total` tickets; ctl: kBatchCtl + G ints, zero at launch; cancel: a word the
+// host may set (device view of pinned host memory); spin_limit: polls of a wait before it gives up
+hipError_t launch_batch_run(int prec, int kpl, int grid, size_t lds, const GraphDev* gd, int G, const BatchSeg* segs,
+                            int nseg, int total, int* ctl, const int* cancel, int spin_limit, hipStream_t s);
 
 }  // namespace tcol
