@@ -33,6 +33,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_c5_hbm_traffic.txt")
 # pass, sparse rows, per-iteration choice at any size
 PENALTY_MODES = {"auto": 0, "dense": 1, "sparse": 2, "auto-any-n": 3}
 PENALTY_NAMES = {v: k for k, v in PENALTY_MODES.items()}
+# step schedules (tcol_options.fused)
+PATHS = {"separate": 0, "fast": 1, "epilogue": 2, "batch": 3}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
 HBM_PEAK = 8.0e12
 PREC = {"fp32": tcolgen.FP32, "bf16": tcolgen.BF16, "fp8": tcolgen.FP8, "fp4": tcolgen.FP4}
 PROBLEMS = {"kcol": tcolgen.KCOL, "ecp": tcolgen.ECP, "kpart": tcolgen.KPART, "bkpart": tcolgen.BKPART,
@@ -171,7 +174,7 @@ def run_batch(args, torch, pk):
     dev = torch.device("cuda:0")
     graphs = [(torch.from_numpy(c.adjacency()).to(dev), torch.from_numpy(c.weights()).to(dev)) for c in cases]
     s = pk.Solver(graphs, [pk.Params.from_dict(c.params()) for c in cases])
-    s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
+    s.set_options(use_graph=0 if args.no_graph else 1, fused=PATHS[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
                   penalty=PENALTY_MODES[args.penalty])
     opts = s.options()
@@ -249,7 +252,8 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5", "c5b"],
                     help="c5b: the batch of 16 uneven graphs in one context")
     ap.add_argument("--precision", default=None, choices=list(PREC))
-    ap.add_argument("--path", default="fast", choices=["separate", "fast", "epilogue"])
+    ap.add_argument("--path", default="fast", choices=list(PATHS),
+                    help="step schedule; batch: one launch per run of iterations over all graphs")
     ap.add_argument("--penalty", default="auto", choices=list(PENALTY_MODES),
                     help="penalty product: per-iteration choice (auto), dense MFMA pass, or sparse rows")
     ap.add_argument("--problem", default=None, choices=list(PROBLEMS),
@@ -305,7 +309,7 @@ def main():
     Wt = torch.from_numpy(W0).to(dev)
     At = torch.from_numpy(A).to(dev)
     s = pk.Solver([(At, Wt)], [pk.Params.from_dict(case.params())])
-    s.set_options(use_graph=0 if args.no_graph else 1, fused={"separate": 0, "fast": 1, "epilogue": 2}[args.path],
+    s.set_options(use_graph=0 if args.no_graph else 1, fused=PATHS[args.path],
                   tile_bm=args.tile_bm, tile_ntw=args.tile_ntw,
                   penalty=PENALTY_MODES[args.penalty])
     if args.autotune:

@@ -57,7 +57,9 @@ enum {
     TCOL_EHIP = -4,        /* a HIP runtime call failed */
     TCOL_ENONFINITE = -5,  /* a weight is NaN or infinite */
     TCOL_ENOMEM = -6,      /* device allocation failed or the workspace is too small */
-    TCOL_ESTATE = -7       /* call not valid in the current state */
+    TCOL_ESTATE = -7,      /* call not valid in the current state */
+    TCOL_EABORT = -8       /* a wait of the batch launch gave up (tcol_cancel, or past the
+                              limit of tcol_set_wait_limit); the run's weights are unspecified */
 };
 
 /* Problem statement.  k-COL is one step of the GCP (Sections 3.1-3.2: fitness =
@@ -127,7 +129,20 @@ typedef struct {
                                iterations are stored as uint16;
                                2 = epilogue path: the contraction kernel itself applies softmax,
                                gradient, update and the next argmax, into a second weight
-                               buffer (k <= 576) */
+                               buffer (k <= 576);
+                               3 = batch launch: the fast schedule's work of a whole run of
+                               iterations (up to 64) over every graph in ONE kernel launch,
+                               whose blocks take items (class sizes and expansion, group
+                               concentration tiles, contraction tiles, fitness, row-update
+                               groups) from a device queue in ticket order; an item waits
+                               until its graph's earlier phases are done, so graphs overlap
+                               their phases (Algorithm 1 per graph; a batch of uneven graphs
+                               is the use).  It needs the dense penalty pass for every graph
+                               (penalty 1, or 0 where the automatic choice keeps it), no
+                               heavy-ball steps, no multicolouring, one operand precision and
+                               k <= 576; otherwise the fast path runs.  Its contraction tile
+                               is 64 x 128 (tile_bm / tile_ntw do not apply).  Waits are
+                               bounded (tcol_set_wait_limit) and cancellable (tcol_cancel) */
     int32_t use_graph;      /* 1: replay each step from a captured hipGraph (default) */
     int32_t unroll;         /* steps per captured graph (1..64, default 8) */
     int32_t tile_bm;        /* GEMM rows per block (64, 128 or 256); 0 = default or autotuned */
@@ -278,6 +293,21 @@ tcol_status tcol_get_counters(tcol_ctx *ctx, int32_t g, int64_t *counts);
  * be NULL) receive the chosen tile.  Allocates a device copy of each W for the
  * duration of the call.  Errors: TCOL_EINVAL, TCOL_ENOMEM, TCOL_EHIP. */
 tcol_status tcol_autotune(tcol_ctx *ctx, int32_t *best_bm, int32_t *best_ntw);
+
+/* Batch launch (tcol_options.fused = 3): the number of polls a waiting item makes before it
+ * gives up (each poll sleeps about 50 ns and reads device memory); 0 restores the default
+ * (about 4 million polls: seconds).  A run whose wait gave up returns TCOL_EABORT from
+ * tcol_step, after every block of the launch has exited.  Drops the captured step graphs (the
+ * limit is a launch argument).  For callers that want runs cut short, e.g. tests of the
+ * abort path with a tiny limit.  Errors: TCOL_EINVAL (NULL, polls < 0). */
+tcol_status tcol_set_wait_limit(tcol_ctx *ctx, int32_t polls);
+
+/* Batch launch: ask a running tcol_step to give up.  Sets a word in pinned host memory that
+ * the launch's waits poll; a waiting item then marks the run aborted and every later item
+ * returns at once, so the call in progress returns TCOL_EABORT.  Safe to call from another
+ * host thread while tcol_step runs; tcol_step clears the word when it starts.  No effect on
+ * the other schedules.  Errors: TCOL_EINVAL. */
+tcol_status tcol_cancel(tcol_ctx *ctx);
 
 /* Measurement utility.  Runs `steps` iterations of every graph eagerly (no
  * captured graph) with HIP events around each kernel on the context's stream

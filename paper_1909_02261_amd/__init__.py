@@ -203,6 +203,14 @@ class Solver:
     def reset(self) -> None:
         _lib.check(self._lib.tcol_reset(self._ctx), "tcol_reset")
 
+    def set_wait_limit(self, polls: int) -> None:
+        """Batch launch (fused = 3): polls of a waiting item before it gives up (0: default)."""
+        _lib.check(self._lib.tcol_set_wait_limit(self._ctx, int(polls)), "tcol_set_wait_limit")
+
+    def cancel(self) -> None:
+        """Batch launch: make the tcol_step in progress (another thread) give up (TCOL_EABORT)."""
+        _lib.check(self._lib.tcol_cancel(self._ctx), "tcol_cancel")
+
     def counters(self, g: int = 0) -> dict:
         """Iterations of graph g evaluated since init, by the route of the penalty product."""
         out = (ctypes.c_int64 * 3)()

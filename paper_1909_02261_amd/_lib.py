@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libtcol.so")
 
 TCOL_OK = 0
 STATUS = {0: "TCOL_OK", -1: "TCOL_EINVAL", -2: "TCOL_ESHAPE", -3: "TCOL_EGRAPH", -4: "TCOL_EHIP",
-          -5: "TCOL_ENONFINITE", -6: "TCOL_ENOMEM", -7: "TCOL_ESTATE"}
+          -5: "TCOL_ENONFINITE", -6: "TCOL_ENOMEM", -7: "TCOL_ESTATE", -8: "TCOL_EABORT"}
 
 KCOL, ECP, KPART, BKPART, MSCP, MCOL = 0, 1, 2, 3, 4, 5
 FP32, BF16, FP8, FP4 = 0, 1, 2, 3
@@ -49,7 +49,7 @@ EXPORTS = ["tcol_status_string", "tcol_workspace_size", "tcol_init", "tcol_set_o
            "tcol_get_options", "tcol_step", "tcol_conflicts", "tcol_loss_grad", "tcol_mtilde",
            "tcol_get_t", "tcol_set_t", "tcol_reset", "tcol_autotune", "tcol_profile", "tcol_destroy",
            "tcol_init_weights", "tcol_descent", "tcol_mfma_peak", "tcol_get_counters", "tcol_conflicts_noalloc",
-           "tcol_class_conflicts", "tcol_set_demand", "tcol_selection"]
+           "tcol_class_conflicts", "tcol_set_demand", "tcol_selection", "tcol_set_wait_limit", "tcol_cancel"]
 NPHASES = 10
 PHASES = ["colors", "class_sizes", "expand", "mtilde", "gemm", "fitness", "update", "advance", "gemm_as_only",
           "gemm_as_store"]
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tcol_get_t.argtypes = [P, i32, ctypes.POINTER(i64)]
     lib.tcol_set_t.argtypes = [P, i32, i64]
     lib.tcol_reset.argtypes = [P]
+    lib.tcol_set_wait_limit.argtypes = [P, i32]
+    lib.tcol_cancel.argtypes = [P]
     lib.tcol_get_counters.argtypes = [P, i32, ctypes.POINTER(i64)]
     lib.tcol_conflicts_noalloc.argtypes = [ctypes.POINTER(GraphParams), P, P, P, P, P, P]
     lib.tcol_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtcol.so")
-SOURCES = ["tcol_host.hip", "tcol_kernels.hip", "tcol_gemm.hip", "tcol_peak.hip"]
+SOURCES = ["tcol_host.hip", "tcol_device.hip", "tcol_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -103,7 +104,18 @@ Layout make_layout(const tcol_graph_params& p) {
     return L;
 }
 
-size_t head_bytes(int G) { return align_up(sizeof(GraphDev) * G) + align_up(sizeof(GraphState) * G); }
+// runs of the batch launch: at most this many iterations (tcol_options.unroll's range)
+constexpr int kBatchMaxIters = 64;
+constexpr int kBatchPhases = 5;
+size_t batch_ctl_bytes(int G) { return align_up(sizeof(int) * (kBatchCtl + (size_t)G)); }
+size_t batch_seg_bytes(int G) { return align_up(sizeof(BatchSeg) * (size_t)kBatchMaxIters * kBatchPhases * G); }
+// descriptors, states, the batch launch's control words and its item segments
+size_t head_bytes(int G) {
+    return align_up(sizeof(GraphDev) * G) + align_up(sizeof(GraphState) * G) + batch_ctl_bytes(G) + batch_seg_bytes(G);
+}
+// default polls of a wait in the batch launch before it gives up (each poll sleeps about 50 ns
+// and reads device memory: seconds in all)
+constexpr int kBatchSpinDefault = 1 << 22;
 
 tcol_status check_params(const tcol_graph_params& p) {
     if (p.n < 1 || p.n > kMaxN || p.k < 1 || p.k > kMaxK || p.D < 1 || p.D > kMaxD) return TCOL_ESHAPE;
@@ -157,6 +169,18 @@ struct tcol_ctx {
     int ps_PM = 0, ps_threads = 0;  // sparse penalty: members per accumulator group, block size
     int ps_kw = 0;                  // sparse penalty: values per lane of the fused row update (0: none)
     bool all_pfuse = false;         // every graph's row update rides on the sparse-rows launch
+    // batch launch (fused = 3): one launch per run of iterations, items in segments
+    bool batch_ok = false;
+    int batch_kpl = 0, batch_grid_cap = 0, batch_prec = 0;
+    int batch_items = 0;            // items of one iteration over all graphs
+    size_t batch_lds = 0;
+    int* dctl = nullptr;            // workspace: kBatchCtl + G ints
+    BatchSeg* dsegs = nullptr;      // workspace: kBatchMaxIters * kBatchPhases * G segments
+    int* hcancel = nullptr;         // pinned host word the launch's waits poll (tcol_cancel)
+    int* dcancel = nullptr;         // its device view
+    int* habort = nullptr;          // pinned host copy of the abort flag after a run
+    int spin_limit = kBatchSpinDefault;
+    int cus = 0;
     size_t ps_lds = 0;              // dynamic LDS of the sparse penalty kernel
     size_t prep_lds = 0;            // dynamic LDS of the class-size kernel
     int total_ps = 0;               // blocks of the sparse penalty kernel (0: no graph uses it)
@@ -262,6 +286,11 @@ static void pick_shapes(tcol_ctx* c) {
         s.bm = c->opt.tile_bm;
         s.ntw = c->opt.tile_ntw;
     }
+    // the batch launch runs its own contraction tile
+    if (c->opt.fused == 3) {
+        s.bm = kBatchBM;
+        s.ntw = kBatchNTW;
+    }
     c->shape = s;
     // fused: whole members per column tile, so 32 * ntw >= k; the smallest such width,
     // with 128-row blocks when that still gives at least 512 tiles
@@ -317,6 +346,65 @@ static bool pick_sparse(int kmax, int dmax, int nmax, int& PM, int& threads) {
 }
 
 static int path_of(const tcol_ctx* c);
+
+// The batch launch (fused = 3): whether it can run these graphs, and its item segments.  It
+// runs the fast schedule with the dense penalty pass, so no graph may take the sparse rows,
+// heavy-ball steps or multiple colours, and the graphs share one operand precision.  Items
+// per graph and phase: class sizes (D) + expansion (groups of kBatchExpand blocks); group
+// concentration (groups of kBatchMtilde tiles); contraction tiles; fitness (1); row update
+// (groups of kBatchRowGroups x 16 rows).  Segments go by iteration, phase, then graph in
+// decreasing tile cost (`order`); a segment's items wait for all earlier items of its graph.
+static tcol_status build_batch(tcol_ctx* c, const std::vector<int>& order) {
+    c->batch_ok = false;
+    if (c->opt.fused != 3) return TCOL_OK;
+    const int prec = common_precision(c);
+    const int kpl = batch_kpl(c->kmax);
+    if (c->total_ps > 0 || c->any_momentum || c->any_mcol || prec < 0 || kpl == 0 || !update_rows_kpl(c->kmax))
+        return TCOL_OK;
+    const int G = c->G;
+    std::vector<std::array<int, kBatchPhases>> items(G);
+    long long per_iter = 0;
+    for (int g = 0; g < G; ++g) {
+        const GraphDev& d = c->hdesc[g];
+        const auto& p = c->params[g];
+        items[g][0] = p.D + ceil_div(d.ex_cblocks, kBatchExpand);
+        items[g][1] = ceil_div(c->layouts[g].mt_tiles, kBatchMtilde);
+        items[g][2] = d.gm_tm[0] * d.gm_tn[0];
+        items[g][3] = 1;
+        items[g][4] = ceil_div(p.D * p.n, 16 * kBatchRowGroups);
+        for (int ph = 0; ph < kBatchPhases; ++ph) per_iter += items[g][ph];
+    }
+    if (per_iter * kBatchMaxIters >= (1LL << 30)) return TCOL_OK;
+    std::vector<BatchSeg> segs;
+    segs.reserve((size_t)kBatchMaxIters * kBatchPhases * G);
+    int start = 0;
+    for (int it = 0; it < kBatchMaxIters; ++it)
+        for (int ph = 0; ph < kBatchPhases; ++ph)
+            for (int g : order) {
+                int before = 0;
+                for (int q = 0; q < kBatchPhases; ++q) before += items[g][q];
+                int need = it * before;
+                for (int q = 0; q < ph; ++q) need += items[g][q];
+                BatchSeg sg{};
+                sg.start = start;
+                sg.g = g;
+                sg.phase = ph;
+                sg.iter = it;
+                sg.need = need;
+                segs.push_back(sg);
+                start += items[g][ph];
+            }
+    int bpc = 0;
+    HIPCHK(batch_prepare(prec, kpl, &bpc));
+    if (bpc < 1) return TCOL_OK;
+    HIPCHK(hipMemcpyAsync(c->dsegs, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice, c->stream));
+    c->batch_prec = prec;
+    c->batch_kpl = kpl;
+    c->batch_items = (int)per_iter;
+    c->batch_lds = batch_lds_bytes(prec, c->prep_lds);
+    c->batch_ok = true;
+    return TCOL_OK;
+}
 
 // recompute flattened work offsets for the tile shapes and upload the descriptors
 static tcol_status rebuild_schedule(tcol_ctx* c) {
@@ -421,6 +509,8 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
     c->total_ex = ex;
     c->total_gm[0] = gm0;
     c->total_gm[1] = gm1;
+    tcol_status bs = build_batch(c, order);
+    if (bs != TCOL_OK) return bs;
     HIPCHK(hipMemcpyAsync(c->ddesc, c->hdesc.data(), sizeof(GraphDev) * c->G, hipMemcpyHostToDevice, c->stream));
     drop_graphs(c);
     return TCOL_OK;
@@ -429,6 +519,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
 // step schedule actually used: 2 needs the epilogue tiling, 1 needs the row-update kernel
 static int path_of(const tcol_ctx* c) {
     if (c->any_mcol) return 0;
+    if (c->opt.fused == 3 && c->batch_ok) return 3;
     if (c->opt.fused == 2 && c->fused_ok && !c->any_momentum) return 2;
     if (c->opt.fused >= 1 && update_rows_kpl(c->kmax)) return 1;
     return 0;
@@ -526,8 +617,25 @@ static hipError_t enqueue_step_fused(tcol_ctx* c, hipStream_t s) {
     return hipSuccess;
 }
 
+// runs of up to kBatchMaxIters iterations, each one batch launch (the counters cleared by a
+// fill kernel first) and the run's last counter advance
+static hipError_t enqueue_batch(tcol_ctx* c, int n, hipStream_t s) {
+    const size_t ctl = batch_ctl_bytes(c->G);
+    for (int done = 0; done < n;) {
+        const int run = std::min(kBatchMaxIters, n - done);
+        HIPRET(launch_zero(c->dctl + 4, ctl - 4 * sizeof(int), s));
+        const int total = run * c->batch_items;
+        HIPRET(launch_batch_run(c->batch_prec, c->batch_kpl, total, c->batch_lds, c->ddesc, c->G, c->dsegs,
+                                run * kBatchPhases * c->G, total, c->dctl, c->dcancel, c->spin_limit, s));
+        HIPRET(launch_advance(c->ddesc, c->G, s));
+        done += run;
+    }
+    return hipSuccess;
+}
+
 static hipError_t enqueue_steps(tcol_ctx* c, int n, hipStream_t s) {
     const int path = path_of(c);
+    if (path == 3) return enqueue_batch(c, n, s);
     for (int i = 0; i < n; ++i)
         HIPRET(path == 2 ? enqueue_step_fused(c, s)
                          : (path == 1 ? enqueue_step_fast(c, i > 0, i == n - 1, s) : enqueue_step_plain(c, s)));
@@ -559,6 +667,8 @@ static tcol_status build_graphs(tcol_ctx* c) {
 // run `steps` iterations (graph replays or eager launches); no synchronisation
 static tcol_status run_steps(tcol_ctx* c, int steps) {
     if (steps <= 0) return TCOL_OK;
+    // the batch launch's abort flag holds for the whole call
+    if (path_of(c) == 3) HIPCHK(launch_zero(c->dctl, 4 * sizeof(int), c->stream));
     // the fast and epilogue paths colour the updated rows themselves: one argmax pass first
     if (path_of(c) != 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, c->stream));
     if (c->opt.use_graph) {
@@ -578,6 +688,7 @@ static tcol_status run_steps(tcol_ctx* c, int steps) {
 // read the graph states (synchronises) and move fused-path weights back into the caller's buffer
 static tcol_status settle(tcol_ctx* c) {
     HIPCHK(hipMemcpyAsync(c->hstate, c->dstate, sizeof(GraphState) * c->G, hipMemcpyDeviceToHost, c->stream));
+    if (c->batch_ok) HIPCHK(hipMemcpyAsync(c->habort, c->dctl, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     bool any = false;
     for (int g = 0; g < c->G; ++g) {
@@ -589,6 +700,15 @@ static tcol_status settle(tcol_ctx* c) {
         }
     }
     if (any) HIPCHK(launch_state(c->ddesc, c->G, 3, -1, 0, c->stream));
+    // a wait of the batch launch gave up (the host's cancel word or the wait limit)
+    if (c->batch_ok && c->habort[0]) {
+        // the run stopped part-way: clear the flag and the conflict accumulators the
+        // contraction tiles of unfinished iterations left behind
+        c->habort[0] = 0;
+        HIPCHK(launch_zero(c->dctl, 4 * sizeof(int), c->stream));
+        HIPCHK(launch_state(c->ddesc, c->G, 4, -1, 0, c->stream));
+        return TCOL_EABORT;
+    }
     return TCOL_OK;
 }
 
@@ -606,6 +726,7 @@ const char* tcol_status_string(tcol_status s) {
         case TCOL_ENONFINITE: return "non-finite weight";
         case TCOL_ENOMEM: return "out of device memory or workspace too small";
         case TCOL_ESTATE: return "invalid state";
+        case TCOL_EABORT: return "a wait of the batch launch gave up (cancelled, or past the wait limit)";
         default: return "unknown status";
     }
 }
@@ -629,6 +750,7 @@ void tcol_destroy(tcol_ctx* c) {
     if (c->cap) hipStreamDestroy(c->cap);
     if (c->ws_owned && c->ws) hipFree(c->ws);
     if (c->hstate) hipHostFree(c->hstate);
+    if (c->hcancel) hipHostFree(c->hcancel);
     delete c;
 }
 
@@ -674,6 +796,22 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
         tcol_destroy(c);
         return TCOL_ENOMEM;
     }
+    // the batch launch's cancel word (polled by its waits) and the abort flag's host copy
+    if (hipHostMalloc((void**)&c->hcancel, 64, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->dcancel, c->hcancel, 0) != hipSuccess) {
+        tcol_destroy(c);
+        return TCOL_ENOMEM;
+    }
+    c->hcancel[0] = 0;
+    c->habort = c->hcancel + 4;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            tcol_destroy(c);
+            return TCOL_EHIP;
+        }
+    }
     if (ws_dev) {
         c->ws = (uint8_t*)ws_dev;
         c->ws_bytes = ws_bytes;
@@ -694,6 +832,8 @@ tcol_status tcol_init(tcol_ctx** out, int32_t G, const tcol_graph_params* p, con
     }
     c->ddesc = (GraphDev*)c->ws;
     c->dstate = (GraphState*)(c->ws + align_up(sizeof(GraphDev) * G));
+    c->dctl = (int*)(c->ws + align_up(sizeof(GraphDev) * G) + align_up(sizeof(GraphState) * G));
+    c->dsegs = (BatchSeg*)((uint8_t*)c->dctl + batch_ctl_bytes(G));
     size_t off = head_bytes(G);
     c->hdesc.resize(G);
     c->layouts.resize(G);
@@ -836,7 +976,7 @@ tcol_status tcol_set_options(tcol_ctx* c, const tcol_options* o) {
     if (!c || !o) return TCOL_EINVAL;
     if (o->unroll < 0 || o->unroll > 64) return TCOL_EINVAL;
     if (o->penalty < 0 || o->penalty > 3) return TCOL_EINVAL;
-    if (o->fused < 0 || o->fused > 2) return TCOL_EINVAL;
+    if (o->fused < 0 || o->fused > 3) return TCOL_EINVAL;
     if ((o->tile_bm || o->tile_ntw) && !shape_listed(o->tile_bm, o->tile_ntw)) return TCOL_EINVAL;
     tcol_options old = c->opt;
     c->opt = *o;
@@ -862,6 +1002,7 @@ tcol_status tcol_get_options(tcol_ctx* c, tcol_options* o) {
 tcol_status tcol_step(tcol_ctx* c, int32_t max_steps, int32_t* steps_done, int32_t* legal_d,
                       int16_t* const* colors_out_dev) {
     if (!c || max_steps < 0) return TCOL_EINVAL;
+    __atomic_store_n(&c->hcancel[0], 0, __ATOMIC_RELEASE);
     HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
     tcol_status rs = run_steps(c, max_steps);
     if (rs != TCOL_OK) return rs;
@@ -981,6 +1122,19 @@ tcol_status tcol_reset(tcol_ctx* c) {
     return TCOL_OK;
 }
 
+tcol_status tcol_set_wait_limit(tcol_ctx* c, int32_t polls) {
+    if (!c || polls < 0) return TCOL_EINVAL;
+    c->spin_limit = polls == 0 ? kBatchSpinDefault : polls;
+    drop_graphs(c);   // the limit is a launch argument of the captured runs
+    return TCOL_OK;
+}
+
+tcol_status tcol_cancel(tcol_ctx* c) {
+    if (!c) return TCOL_EINVAL;
+    __atomic_store_n(&c->hcancel[0], 1, __ATOMIC_RELEASE);
+    return TCOL_OK;
+}
+
 tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms) {
     if (!c || steps < 1 || !ms) return TCOL_EINVAL;
     constexpr int NP = TCOL_NPHASES;
@@ -989,7 +1143,8 @@ tcol_status tcol_profile(tcol_ctx* c, int32_t steps, int32_t as_only, float* ms)
     for (int i = 0; i < NE; ++i) HIPCHK(hipEventCreate(&ev[i]));
     double acc[NP] = {0};
     hipStream_t s = c->stream;
-    const int path = path_of(c);
+    // the batch launch's phases are timed as the fast schedule's kernels
+    const int path = path_of(c) == 3 ? 1 : path_of(c);
     HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, s));
     if (path != 0) HIPCHK(launch_colors(c->ddesc, c->G, c->total_rows, 1, s));
     for (int it = 0; it < steps; ++it) {
@@ -1170,6 +1325,14 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
     HIPCHK(hipEventCreate(&e1));
     std::vector<tcol_options> cands;
     const std::vector<int> paths = base.fused == 0 ? std::vector<int>{0} : std::vector<int>{1, 2};
+    {
+        // the batch launch, with its own tile, when these graphs can take it
+        tcol_options o = base;
+        o.fused = 3;
+        o.penalty = 0;
+        o.tile_bm = o.tile_ntw = 0;
+        if (base.fused != 0) cands.push_back(o);
+    }
     for (int path : paths)
         for (auto& sh : kShapes) {
             tcol_options o = base;
@@ -1191,6 +1354,7 @@ tcol_status tcol_autotune(tcol_ctx* c, int32_t* best_bm, int32_t* best_ntw) {
     for (auto& o : cands) {
         c->opt = o;
         if (rebuild_schedule(c) != TCOL_OK) continue;
+        if (o.fused == 3 && path_of(c) != 3) continue;
         HIPCHK(launch_state(c->ddesc, c->G, 0, -1, 0, c->stream));
         if (run_steps(c, warm) != TCOL_OK) continue;
         HIPCHK(hipEventRecord(e0, c->stream));

@@ -78,7 +78,7 @@ hipError_t launch_gemm(const GemmShape& s, const GraphDev* gd, int G, int total_
 size_t gemm_lds_bytes(const GemmShape& s, int cstage);
 int gemm_bn(int ntw);
 
-// Persistent launch of a run of iterations over all graphs (fast schedule, dense penalty
+// One launch for a run of iterations over all graphs (fast schedule, dense penalty
 // pass, no heavy-ball steps, one operand precision): a queue of items in segments, one per
 // (iteration, phase, graph) in that order, phases 0 class sizes + expansion, 1 group
 // concentration, 2 contraction tiles, 3 fitness, 4 row update.  Segment s holds tickets
@@ -87,18 +87,22 @@ struct BatchSeg {
     int start, g, phase, iter, need;
     int pad[3];
 };
-// contraction tile of the persistent launch (rows per block, 16-column subtiles per wave)
-constexpr int kBatchBM = 128, kBatchNTW = 4;
-// control words before the per-graph done counts: ticket, abort flag, tickets past the end, spare
-constexpr int kBatchCtl = 4;
+// contraction tile of the batch launch (rows per block, 16-column subtiles per wave), and the
+// expansion blocks, group-concentration tiles and 16-row groups of the row update per item
+constexpr int kBatchBM = 64, kBatchNTW = 4;
+constexpr int kBatchExpand = 8, kBatchMtilde = 4, kBatchRowGroups = 8;
+// control words before the per-graph done counts: [0] abort flag (cleared when tcol_step
+// starts), [4] ticket and [5] tickets past the end (cleared before every launch)
+constexpr int kBatchCtl = 8;
 // the row update's values per 16-lane group (8 or 36; 0: k too large)
 int batch_kpl(int kmax);
 // dynamic LDS of the launch (prep_bytes: the class-size block's, prep_lds)
 size_t batch_lds_bytes(int prec, size_t prep_bytes);
 // LDS attribute; resident blocks per CU of the instantiation
 hipError_t batch_prepare(int prec, int kpl, int* blocks_per_cu);
-// nseg segments of `total` tickets; ctl: kBatchCtl + G ints, zero at launch; cancel: a word the
-// host may set (device view of pinned host memory); spin_limit: polls of a wait before it gives up
+// nseg segments of `total` tickets; ctl: kBatchCtl + G ints, words 4.. zero at launch, word 0 the
+// sticky abort flag; cancel: a word the host may set (device view of pinned host memory), read by
+// waits and by every 256th item; spin_limit: polls of a wait before it gives up
 hipError_t launch_batch_run(int prec, int kpl, int grid, size_t lds, const GraphDev* gd, int G, const BatchSeg* segs,
                             int nseg, int total, int* ctl, const int* cancel, int spin_limit, hipStream_t s);
 

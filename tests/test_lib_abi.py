@@ -103,6 +103,8 @@ def test_init_rejects_bad_arguments_without_gpu(lib):
     assert lib.tcol_mtilde(None, 0, None) == -1
     assert lib.tcol_set_t(None, 0, 0) == -1
     assert lib.tcol_reset(None) == -1
+    assert lib.tcol_cancel(None) == -1
+    assert lib.tcol_set_wait_limit(None, 0) == -1
     lib.tcol_destroy(None)
     # the colour-count descent is for colouring problems only (checked before any device work)
     dopt = _lib.DescentOptions(10, 1, 100, 1, 0, 0.01)
@@ -114,7 +116,7 @@ def test_init_rejects_bad_arguments_without_gpu(lib):
 
 
 def test_status_strings(lib):
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert lib.tcol_status_string(code)
     assert b"non-finite" in lib.tcol_status_string(-5)
 
