@@ -75,9 +75,10 @@ def mixed_peak(prec: str, f_as: float, f_pen: float) -> float:
     return (f_as + f_pen) / ideal
 
 
-def measured_traffic(config: dict):
-    """HBM bytes per contraction launch from the committed counter summary, when it was taken
-    on this workload and tiling with the current kernel source; else None."""
+def measured_traffic(config: dict, routes: dict):
+    """HBM bytes per contraction launch from the committed counter summary (each launch form
+    weighted by the timed iterations' penalty routes), when it was taken on this workload and
+    tiling with the current kernel source; else None."""
     import hashlib
     try:
         fields = {}
@@ -91,7 +92,10 @@ def measured_traffic(config: dict):
         for key in ("workload", "tile_bm", "tile_ntw", "penalty", "path", "precision"):
             if fields.get(key) != str(config[key]):
                 return None
-        return float(fields["traffic_bytes_per_launch"])
+        n_d = routes["dense"]
+        n_s = routes["sparse"] + routes["no_penalty"]
+        return (n_d * float(fields["traffic_bytes_dense_launch"]) +
+                n_s * float(fields["traffic_bytes_sparse_launch"])) / (n_d + n_s)
     except (OSError, KeyError, ValueError):
         return None
 
@@ -384,7 +388,7 @@ def main():
               "penalty": PENALTY_NAMES[opts["penalty"]], "fused": opts["fused"]}
     if case.momentum:
         config["momentum"] = case.momentum
-    roof["traffic"] = measured_traffic(config)
+    roof["traffic"] = measured_traffic(config, routes)
     out = {
         "metric": "population-iterations/s (D*steps/s)",
         "value": value,
