@@ -97,7 +97,7 @@ enum { TCOL_FP32 = 0, TCOL_BF16 = 1, TCOL_FP8 = 2, TCOL_FP4 = 3 };
  * rho in {1,2,10,100,200}, alpha 2.5, lambda 1e-5, beta 1.2, mu 1e-6 (GCP) or 0
  * (ECP), nu 0 (GCP) or 1e-5 (ECP)). */
 typedef struct {
-    int32_t problem;        /* TCOL_KCOL, TCOL_ECP, TCOL_KPART, TCOL_BKPART or TCOL_MSCP */
+    int32_t problem;        /* TCOL_KCOL, TCOL_ECP, TCOL_KPART, TCOL_BKPART, TCOL_MSCP or TCOL_MCOL */
     int32_t precision;      /* TCOL_FP32, TCOL_BF16, TCOL_FP8 or TCOL_FP4 */
     int32_t n, k, D;        /* vertices (1..32768), colours (1..4096), members (1..1024) */
     float eta, rho;         /* learning rate > 0; smoothing divisor >= 1 */
