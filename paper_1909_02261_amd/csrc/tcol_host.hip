@@ -328,20 +328,18 @@ static bool sparse_preferred(const tcol_graph_params& p, bool size_floor) {
     return 4LL * p.D <= p.k && (!size_floor || p.n >= kSparseMinN);
 }
 
-// Members per accumulator group PM of the sparse penalty kernel (a multiple of 8, at most
-// D rounded up to 8): the largest whose LDS keeps four 512-thread blocks per CU (40 KB),
-// else three (53 KB), two (80 KB), one (160 KB).  Rows in flight count for more than
-// fewer member groups per row (C5: 8 members per group, four blocks per CU, 3 % faster
-// per step than 16 members and three blocks).  Returns false when not even PM = 8 fits.
+// Members per accumulator group PM of the sparse penalty kernel: 8 (a list entry's colours in
+// the group are one 16-byte word of the vertex-major colours), and the block size whose LDS
+// keeps the most blocks per CU: four 512-thread blocks (40 KB), else three (53 KB), two
+// (80 KB), else one of 1024 threads (160 KB).  Rows in flight count for more than fewer member
+// groups per row.  Returns false when the group's LDS does not fit.
 static bool pick_sparse(int kmax, int dmax, int nmax, int& PM, int& threads) {
-    const int top = round_up(dmax, 8);
     for (size_t budget : {(size_t)40 * 1024, (size_t)53 * 1024, (size_t)80 * 1024, (size_t)160 * 1024})
-        for (int pm = top; pm >= 8; pm -= 8)
-            if (penalty_sparse_lds(pm, kmax, dmax, nmax) <= budget) {
-                PM = pm;
-                threads = budget > 80 * 1024 ? 1024 : 512;
-                return true;
-            }
+        if (penalty_sparse_lds(8, kmax, dmax, nmax) <= budget) {
+            PM = 8;
+            threads = budget > 80 * 1024 ? 1024 : 512;
+            return true;
+        }
     return false;
 }
 
@@ -553,7 +551,8 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 // them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
     if (c->total_ps > 0 && path_of(c) == 2)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, 0, c->ps_lds, 1, 0, 0, s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, 0, 0, c->ps_lds, 1, 0, 0,
+                                     s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
@@ -572,8 +571,8 @@ static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
 // launches it
 static hipError_t enqueue_sparse_add(tcol_ctx* c, bool fitness, hipStream_t s) {
     if (c->total_ps > 0)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_kw, c->ps_lds, 1, 1, 0,
-                                     s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_kw,
+                                     c->update_var & 1, c->ps_lds, 1, 1, 0, s));
     if (fitness) HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFoldSparse | kFlagFlipFused, -1, s));
     return hipSuccess;
 }

@@ -539,11 +539,11 @@ __device__ inline void fuse_row_load(const GraphDev& d, const FuseCtx& f, int dd
 }
 
 // gv: the lane's entries of gS without the added-fitness term (entries past k are ignored)
-template <int KW>
+template <int KW, int ADD>
 __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const FuseCtx& f, int dd, int i, int lane,
                                        const float (&wv)[KW], float (&gv)[KW]) {
     const int k = d.k;
-    if (f.nut != 0.0f) {
+    if (ADD && f.nut != 0.0f) {
         const auto* __restrict__ V = gview(f.V) + (size_t)dd * k + lane;
 #pragma unroll
         for (int q = 0; q < KW; ++q)
@@ -601,7 +601,7 @@ __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const 
 // the row update alone for every member of vertex i (iterations of a pfuse graph whose penalty
 // took the dense pass, or without a penalty): G holds the whole fp32 gradient; each wave takes
 // members wave, wave + NT/64, ... (the launch's blocks per CU keep enough rows in flight)
-template <int NT, int KW>
+template <int NT, int KW, int ADD>
 __device__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -612,11 +612,11 @@ __device__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
         fuse_row_load<KW>(d, f, dd, i, lane, false, wv, gr);
 #pragma unroll
         for (int q = 0; q < KW; ++q) gv[q] = __uint_as_float(gr[q]);
-        fuse_row_update<KW>(d, st, f, dd, i, lane, wv, gv);
+        fuse_row_update<KW, ADD>(d, st, f, dd, i, lane, wv, gv);
     }
 }
 
-template <int NT, int KW>
+template <int NT, int KW, int ADD>
 __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks,
                                                    int honor_stop, int PM, int accumulate, int fit_graphs) {
     extern __shared__ __attribute__((aligned(16))) uint8_t ps_sh[];
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     const bool fuse = KW > 0 && d.pfuse && accumulate;
     if constexpr (KW > 0) {
         if (fuse && !sparse_now) {
-            fuse_update_only<NT, KW>(d, st, b - d.ps_begin);
+            fuse_update_only<NT, KW, ADD>(d, st, b - d.ps_begin);
             return;
         }
     }
@@ -839,8 +839,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
     }
     __syncthreads();
     const int nnz = nzc[0];
-    // 3. members PM at a time; entry e = (list entry e / pm, member e % pm), advanced
-    // by NT per entry
+    // 3. members PM (= 8) at a time
     __attribute__((address_space(1))) float* Gg = (__attribute__((address_space(1))) float*)d.G;
     const double inv = ldexp(1.0, -sc);
     constexpr int KWF = KW > 0 ? KW : 1;
@@ -868,35 +867,34 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
         if ((pm * k) & 1)
             if (tid == 0) acc[pm * k - 1] = 0ull;
         __syncthreads();
-        const int total = nnz * pm;
-        const int sle = NT / pm, sdm = NT - sle * pm;
-        int le = tid / pm, dm = tid - le * pm;
-        // per entry: its colour, and member | table index << 16 (-1: none)
-        int col[B], dv[B];
-        auto fetch = [&](int e0) {
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                dv[u] = -1;
-                if (e0 + u * NT < total) {
-                    const uint32_t ent = list[le];
-                    col[u] = gview(cT)[(size_t)(ent & 0xFFFFu) * cTs + d0 + dm];
-                    dv[u] = dm | (int)((ent >> 16) << 16);
-                }
-                le += sle;
-                dm += sdm;
-                if (dm >= pm) { dm -= pm; ++le; }
+        // one list entry per thread: the colours of its vertex j in the group's (at most eight)
+        // members come in one 16-byte word of the vertex-major colours (rows padded to a multiple
+        // of eight), and each member's accumulator of that colour takes P_ij.  The next entry's
+        // word is loaded before this entry's LDS atomics.
+        const auto* __restrict__ cTg = gview(cT);
+        auto word = [&](int e, u32x4n& w, int& vi) {
+            vi = 0;
+            if (e < nnz) {
+                const uint32_t ent = list[e];
+                w = *(const __attribute__((address_space(1))) u32x4n*)(cTg + (size_t)(ent & 0xFFFFu) * cTs + d0);
+                vi = (int)(ent >> 16);
             }
         };
-        fetch(tid);
-        for (int e0 = tid; e0 < total; e0 += B * NT) {
-            int ccol[B], cdv[B];
+        u32x4n wn = {0u, 0u, 0u, 0u};
+        int vn;
+        word(tid, wn, vn);
+        for (int e = tid; e < nnz; e += NT) {
+            const u32x4n wc = wn;
+            const int vc = vn;
+            word(e + NT, wn, vn);
+            const unsigned long long v = (unsigned long long)tab[vc];
 #pragma unroll
-            for (int u = 0; u < B; ++u) { ccol[u] = col[u]; cdv[u] = dv[u]; }
-            if (e0 + B * NT < total) fetch(e0 + B * NT);
-#pragma unroll
-            for (int u = 0; u < B; ++u)
-                if (cdv[u] >= 0)
-                    atomicAdd(&acc[(cdv[u] & 0xFFFF) * k + ccol[u]], (unsigned long long)tab[cdv[u] >> 16]);
+            for (int h = 0; h < 8; ++h) {
+                if (h < pm) {
+                    const int c = (int)((wc[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
+                    atomicAdd(&acc[h * k + c], v);
+                }
+            }
         }
         // the number of row i's neighbours sharing its colour (the gather of 2 f_color)
         if (accumulate && tid < pm)
@@ -934,7 +932,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
                     const float* __restrict__ pr = pf + wave * k + lane;
 #pragma unroll
                     for (int q = 0; q < KW; ++q) gv[q] = lane + 64 * q < k ? sgn * (float)gr[q] + pr[64 * q] : 0.0f;
-                    fuse_row_update<KW>(d, st, fc, d0 + wave, i, lane, wv, gv);
+                    fuse_row_update<KW, ADD>(d, st, fc, d0 + wave, i, lane, wv, gv);
                 }
                 __syncthreads();
                 continue;
@@ -1832,10 +1830,14 @@ hipError_t launch_prep(const GraphDev* gd, int G, int total_mem, size_t lds, int
 }
 
 // instantiations of the sparse rows: KW = 0 (no row update), or the row update's values per lane
-// (k <= 64 KW) for graphs whose update rides on the launch
+// (k <= 64 KW) for graphs whose update rides on the launch, with (ADD = 1) or without the added
+// fitness term (the equity or colour-cost gradient, whose class-size loads take registers)
 #define TCOL_PS_KERNELS(X) \
-    X(256, 0) X(512, 0) X(1024, 0) X(512, 2) X(512, 3) X(512, 5) X(512, 7) X(512, 9) \
-    X(1024, 2) X(1024, 3) X(1024, 5) X(1024, 7) X(1024, 9)
+    X(256, 0, 0) X(512, 0, 0) X(1024, 0, 0) \
+    X(512, 2, 0) X(512, 3, 0) X(512, 5, 0) X(512, 7, 0) X(512, 9, 0) \
+    X(512, 2, 1) X(512, 3, 1) X(512, 5, 1) X(512, 7, 1) X(512, 9, 1) \
+    X(1024, 2, 0) X(1024, 3, 0) X(1024, 5, 0) X(1024, 7, 0) X(1024, 9, 0) \
+    X(1024, 2, 1) X(1024, 3, 1) X(1024, 5, 1) X(1024, 7, 1) X(1024, 9, 1)
 
 int penalty_sparse_kw(int kmax) {
     for (int kw : {2, 3, 5, 7, 9})
@@ -1844,9 +1846,9 @@ int penalty_sparse_kw(int kmax) {
 }
 
 hipError_t penalty_sparse_prepare() {
-#define TCOL_PS_ATTR(NT, KW)                                                                                 \
+#define TCOL_PS_ATTR(NT, KW, ADD)                                                                            \
     {                                                                                                        \
-        const hipError_t e = hipFuncSetAttribute((const void*)k_pen_sparse<NT, KW>,                          \
+        const hipError_t e = hipFuncSetAttribute((const void*)k_pen_sparse<NT, KW, ADD>,                     \
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);    \
         if (e != hipSuccess) return e;                                                                       \
     }
@@ -1865,17 +1867,19 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
     return (b + 15) / 16 * 16;
 }
 
-hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, size_t lds,
-                                 int honor_stop, int accumulate, int fit_graphs, hipStream_t s) {
+hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, int add,
+                                 size_t lds, int honor_stop, int accumulate, int fit_graphs, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     const int grid = blocks + fit_graphs;
-    if (PM < 8 || (PM & 7) || lds > 160 * 1024) return hipErrorInvalidValue;
+    if (PM != 8 || lds > 160 * 1024) return hipErrorInvalidValue;
     // the fused row update takes one wave per member of a group
     if (kw > 0 && PM > threads / 64) return hipErrorInvalidValue;
     bool done = false;
-#define TCOL_PS_LAUNCH(NT, KW)                                                                              \
-    if (!done && threads == NT && kw == KW) {                                                               \
-        k_pen_sparse<NT, KW><<<grid, NT, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate, fit_graphs);   \
+    if (kw == 0) add = 0;
+#define TCOL_PS_LAUNCH(NT, KW, ADD)                                                                         \
+    if (!done && threads == NT && kw == KW && add == ADD) {                                                 \
+        k_pen_sparse<NT, KW, ADD><<<grid, NT, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate,          \
+                                                        fit_graphs);                                        \
         done = true;                                                                                        \
     }
     TCOL_PS_KERNELS(TCOL_PS_LAUNCH)
