@@ -551,8 +551,7 @@ static hipError_t enqueue_step_plain(tcol_ctx* c, hipStream_t s) {
 // them; the fast path adds them to the contraction's G afterwards (enqueue_sparse_add).
 static hipError_t enqueue_penalty(tcol_ctx* c, hipStream_t s) {
     if (c->total_ps > 0 && path_of(c) == 2)
-        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, 0, 0, c->ps_lds, 1, 0, 0,
-                                     s));
+        HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, 0, 0, c->ps_lds, 1, 0, s));
     HIPRET(launch_mtilde(c->ddesc, c->G, c->total_mt, 1, kFlagGate, -1, nullptr, s));
     return hipSuccess;
 }
@@ -572,7 +571,7 @@ static hipError_t enqueue_prep(tcol_ctx* c, hipStream_t s) {
 static hipError_t enqueue_sparse_add(tcol_ctx* c, bool fitness, hipStream_t s) {
     if (c->total_ps > 0)
         HIPRET(launch_penalty_sparse(c->ddesc, c->G, c->total_ps, c->ps_PM, c->ps_threads, c->ps_kw,
-                                     c->update_var & 1, c->ps_lds, 1, 1, 0, s));
+                                     c->update_var & 1, c->ps_lds, 1, 1, s));
     if (fitness) HIPRET(launch_fitness(c->ddesc, c->G, 1, kFlagFoldSparse | kFlagFlipFused, -1, s));
     return hipSuccess;
 }

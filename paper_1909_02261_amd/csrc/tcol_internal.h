@@ -152,8 +152,6 @@ enum : int {
     kFlagGate = 16,       // group-concentration kernel runs only for graphs on the dense penalty this iteration
     kFlagFused = 32,      // fitness kernel of the fused path: accept the update by flipping buffers
     kFlagPlainPen = 64,   // fitness kernel of the plain path: the penalty took the dense pass
-    kFlagSkipSparse = 128,  // fitness blocks of the sparse-rows launch: leave the graphs whose
-                            // iteration takes the sparse rows to the fitness launch that follows
     kFlagFoldSparse = 256,  // fitness kernel of the fast path: graphs whose iteration took the
                             // sparse rows have their f_color in the rows' slots (f2p)
     kFlagFlipFused = 512,   // fitness kernel of the fast path: graphs whose row update rode on the

@@ -618,19 +618,11 @@ __device__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
 
 template <int NT, int KW, int ADD>
 __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks,
-                                                   int honor_stop, int PM, int accumulate, int fit_graphs) {
+                                                   int honor_stop, int PM, int accumulate) {
     extern __shared__ __attribute__((aligned(16))) uint8_t ps_sh[];
     constexpr int B = KW > 0 ? 2 : kPsBatch;
     const int b = blockIdx.x;
-    if (b >= total_blocks) {
-        // blocks past the rows: the fitness of graph b - total_blocks (its one shared word
-        // in the dynamic LDS: the kernel has no static LDS, so the dynamic size may reach
-        // the full 160 KB), unless (accumulate) this iteration's rows of that graph gather
-        // f_color, when the fitness follows in a launch of its own
-        if (b - total_blocks < fit_graphs)
-            fitness_graph(gd, b - total_blocks, honor_stop, accumulate ? kFlagSkipSparse : 0, (int*)ps_sh);
-        return;
-    }
+    if (b >= total_blocks) return;
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ps_begin; })];
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
@@ -1292,7 +1284,6 @@ __device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_
     GraphState* st = d.st;
     if (honor_stop && st->stopped) return;
     const bool sparse_now = d.psparse && !st->pdense && pen_active(d, st);
-    if ((flags & kFlagSkipSparse) && sparse_now) return;
     const int p = st->pS;
     if (threadIdx.x == 0) best = 0x7FFFFFFF;
     if ((flags & kFlagFoldSparse) && sparse_now) {
@@ -1868,9 +1859,9 @@ size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax) {
 }
 
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, int add,
-                                 size_t lds, int honor_stop, int accumulate, int fit_graphs, hipStream_t s) {
+                                 size_t lds, int honor_stop, int accumulate, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    const int grid = blocks + fit_graphs;
+    const int grid = blocks;
     if (PM != 8 || lds > 160 * 1024) return hipErrorInvalidValue;
     // the fused row update takes one wave per member of a group
     if (kw > 0 && PM > threads / 64) return hipErrorInvalidValue;
@@ -1878,8 +1869,7 @@ hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, 
     if (kw == 0) add = 0;
 #define TCOL_PS_LAUNCH(NT, KW, ADD)                                                                         \
     if (!done && threads == NT && kw == KW && add == ADD) {                                                 \
-        k_pen_sparse<NT, KW, ADD><<<grid, NT, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate,          \
-                                                        fit_graphs);                                        \
+        k_pen_sparse<NT, KW, ADD><<<grid, NT, lds, s>>>(gd, G, blocks, honor_stop, PM, accumulate);         \
         done = true;                                                                                        \
     }
     TCOL_PS_KERNELS(TCOL_PS_LAUNCH)

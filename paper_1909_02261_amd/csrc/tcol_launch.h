@@ -25,13 +25,12 @@ hipError_t penalty_sparse_prepare();
 // time
 size_t penalty_sparse_lds(int PM, int kmax, int dmax, int nmax);
 // accumulate 0: rows written to G before the contraction (epilogue path); 1: added to the
-// contraction's G (fast path).  fit_graphs > 0: the same launch also takes the fitness of
-// graphs 0 .. fit_graphs - 1 (as launch_fitness with flags 0), in blocks after the rows.
+// contraction's G (fast path).
 // kw > 0 (penalty_sparse_kw of the largest k of those graphs; PM at most threads / 64): graphs
 // with pfuse take their row update in this launch as well, in every iteration (accumulate 1);
 // add: some such graph has an added fitness term (equity or colour cost)
 hipError_t launch_penalty_sparse(const GraphDev* gd, int G, int blocks, int PM, int threads, int kw, int add,
-                                 size_t lds, int honor_stop, int accumulate, int fit_graphs, hipStream_t s);
+                                 size_t lds, int honor_stop, int accumulate, hipStream_t s);
 // values per lane of the fused row update for k <= kmax (2, 3, 5, 7 or 9), or -1 past k = 576
 int penalty_sparse_kw(int kmax);
 hipError_t launch_expand(const GraphDev* gd, int G, int total_blocks, int honor_stop, int next, int gate,
