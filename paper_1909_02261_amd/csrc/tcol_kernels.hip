@@ -24,6 +24,37 @@ __device__ inline uint16_t f32_to_bf16_rne(float x) {
 
 __device__ inline bool finite_f(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
 
+// Wave-wide reductions in six DPP steps (a wave whose 64 lanes are all active): xor 1 and 2
+// inside each quad, rotations by 4 and 8 inside each 16-lane row (every lane then holds its
+// row's result), lane 15 of rows 0 and 2 into rows 1 and 3, and lane 31 into rows 2 and 3.
+// Lane 63 ends with the result over all 64 lanes, returned from a scalar register.  Lanes
+// that a step's row mask leaves out combine with the identity.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_from(T ident, T v) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, ident), __builtin_bit_cast(int, v),
+                                                             CTRL, ROWS, 0xF, false));
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T ident, Op op) {
+    static_assert(sizeof(T) == 4, "32-bit lanes");
+    v = op(v, dpp_from<0xB1, 0xF>(ident, v));    // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp_from<0x4E, 0xF>(ident, v));    // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp_from<0x124, 0xF>(ident, v));   // row_ror 4
+    v = op(v, dpp_from<0x128, 0xF>(ident, v));   // row_ror 8
+    v = op(v, dpp_from<0x142, 0xA>(ident, v));   // row_bcast 15 into rows 1 and 3
+    v = op(v, dpp_from<0x143, 0xC>(ident, v));   // row_bcast 31 into rows 2 and 3
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_max(float v) {
+    return wave_reduce(v, -INFINITY, [](float a, float b) { return fmaxf(a, b); });
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    return wave_reduce(v, 0.0f, [](float a, float b) { return a + b; });
+}
+__device__ __forceinline__ int wave_min(int v) {
+    return wave_reduce(v, 0x7FFFFFFF, [](int a, int b) { return min(a, b); });
+}
+
 // 1.0 in each operand format
 __device__ inline uint32_t one_bits(int prec) {
     return prec == kPrecFP32 ? 0x3F800000u : (prec == kPrecBF16 ? 0x3F80u : 0x38u);
@@ -553,48 +584,46 @@ __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const 
 #pragma unroll
     for (int q = 0; q < KW; ++q)
         if (lane + 64 * q < k) mx = fmaxf(mx, wv[q]);
-    for (int s = 32; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+    mx = wave_max(mx);
+    float e[KW];
     float z = 0.0f, qs = 0.0f;
 #pragma unroll
     for (int q = 0; q < KW; ++q) {
-        const float e = (lane + 64 * q < k) ? expf(wv[q] - mx) : 0.0f;
-        z += e;
-        qs += e * gv[q];
+        e[q] = (lane + 64 * q < k) ? expf(wv[q] - mx) : 0.0f;
+        z += e[q];
+        qs += e[q] * gv[q];
     }
-    for (int s = 32; s >= 1; s >>= 1) {
-        z += __shfl_xor(z, s);
-        qs += __shfl_xor(qs, s);
-    }
+    z = wave_sum(z);
+    qs = wave_sum(qs);
     const float rz = 1.0f / z;
     const float rq = qs * rz;
     float* __restrict__ wo = f.Wn + ((size_t)dd * d.n + i) * k + lane;
     float best = -INFINITY;
-    int bi = 0x7FFFFFFF, bad = 0;
+    int bi = 0x7FFFFFFF;
+    bool bad = false;
 #pragma unroll
     for (int q = 0; q < KW; ++q) {
         const int l = lane + 64 * q;
         if (l < k) {
-            const float e = expf(wv[q] - mx);
-            const float step = e * rz * (gv[q] - rq);
+            const float step = e[q] * rz * (gv[q] - rq);
             float nw = wv[q] - f.eta * step;
             if (f.smooth) nw = nw / f.rho;
             wo[64 * q] = nw;
-            if (!finite_f(nw)) bad = 1;
+            if (!finite_f(nw)) bad = true;
             if (nw > best) { best = nw; bi = l; }
         }
     }
-    for (int s = 32; s >= 1; s >>= 1) {
-        const float ob = __shfl_xor(best, s);
-        const int oi = __shfl_xor(bi, s);
-        bad |= __shfl_xor(bad, s);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
+    // the argmax: the largest value, then the lowest colour holding it
+    const float bmax = wave_max(best);
+    const int arg = wave_min(best == bmax ? bi : 0x7FFFFFFF);
+    const bool any_bad = __any(bad);
     if (lane == 0) {
-        if (bad || bi >= k) {
-            bi = 0;
+        int c = arg;
+        if (any_bad || c >= k) {
+            c = 0;
             atomicExch(&st->next_bad, 1);
         }
-        f.cn[(size_t)dd * d.cs + i] = (int16_t)bi;
+        f.cn[(size_t)dd * d.cs + i] = (int16_t)c;
     }
 }
 
