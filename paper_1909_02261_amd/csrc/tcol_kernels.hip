@@ -884,10 +884,15 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
             const size_t o = ((size_t)(d0 + tid) * n + i) * k + ci[d0 + tid];
             own = fuse ? (float)gview((const uint16_t*)d.G)[o] : sgn * Gg[o];
         }
-        for (int e = tid; e < pm * k / 2; e += NT) ((u32x4n*)acc)[e] = u32x4n{0u, 0u, 0u, 0u};
-        if ((pm * k) & 1)
-            if (tid == 0) acc[pm * k - 1] = 0ull;
-        __syncthreads();
+        // the accumulators start at zero: cleared here before the first group (they share their
+        // words with the counts of steps 1-2), and by the fused row updates, which clear each
+        // member's row once they have read it, before the later groups
+        if (!fuse || d0 == 0) {
+            for (int e = tid; e < pm * k / 2; e += NT) ((u32x4n*)acc)[e] = u32x4n{0u, 0u, 0u, 0u};
+            if ((pm * k) & 1)
+                if (tid == 0) acc[pm * k - 1] = 0ull;
+            __syncthreads();
+        }
         // one list entry per thread: the colours of its vertex j in the group's (at most eight)
         // members come in one 16-byte word of the vertex-major colours (rows padded to a multiple
         // of eight), and each member's accumulator of that colour takes P_ij.  The next entry's
@@ -923,36 +928,20 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
         __syncthreads();
         if constexpr (KW > 0) {
             if (fuse) {
-                // the group's sums as FP32 (sgn P.S), in place, U NT entries per pass: every thread
-                // converts its entries of the pass, and after a barrier stores them as floats over
-                // the accumulators (the floats of pass p end at byte 16 U NT (p + 1), where the
-                // 64-bit entries of pass p + 1 begin at twice that)
-                float* pf = (float*)acc;
-                {
-                    constexpr int U = 8;
-                    float v[U];
-                    for (int e0 = 0; e0 < pm * k; e0 += U * NT) {
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int e = e0 + tid + u * NT;
-                            v[u] = e < pm * k ? sgn * (float)((double)(long long)acc[e] * inv) : 0.0f;
-                        }
-                        __syncthreads();
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int e = e0 + tid + u * NT;
-                            if (e < pm * k) pf[e] = v[u];
-                        }
-                    }
-                }
-                __syncthreads();
-                // gS = sgn (A.S + P.S) for row (d0 + wave, i), rounded as the unfused path rounds
-                // the stored G, then the row update
+                // gS = sgn (A.S + P.S) for row (d0 + wave, i): the member's sums to FP32 (sgn P.S)
+                // and added to the A.S counts, rounded as the unfused path rounds the stored G;
+                // the row's accumulators are cleared for the next group; then the row update
                 if (wave < pm) {
                     float gv[KW];
-                    const float* __restrict__ pr = pf + wave * k + lane;
+                    unsigned long long* __restrict__ ar = acc + wave * k + lane;
 #pragma unroll
-                    for (int q = 0; q < KW; ++q) gv[q] = lane + 64 * q < k ? sgn * (float)gr[q] + pr[64 * q] : 0.0f;
+                    for (int q = 0; q < KW; ++q) {
+                        gv[q] = 0.0f;
+                        if (lane + 64 * q < k) {
+                            gv[q] = sgn * (float)gr[q] + sgn * (float)((double)(long long)ar[64 * q] * inv);
+                            ar[64 * q] = 0ull;
+                        }
+                    }
                     fuse_row_update<KW, ADD>(d, st, fc, d0 + wave, i, lane, wv, gv);
                 }
                 __syncthreads();
