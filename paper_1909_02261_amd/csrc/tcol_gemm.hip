@@ -749,26 +749,24 @@ __device__ __forceinline__ void gemm_tile(const GraphDev* __restrict__ gd, int g
                 const int32_t* V = Vp + (size_t)dd * k;
                 float mx = -INFINITY;
                 for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
-                for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+                mx = row16_max(mx);
                 float z = 0.0f, q = 0.0f;
                 for (int l = l16; l < k; l += 16) {
-                    const float e = expf(w[l] - mx);
+                    const float e = exp_soft(w[l] - mx);
                     float gv = sgn * gr[l];
                     if (sparse_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
                     z += e;
                     q += e * gv;
                 }
-                for (int s = 8; s >= 1; s >>= 1) {
-                    z += __shfl_xor(z, s, 16);
-                    q += __shfl_xor(q, s, 16);
-                }
+                z = row16_sum(z);
+                q = row16_sum(q);
                 const float rz = 1.0f / z;
                 const float rq = q * rz;
                 float best = -INFINITY;
                 int bi = 0x7FFFFFFF, bad = 0;
                 for (int l = l16; l < k; l += 16) {
-                    const float e = expf(w[l] - mx) * rz;
+                    const float e = exp_soft(w[l] - mx) * rz;
                     float gv = sgn * gr[l];
                     if (sparse_pen) gv += g1[l];
                     if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, c1, c2);
@@ -778,12 +776,11 @@ __device__ __forceinline__ void gemm_tile(const GraphDev* __restrict__ gd, int g
                     if ((__float_as_uint(nw) & 0x7F800000u) == 0x7F800000u) bad = 1;
                     if (nw > best) { best = nw; bi = l; }
                 }
-                for (int s = 8; s >= 1; s >>= 1) {
-                    const float ob = __shfl_xor(best, s, 16);
-                    const int oi = __shfl_xor(bi, s, 16);
-                    bad |= __shfl_xor(bad, s, 16);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
+                // the argmax over the row: the largest value, then the lowest colour holding it
+                const int bo = f32_ord(best);
+                const int bmax = row16_max_i(bo);
+                bi = row16_min_i(bo == bmax ? bi : 0x7FFFFFFF);
+                bad = row16_max_i(bad);
                 if (l16 == 0) {
                     if (bad || bi >= k) {
                         bi = 0;

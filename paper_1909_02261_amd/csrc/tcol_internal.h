@@ -162,6 +162,74 @@ enum : int {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
 
+// ---- softmax arithmetic of the row updates ----
+// e^x on the hardware base-2 exponential of x log2(e): for the arguments of a softmax (x <= 0,
+// a few tens at most in magnitude) the relative error is below about 2^-21
+__device__ __forceinline__ float exp_soft(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// Lane reductions in DPP steps, over lanes that are all active.  Floats take part as
+// integers of the same order (an involution on the bit patterns of finite values and
+// infinities), so that every step is one integer max or min.
+__device__ __forceinline__ int f32_ord(float x) {
+    const int b = __float_as_int(x);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float f32_from_ord(int o) { return __int_as_float(o ^ ((o >> 31) & 0x7FFFFFFF)); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int ident, int v) {
+    return __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float ident, float v) {
+    return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(ident), __float_as_int(v)));
+}
+// within each 16-lane row: xor 1 and 2 inside each quad, then rotations by 4 and 8; every lane
+// of the row ends with the row's result
+__device__ __forceinline__ int row16_max_i(int v) {
+    constexpr int I = (int)0x80000000;
+    v = max(v, dpp_i<0xB1, 0xF>(I, v));    // quad_perm [1, 0, 3, 2]
+    v = max(v, dpp_i<0x4E, 0xF>(I, v));    // quad_perm [2, 3, 0, 1]
+    v = max(v, dpp_i<0x124, 0xF>(I, v));   // row_ror 4
+    return max(v, dpp_i<0x128, 0xF>(I, v));   // row_ror 8
+}
+__device__ __forceinline__ int row16_min_i(int v) {
+    constexpr int I = 0x7FFFFFFF;
+    v = min(v, dpp_i<0xB1, 0xF>(I, v));
+    v = min(v, dpp_i<0x4E, 0xF>(I, v));
+    v = min(v, dpp_i<0x124, 0xF>(I, v));
+    return min(v, dpp_i<0x128, 0xF>(I, v));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_f<0xB1, 0xF>(0.0f, v);
+    v += dpp_f<0x4E, 0xF>(0.0f, v);
+    v += dpp_f<0x124, 0xF>(0.0f, v);
+    return v + dpp_f<0x128, 0xF>(0.0f, v);
+}
+__device__ __forceinline__ float row16_max(float v) { return f32_from_ord(row16_max_i(f32_ord(v))); }
+// over the 64 lanes: the row results, then lane 15 of rows 0 and 2 into rows 1 and 3 and lane
+// 31 into rows 2 and 3; lane 63 ends with the wave's result, returned from a scalar register
+__device__ __forceinline__ int wave_max_i(int v) {
+    constexpr int I = (int)0x80000000;
+    v = row16_max_i(v);
+    v = max(v, dpp_i<0x142, 0xA>(I, v));   // row_bcast 15 into rows 1 and 3
+    v = max(v, dpp_i<0x143, 0xC>(I, v));   // row_bcast 31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+    constexpr int I = 0x7FFFFFFF;
+    v = row16_min_i(v);
+    v = min(v, dpp_i<0x142, 0xA>(I, v));
+    v = min(v, dpp_i<0x143, 0xC>(I, v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v = row16_sum(v);
+    v += dpp_f<0x142, 0xA>(0.0f, v);
+    v += dpp_f<0x143, 0xC>(0.0f, v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ float wave_max(float v) { return f32_from_ord(wave_max_i(f32_ord(v))); }
+
 // find the graph that owns flattened work item `w` given a begin offset per graph
 template <typename F>
 __device__ inline int find_graph(const GraphDev* gd, int G, int w, F begin_of) {

@@ -24,37 +24,6 @@ __device__ inline uint16_t f32_to_bf16_rne(float x) {
 
 __device__ inline bool finite_f(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
 
-// Wave-wide reductions in six DPP steps (a wave whose 64 lanes are all active): xor 1 and 2
-// inside each quad, rotations by 4 and 8 inside each 16-lane row (every lane then holds its
-// row's result), lane 15 of rows 0 and 2 into rows 1 and 3, and lane 31 into rows 2 and 3.
-// Lane 63 ends with the result over all 64 lanes, returned from a scalar register.  Lanes
-// that a step's row mask leaves out combine with the identity.
-template <int CTRL, int ROWS, typename T>
-__device__ __forceinline__ T dpp_from(T ident, T v) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, ident), __builtin_bit_cast(int, v),
-                                                             CTRL, ROWS, 0xF, false));
-}
-template <typename T, typename Op>
-__device__ __forceinline__ T wave_reduce(T v, T ident, Op op) {
-    static_assert(sizeof(T) == 4, "32-bit lanes");
-    v = op(v, dpp_from<0xB1, 0xF>(ident, v));    // quad_perm [1, 0, 3, 2]
-    v = op(v, dpp_from<0x4E, 0xF>(ident, v));    // quad_perm [2, 3, 0, 1]
-    v = op(v, dpp_from<0x124, 0xF>(ident, v));   // row_ror 4
-    v = op(v, dpp_from<0x128, 0xF>(ident, v));   // row_ror 8
-    v = op(v, dpp_from<0x142, 0xA>(ident, v));   // row_bcast 15 into rows 1 and 3
-    v = op(v, dpp_from<0x143, 0xC>(ident, v));   // row_bcast 31 into rows 2 and 3
-    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-__device__ __forceinline__ float wave_max(float v) {
-    return wave_reduce(v, -INFINITY, [](float a, float b) { return fmaxf(a, b); });
-}
-__device__ __forceinline__ float wave_sum(float v) {
-    return wave_reduce(v, 0.0f, [](float a, float b) { return a + b; });
-}
-__device__ __forceinline__ int wave_min(int v) {
-    return wave_reduce(v, 0x7FFFFFFF, [](int a, int b) { return min(a, b); });
-}
-
 // 1.0 in each operand format
 __device__ inline uint32_t one_bits(int prec) {
     return prec == kPrecFP32 ? 0x3F800000u : (prec == kPrecBF16 ? 0x3F80u : 0x38u);
@@ -589,7 +558,7 @@ __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const 
     float z = 0.0f, qs = 0.0f;
 #pragma unroll
     for (int q = 0; q < KW; ++q) {
-        e[q] = (lane + 64 * q < k) ? expf(wv[q] - mx) : 0.0f;
+        e[q] = (lane + 64 * q < k) ? exp_soft(wv[q] - mx) : 0.0f;
         z += e[q];
         qs += e[q] * gv[q];
     }
@@ -614,8 +583,9 @@ __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const 
         }
     }
     // the argmax: the largest value, then the lowest colour holding it
-    const float bmax = wave_max(best);
-    const int arg = wave_min(best == bmax ? bi : 0x7FFFFFFF);
+    const int bo = f32_ord(best);
+    const int bmax = wave_max_i(bo);
+    const int arg = wave_min_i(bo == bmax ? bi : 0x7FFFFFFF);
     const bool any_bad = __any(bad);
     if (lane == 0) {
         int c = arg;
@@ -1408,24 +1378,22 @@ __global__ __launch_bounds__(256) void k_update(const GraphDev* __restrict__ gd,
     float* vel = d.vel ? d.vel + (size_t)r * k : nullptr;
     float mx = -INFINITY;
     for (int l = l16; l < k; l += 16) mx = fmaxf(mx, w[l]);
-    for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+    mx = row16_max(mx);
     float z = 0.0f, q = 0.0f;
     for (int l = l16; l < k; l += 16) {
-        float e = expf(w[l] - mx);
+        float e = exp_soft(w[l] - mx);
         float gv = gs[l];
         if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, d.c1, d.c2);
         z += e;
         q += e * gv;
     }
-    for (int s = 8; s >= 1; s >>= 1) {
-        z += __shfl_xor(z, s, 16);
-        q += __shfl_xor(q, s, 16);
-    }
+    z = row16_sum(z);
+    q = row16_sum(q);
     const float rz = 1.0f / z;
     const float rr = q * rz;
     const bool smooth = d.nb_iter > 0 && ((t + 1) % d.nb_iter) == 0;
     for (int l = l16; l < k; l += 16) {
-        float e = expf(w[l] - mx) * rz;
+        float e = exp_soft(w[l] - mx) * rz;
         float gv = gs[l];
         if (nut != 0.0f) gv += nut * added_grad(prob, V[l], l, d.c1, d.c2);
         float gw = e * (gv - rr);
@@ -1516,19 +1484,17 @@ __device__ __forceinline__ void update_row(const GraphDev* __restrict__ gd, int 
     float mx = -INFINITY;
 #pragma unroll
     for (int q = 0; q < KPL; ++q) mx = fmaxf(mx, wv[q]);
-    for (int s = 8; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s, 16));
+    mx = row16_max(mx);
     float ev[KPL];
     float z = 0.0f, qs = 0.0f;
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-        ev[q] = (l16 + 16 * q < k) ? expf(wv[q] - mx) : 0.0f;
+        ev[q] = (l16 + 16 * q < k) ? exp_soft(wv[q] - mx) : 0.0f;
         z += ev[q];
         qs += ev[q] * gv[q];
     }
-    for (int s = 8; s >= 1; s >>= 1) {
-        z += __shfl_xor(z, s, 16);
-        qs += __shfl_xor(qs, s, 16);
-    }
+    z = row16_sum(z);
+    qs = row16_sum(qs);
     const float rz = 1.0f / z;
     const float rq = qs * rz;
     if (mode == 1) {
@@ -1563,12 +1529,11 @@ __device__ __forceinline__ void update_row(const GraphDev* __restrict__ gd, int 
             if (nw > best) { best = nw; bi = l; }
         }
     }
-    for (int s = 8; s >= 1; s >>= 1) {
-        const float ob = __shfl_xor(best, s, 16);
-        const int oi = __shfl_xor(bi, s, 16);
-        bad |= __shfl_xor(bad, s, 16);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
+    // the argmax over the row: the largest value, then the lowest colour holding it
+    const int bo = f32_ord(best);
+    const int bmax = row16_max_i(bo);
+    bi = row16_min_i(bo == bmax ? bi : 0x7FFFFFFF);
+    bad = row16_max_i(bad);
     if (l16 == 0) {
         if (bad || bi >= k) {
             bi = 0;
