@@ -228,7 +228,7 @@ __device__ inline int penalty_choice(const GraphDev& d, long long w) {
 // extra blocks of the class-size launch, since both read only the colours)
 // (adv: the launch also ends the previous iteration, so a pending non-finite update counts as
 // a stop)
-__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
+__device__ __forceinline__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
                              int adv);
 
 // end of an iteration for a running graph: t <- t + 1, and a non-finite weight from the
@@ -246,7 +246,7 @@ __device__ inline void advance_graph(GraphState* st) {
 constexpr int kPrepScratch = 288;   // words of the class-size block's LDS scratch
 
 // the class-size kernel's block for member `mem` (flattened over the graphs)
-__device__ void prep_member(const GraphDev* __restrict__ gd, int G, int mem, int honor_stop, int next, int decide,
+__device__ __forceinline__ void prep_member(const GraphDev* __restrict__ gd, int G, int mem, int honor_stop, int next, int decide,
                             int advance_prev) {
     // dynamic LDS (prep_lds): a scratch of kPrepScratch words (the scan's run sums, two
     // four-wave reductions, the ticket result), then the counts and class lists
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_prep(const GraphDev* __restrict__ gd, i
 // [n_pad] u32 overlaid by the group's accumulators [PM][k] i64.
 // the fitness of one graph (the fitness kernel's body; the fast path runs it in extra
 // blocks of the sparse penalty launch, since both follow the contraction)
-__device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best);
+__device__ __forceinline__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best);
 
 __host__ __device__ inline size_t ps_tab_words(int D) { return ((size_t)2 * (D + 1) + 1 + 1) & ~(size_t)1; }
 __host__ __device__ inline size_t ps_int_words(int D) { return ((size_t)D + 1 + 3) & ~(size_t)3; }
@@ -601,7 +601,7 @@ __device__ inline void fuse_row_update(const GraphDev& d, GraphState* st, const 
 // took the dense pass, or without a penalty): G holds the whole fp32 gradient; each wave takes
 // members wave, wave + NT/64, ... (the launch's blocks per CU keep enough rows in flight)
 template <int NT, int KW, int ADD>
-__device__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
+__device__ __forceinline__ void fuse_update_only(const GraphDev& d, GraphState* st, int i) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const FuseCtx f = fuse_ctx(d, st);
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(NT) void k_pen_sparse(const GraphDev* __restrict__ 
 // (fp4: two columns per byte, the lower in the low nibble, 1.0 = 0x2).  For FP8
 // graphs the bf16 copy used by the penalty pass is written as well (the fp4 penalty
 // pass reads the fp4 operand itself).
-__device__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
+__device__ __forceinline__ void expand_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int next, int gate,
                              int adv) {
     const GraphDev& d = gd[find_graph(gd, G, b, [](const GraphDev& x) { return x.ex_begin; })];
     GraphState* st = d.st;
@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(256) void k_expand(const GraphDev* __restrict__ gd,
 constexpr int kMtChunk = 128;   // members per LDS chunk
 
 template <int PT>
-__device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags, int32_t* __restrict__ mt_out,
+__device__ __forceinline__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags, int32_t* __restrict__ mt_out,
                             int16_t (*ci)[64], int16_t (*cj)[64], double (*red)[256]) {
     constexpr int TS = 16 * PT;
     const float tf = (float)st->t;
@@ -1233,7 +1233,7 @@ __device__ void mtilde_tile(const GraphDev& d, GraphState* st, int b, int flags,
 }
 
 // tile b (flattened over the graphs) of the group-concentration kernel; ci, cj, red: its LDS
-__device__ void mtilde_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int flags, int gsel,
+__device__ __forceinline__ void mtilde_block(const GraphDev* __restrict__ gd, int G, int b, int honor_stop, int flags, int gsel,
                              int32_t* __restrict__ mt_out, int16_t (*ci)[64], int16_t (*cj)[64], double (*red)[256]) {
     const int g = find_graph(gd, G, b, [](const GraphDev& x) { return x.mt_begin; });
     const GraphDev& d = gd[g];
@@ -1266,7 +1266,7 @@ __global__ __launch_bounds__(256) void k_mtilde(const GraphDev* __restrict__ gd,
 // the colour cost sum_l (l + 1) #V_l) as the class-size kernel left it; f = main + added;
 // lowest legal member; stop rule.  Clears f2.  With kFlagReport only the fitness
 // arrays are written.
-__device__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best_sh) {
+__device__ __forceinline__ void fitness_graph(const GraphDev* __restrict__ gd, int g, int honor_stop, int flags, int* best_sh) {
     int& best = *best_sh;
     const GraphDev& d = gd[g];
     GraphState* st = d.st;
