@@ -159,7 +159,7 @@ typedef struct {
                                fixed-point sums of the FP32 values, exact for the paper's
                                parameters up to n = 4000, rounded once to FP32);
                                0 = choose (default): the sparse rows in the iterations where the
-                               rows average at most 0.4 n class-mates and the dense pass in the
+                               rows average at most n class-mates and the dense pass in the
                                others (decided on the device each iteration), the dense pass
                                throughout when 4 D > k or n < 2750, the sparse rows throughout
                                for k-partitioning with n >= 2048 (the dense pass below: the

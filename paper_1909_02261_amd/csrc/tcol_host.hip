@@ -314,8 +314,8 @@ static void pick_shapes(tcol_ctx* c) {
 
 // Automatic penalty mode.  A balanced colouring gives each row about D n / k class-mates,
 // and the per-iteration choice takes the sparse rows only while the rows average at most
-// 0.4 n of them: with 4 D > k that is rare (never with 2.5 D > k), so such graphs keep the
-// dense operand pass (and skip the class lists).  Otherwise the choice is made per iteration, and
+// n of them: graphs with 4 D > k start too close to that bound (and from k < D above it), so
+// they keep the dense operand pass (and skip the class lists).  Otherwise the choice is made per iteration, and
 // partitioning, whose rows are dense either way, always takes the sparse rows.  Below a
 // floor on n the dense pass is the faster route anyway: on G(n, .5) with k = n / 14.3
 // the two cost the same at n = 2600-2900 for colouring (D = 16 and 32, fp4 and bf16

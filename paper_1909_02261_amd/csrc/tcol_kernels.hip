@@ -206,14 +206,14 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
 
 // Per-iteration penalty choice of graphs on the sparse rows (ps_mode 2): row i has at
 // most sum_d |class of c_d(i)| nonzeros in P, and over all rows that is
-// w = sum_d sum_l #V_{d,l}^2.  While its average over the rows stays within 0.4 n the
+// w = sum_d sum_l #V_{d,l}^2.  While its average over the rows stays within n the
 // iteration takes the sparse rows; beyond (the population collapsing into a few large
 // classes) the dense pass, whose cost does not depend on the classes.  Partitioning
 // keeps the sparse rows: its operand over D - Mt has nonzeros wherever Mt < D, so its
 // rows are dense anyway and the sparse kernel is the faster on them.  Returns pdense.
 __device__ inline int penalty_choice(const GraphDev& d, long long w) {
-    // 0.4 n: at C5 the step took 0.387 ms against 0.388 (n / 3), 0.389 (n / 4), 0.392 (n / 5)
-    return d.ps_mode == 2 && !prob_partition(d.problem) && w * 5 > (long long)d.n * d.n * 2 ? 1 : 0;
+    // n: at C5 the step took 0.326 ms against 0.334 (0.4 n), 0.324 (1.5 n), 0.330 (2 n), 0.340 (3 n)
+    return d.ps_mode == 2 && !prob_partition(d.problem) && w > (long long)d.n * d.n ? 1 : 0;
 }
 
 // Class sizes #V_{d,l} of member d, its added fitness (equity or colour cost) and

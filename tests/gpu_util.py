@@ -186,7 +186,7 @@ def expected_route(case, opts: dict, t: int, c: np.ndarray) -> str:
     schedule and penalty 1 the dense pass; penalty 2 the sparse rows; penalty 0 and 3 the sparse
     rows for graphs that prefer them (partitioning, or 4 D <= k; with penalty 0 only from
     n = 2048 for partitioning and n = 2750 for colouring) in the iterations whose rows average at
-    most 0.4 n class-mates (sum_d sum_l #V_dl^2 <= 0.4 n^2; partitioning always), else dense."""
+    most n class-mates (sum_d sum_l #V_dl^2 <= n^2; partitioning always), else dense."""
     t32 = np.float32(t)
     if np.float32(case.lam) * t32 == 0 and np.float32(case.mu) * t32 == 0:
         return "none"
@@ -205,7 +205,7 @@ def expected_route(case, opts: dict, t: int, c: np.ndarray) -> str:
     if part:
         return "sparse"
     V = oracle.class_sizes(c, case.k).astype(np.int64)
-    return "dense" if 5 * int((V * V).sum()) > 2 * case.n * case.n else "sparse"
+    return "dense" if int((V * V).sum()) > case.n * case.n else "sparse"
 
 
 def run_resynced(case, steps, check_every=1, t0=0, W=None, check_routes=True, **opts):

@@ -607,7 +607,7 @@ def test_penalty_pass_every_tile_shape(prec):
 @pytest.mark.parametrize("prec", [FP32, FP8, FP4])
 def test_auto_penalty_small_classes(prec):
     """Per-iteration penalty choice without the size floor (penalty 3) on rows that stay
-    sparse (n = 600, k = 60, D = 4: about 40 class-mates per row against 0.4 n = 240), so
+    sparse (n = 600, k = 60, D = 4: about 40 class-mates per row against n = 600), so
     every iteration takes the sparse rows, which are FP32 in every operand mode."""
     case = GraphCase("auto_sparse", KCOL, 600, 60, 4, prec, "gnp", 0.3, graph_seed=61, rho=10.0,
                      lam=1e-2, mu=3e-3, stop_on_legal=0)
