@@ -246,6 +246,8 @@ __device__ inline void advance_graph(GraphState* st) {
 constexpr int kPrepScratch = 288;   // words of the class-size block's LDS scratch
 
 // the class-size kernel's block for member `mem` (flattened over the graphs)
+constexpr int kPrepBatch = 8;   // colours loaded per lane before the class-size atomics use them
+
 __device__ __forceinline__ void prep_member(const GraphDev* __restrict__ gd, int G, int mem, int honor_stop, int next, int decide,
                             int advance_prev) {
     // dynamic LDS (prep_lds): a scratch of kPrepScratch words (the scan's run sums, two
@@ -286,13 +288,23 @@ __device__ __forceinline__ void prep_member(const GraphDev* __restrict__ gd, int
     if (lists)
         for (int l = tid; l < NW * k; l += 256) cw[l] = 0;
     __syncthreads();
+    // the vertex loops load kPrepBatch colours per lane before using any of them (one round
+    // of load latency per batch instead of one per vertex)
     if (lists) {
         const int e = min(n, (wv + 1) * Q);
-        for (int i = wv * Q + lane; i < e; i += 64) {
-            const int16_t x = gview(c)[i];
-            atomicAdd(&cnt[x], 1);
-            atomicAdd(&cw[wv * k + x], 1);
-            cT[(size_t)i * cTs + m] = x;
+        for (int i0 = wv * Q + lane; i0 < e; i0 += 64 * kPrepBatch) {
+            int16_t xs[kPrepBatch];
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) xs[u] = i0 + 64 * u < e ? gview(c)[i0 + 64 * u] : (int16_t)0;
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < e) {
+                    atomicAdd(&cnt[xs[u]], 1);
+                    atomicAdd(&cw[wv * k + xs[u]], 1);
+                    cT[(size_t)i * cTs + m] = xs[u];
+                }
+            }
         }
     } else if (d.cmax > 1) {
         // multicolouring: every selected colour of the vertex counts in its class
@@ -304,10 +316,18 @@ __device__ __forceinline__ void prep_member(const GraphDev* __restrict__ gd, int
             cT[(size_t)i * cTs + m] = gview(c)[i];
         }
     } else {
-        for (int i = tid; i < n; i += 256) {
-            const int16_t x = gview(c)[i];
-            atomicAdd(&cnt[x], 1);
-            cT[(size_t)i * cTs + m] = x;
+        for (int i0 = tid; i0 < n; i0 += 256 * kPrepBatch) {
+            int16_t xs[kPrepBatch];
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) xs[u] = i0 + 256 * u < n ? gview(c)[i0 + 256 * u] : (int16_t)0;
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) {
+                const int i = i0 + 256 * u;
+                if (i < n) {
+                    atomicAdd(&cnt[xs[u]], 1);
+                    cT[(size_t)i * cTs + m] = xs[u];
+                }
+            }
         }
     }
     __syncthreads();
@@ -415,11 +435,20 @@ __device__ __forceinline__ void prep_member(const GraphDev* __restrict__ gd, int
         int* cur = cw + wv * k;
         int2* __restrict__ cinfo = d.cinfo;
         const int qb = wv * Q, qe = min(n, (wv + 1) * Q);
-        for (int i = qb + lane; i < qe; i += 64) {
-            const int x = gview(c)[i];
-            const int pos = atomicAdd(&cur[x], 1);
-            lst[pos] = (int16_t)i;
-            cinfo[(size_t)m * d.cs + i] = make_int2(offl[x], cnt[x]);
+        for (int i0 = qb + lane; i0 < qe; i0 += 64 * kPrepBatch) {
+            int xs[kPrepBatch];
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) xs[u] = i0 + 64 * u < qe ? (int)gview(c)[i0 + 64 * u] : 0;
+#pragma unroll
+            for (int u = 0; u < kPrepBatch; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < qe) {
+                    const int x = xs[u];
+                    const int pos = atomicAdd(&cur[x], 1);
+                    lst[pos] = (int16_t)i;
+                    cinfo[(size_t)m * d.cs + i] = make_int2(offl[x], cnt[x]);
+                }
+            }
         }
     }
     __syncthreads();
