@@ -677,6 +677,38 @@ __device__ __forceinline__ void gemm_tile(const GraphDev* __restrict__ gd, int g
             // the sparse-rows launch takes this iteration's penalty and row update: it reads the
             // A.S counts (integers below n <= 32768) as uint16, half the bytes of fp32
             uint16_t* __restrict__ G16 = (uint16_t*)Gg;
+            if ((k & 7) == 0) {
+                // k a multiple of 8: column tiles start at multiples of 32 and members at multiples
+                // of 8, so every 8-column piece of a tile row lies in one member's row.  The tile
+                // goes through LDS (the stage buffers are free once every wave has read its last
+                // fragments) and leaves in 16-byte stores along the rows, instead of 2-byte
+                // stores that touch four rows at once
+                constexpr int L16 = BN + 8;   // uint16 per LDS row (rows four apart on other banks)
+                static_assert(BM * L16 * 2 <= T::NB * T::STAGE, "count tile fits the stage buffers");
+                uint16_t* T16 = (uint16_t*)lds;
+                __syncthreads();
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = wm * T::RW + mt * 16 + (lane >> 4) * 4 + r;
+                            const int col = wn * (NTW * 16) + nt * 16 + (lane & 15);
+                            T16[row * L16 + col] = (uint16_t)acc[mt][nt][r];
+                        }
+                __syncthreads();
+                constexpr int CPR = BN / 8;   // 16-byte pieces per tile row
+                for (int e = tid; e < BM * CPR; e += T::THREADS) {
+                    const int row = e / CPR, ch = e - row * CPR;
+                    const int i = m0 + row, col = n0 + ch * 8;
+                    if (i < n && col < ncol_end) {
+                        const int dm = col / k, l = col - dm * k;
+                        *(uint4*)(G16 + ((size_t)dm * n + i) * k + l) = *(const uint4*)(T16 + row * L16 + ch * 8);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
