@@ -11,7 +11,7 @@ import pytest
 import oracle
 import tcolgen
 from gpu_util import expected_route, host, make_solver, normwise, orc_params, reference_step, step_route
-from tcolgen import BF16, FP4, FP8, FP32, KCOL, GraphCase
+from tcolgen import BF16, FP4, FP8, FP32
 
 pytestmark = pytest.mark.gpu
 
@@ -92,35 +92,6 @@ def test_batch_launch_equals_fast_schedule(prec, use_graph):
         assert np.array_equal(a[2][g], b[2][g]), cases[g].name
         assert a[3][g] == b[3][g] == 32
         assert np.array_equal(a[4][g], b[4][g])
-
-
-def test_batch_launch_stop_rule():
-    """A graph that reaches a legal colouring stops inside a run while the others keep going:
-    the Mycielski graph M4 (chi = 4) with k = 4 beside two uneven graphs; steps, the legal
-    member, its colouring and every W equal the fast schedule's (stop before the update)."""
-    M = tcolgen.mycielski(4)
-    n = M.shape[0]
-    myc = GraphCase("mycielski4", KCOL, n, 4, 8, BF16, "gnp", 0.5, graph_seed=3, rho=200.0, lam=0.0, mu=0.0,
-                    stop_on_legal=1)
-    others = batch_cases(BF16, 2)
-    cases = [myc] + others
-    As = [M] + [c.adjacency() for c in others]
-    res = []
-    for opts in (dict(fused=3, unroll=8), dict(fused=1, unroll=8, tile_bm=64, tile_ntw=4)):
-        s, _ = make_solver(cases, As=As, **opts)
-        import torch
-        col = torch.zeros(n, dtype=torch.int16, device="cuda")
-        done, legal = s.step(400, colors_out=[col, None, None])
-        res.append((done, legal, [host(w) for w in s.W], host(col), [s.get_t(g) for g in range(3)]))
-        s.close()
-    (d3, l3, W3, c3, t3), (d1, l1, W1, c1, t1) = res
-    assert l3[0] >= 0, "the Mycielski graph did not stop"
-    assert oracle.fcolor(M, c3[None, :])[0] == 0
-    assert l3 == l1 and d3 == d1 and t3 == t1
-    assert t3[0] < t3[1] == t3[2] == 400
-    assert np.array_equal(c3, c1)
-    for g in range(3):
-        assert np.array_equal(W3[g], W1[g])
 
 
 def test_batch_launch_wait_limit_aborts_and_recovers():
