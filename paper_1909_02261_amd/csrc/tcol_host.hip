@@ -473,8 +473,7 @@ static tcol_status rebuild_schedule(tcol_ctx* c) {
         d.mt_ts = L.mt_ts;
         mt += L.mt_tiles;
         d.ex_begin = ex;
-        const long long items = (long long)p.D * p.k * (L.n_pad / 16);
-        d.ex_cblocks = (int)((items + 255) / 256);
+        d.ex_cblocks = expand_blocks(p.D, p.k, L.n_pad);
         ex += d.ex_cblocks;
         d.gm_tm[0] = L.n_pad / c->shape.bm;
         d.gm_tn[0] = ceil_div(p.D * p.k, BN0);
@@ -1510,8 +1509,7 @@ extern "C" tcol_status tcol_conflicts_noalloc(const tcol_graph_params* p, const 
     d.f = (int64_t*)(base + L.f);
     d.st = (GraphState*)(base + L.state);
     const int total_rows = p->D * p->n;
-    const long long items = (long long)p->D * p->k * (L.n_pad / 16);
-    d.ex_cblocks = (int)((items + 255) / 256);
+    d.ex_cblocks = expand_blocks(p->D, p->k, L.n_pad);
     const GemmShape sh{kPrecFP4, L.n_pad >= 2048 ? 128 : 64, L.n_pad >= 2048 ? 6 : 4, 0};
     d.gm_tm[0] = L.n_pad / sh.bm;
     d.gm_tn[0] = ceil_div(d.ncols, gemm_bn(sh.ntw));

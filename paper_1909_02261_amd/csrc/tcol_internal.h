@@ -162,6 +162,14 @@ enum : int {
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
 
+// S^T expansion: colour rows per thread (the member's colours are loaded once for them), and
+// the launch's blocks of 256 threads for a graph
+constexpr int kExpandRows = 4;
+inline int expand_blocks(int D, int k, int n_pad) {
+    const long long items = (long long)D * ((k + kExpandRows - 1) / kExpandRows) * (n_pad / 16);
+    return (int)((items + 255) / 256);
+}
+
 // ---- softmax arithmetic of the row updates ----
 // e^x on the hardware base-2 exponential of x log2(e): for the arguments of a softmax (x <= 0,
 // a few tens at most in magnitude) the relative error is below about 2^-21

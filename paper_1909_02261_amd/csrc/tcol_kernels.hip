@@ -987,27 +987,51 @@ __device__ __forceinline__ void expand_block(const GraphDev* __restrict__ gd, in
     const int p = next ? st->pS ^ 1 : st->pS;
     // the bf16 copy of S feeds only the dense penalty pass of FP8 graphs
     const bool want_sp2 = prec_split(d.precision) && (!gate || !d.psparse || st->pdense);
+    // a thread takes 16 columns of kExpandRows consecutive colour rows of one member: their
+    // colours are loaded once for all of its rows
     const int cgs = d.n_pad / 16;
+    const int kr = (d.k + kExpandRows - 1) / kExpandRows;   // row groups per member
     const long long item = (long long)(b - d.ex_begin) * 256 + threadIdx.x;
-    const int row = (int)(item / cgs);
-    const int cg = (int)(item - (long long)row * cgs);
-    if (row >= d.ncols) return;
-    const int dm = row / d.k;
-    const int l = row - dm * d.k;
+    const long long rg = item / cgs;
+    const int cg = (int)(item - rg * cgs);
+    if (rg >= (long long)d.D * kr) return;
+    const int dm = (int)(rg / kr);
+    const int l0 = (int)(rg - (long long)dm * kr) * kExpandRows;
     const int j0 = cg * 16;
-    uint32_t mask = 0;   // bit q set when column j0+q has colour l (one of its colours: multicolouring)
     const int CM = d.cmax;
+    uint32_t w1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};   // the member's 16 colours (one colour per vertex)
+    if (CM == 1 && j0 < d.n) {
+        // 16 colours in two 16-byte loads (rows are padded to 64 entries)
+        const int16_t* c = d.c[p] + (size_t)dm * d.cs;
+        const uint4 a = *(const uint4*)(c + j0);
+        const uint4 bb = *(const uint4*)(c + j0 + 8);
+        w1[0] = a.x; w1[1] = a.y; w1[2] = a.z; w1[3] = a.w;
+        w1[4] = bb.x; w1[5] = bb.y; w1[6] = bb.z; w1[7] = bb.w;
+    }
+#pragma unroll 1
+    for (int rr = 0; rr < kExpandRows; ++rr) {
+    const int l = l0 + rr;
+    if (l >= d.k) break;
+    const int row = dm * d.k + l;
+    uint32_t mask = 0;   // bit q set when column j0+q has colour l (one of its colours: multicolouring)
     if (j0 < d.n) {
-        for (int sl = 0; sl < CM; ++sl) {
-            const int16_t* c = CM > 1 ? d.sel + ((size_t)dm * CM + sl) * d.cs : d.c[p] + (size_t)dm * d.cs;
-            // 16 colours in two 16-byte loads (rows are padded to 64 entries)
-            const uint4 a = *(const uint4*)(c + j0);
-            const uint4 b = *(const uint4*)(c + j0 + 8);
-            const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        if (CM == 1) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int col = (int)((w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
+                const int col = (int)((w1[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
                 if (j0 + q < d.n && col == l) mask |= 1u << q;
+            }
+        } else {
+            for (int sl = 0; sl < CM; ++sl) {
+                const int16_t* c = d.sel + ((size_t)dm * CM + sl) * d.cs;
+                const uint4 a = *(const uint4*)(c + j0);
+                const uint4 bb = *(const uint4*)(c + j0 + 8);
+                const uint32_t w[8] = {a.x, a.y, a.z, a.w, bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int col = (int)((w[q >> 1] >> (16 * (q & 1))) & 0xFFFFu);
+                    if (j0 + q < d.n && col == l) mask |= 1u << q;
+                }
             }
         }
     }
@@ -1057,6 +1081,7 @@ __device__ __forceinline__ void expand_block(const GraphDev* __restrict__ gd, in
                 if ((mask >> q) & 1) w[q >> 3] |= 0x2u << (4 * (q & 7));
             *(uint2*)((uint8_t*)d.Sop[p] + (off >> 1)) = make_uint2(w[0], w[1]);
         }
+    }
     }
 }
 
