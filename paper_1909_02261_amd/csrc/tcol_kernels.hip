@@ -212,7 +212,8 @@ __global__ __launch_bounds__(256) void k_colors(const GraphDev* __restrict__ gd,
 // keeps the sparse rows: its operand over D - Mt has nonzeros wherever Mt < D, so its
 // rows are dense anyway and the sparse kernel is the faster on them.  Returns pdense.
 __device__ inline int penalty_choice(const GraphDev& d, long long w) {
-    // n: at C5 the step took 0.326 ms against 0.334 (0.4 n), 0.324 (1.5 n), 0.330 (2 n), 0.340 (3 n)
+    // n: on k-colouring of G(4000, .5) with k = 280, D = 32 (fp4) the step took 0.326 ms against
+    // 0.334 (0.4 n), 0.324 (1.5 n), 0.330 (2 n), 0.340 (3 n)
     return d.ps_mode == 2 && !prob_partition(d.problem) && w > (long long)d.n * d.n ? 1 : 0;
 }
 
@@ -645,8 +646,9 @@ __device__ __forceinline__ void fuse_update_only(const GraphDev& d, GraphState* 
 }
 
 // The fused variants with at most five values per lane are held to 64 registers (eight waves per
-// SIMD): with their 35 KB of LDS at C5 that runs four 512-thread blocks per CU instead of three
-// (the step 0.321 -> 0.310 ms; two registers spill in the variant with an added fitness term).
+// SIMD): with their 35 KB of LDS at n = 4000, k = 280, D = 32 that runs four 512-thread blocks per
+// CU instead of three (the step 0.321 -> 0.310 ms there; two registers spill in the variant with
+// an added fitness term).
 template <int NT, int KW, int ADD>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 512 && KW > 0 && KW <= 5 ? 8 : 1))) void
 k_pen_sparse(const GraphDev* __restrict__ gd, int G, int total_blocks, int honor_stop, int PM, int accumulate) {
