@@ -280,8 +280,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the population step on a single MI355X "
-              "(the population would shard over GPUs by members; see DESIGN.md). Use --gpus 1.",
+        print("bench.py measures one GPU: the population step runs on a single MI355X "
+              "(a population would shard over GPUs by members). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
