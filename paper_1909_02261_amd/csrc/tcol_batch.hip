@@ -138,17 +138,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         if (!go) atomicExch(abort_flag, 1);
         // acquire: the writes of the graph's earlier items (other blocks, other XCDs), for
-        // every wave of the block (they share this CU's caches)
+        // every wave of the block (they share this CU's caches).  The fence's cache
+        // invalidation is not counted by the compiler's wait tracking, so the wait for it
+        // is explicit: the other waves load only after the barrier below.
         __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        wait_vm<0>();
         bc[2] = go;
     }
     __syncthreads();
     if (!__builtin_amdgcn_readfirstlane(bc[2])) return;
     batch_item<PREC, BM, NTW, KPL>(gd, G, S, t - S.start);
-    // every wave's stores have completed at the barrier; one release then publishes them
+    // every wave's stores have completed at the barrier; one release then publishes them.
+    // The release writes this XCD's L2 back to memory; the compiler does not count that
+    // write-back among the operations a wait covers and drops the wait after it.  Without
+    // the explicit wait the count can rise while the write-back is still under way, and a
+    // waiting item on another XCD then reads stale weights.
     __syncthreads();
     if (threadIdx.x == 0) {
         __atomic_thread_fence(__ATOMIC_RELEASE);
+        wait_vm<0>();
         __hip_atomic_fetch_add(&done[S.g], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }

@@ -1,8 +1,10 @@
 """The batch launch (tcol_options.fused = 3) against the fast schedule when a graph stops inside
 a run of iterations (Algorithm 1's stop rule per graph).  Kept in a file of its own that is
-collected after the other GPU tests: in one full run of the GPU suite this comparison once found
-one graph's weights differing from the fast schedule's after 400 iterations, while six repeats of
-the same comparison in fresh processes matched bit for bit; the cause has not been found."""
+collected after the other GPU tests.  In one full run of the GPU suite this comparison once found
+one graph's weights differing from the fast schedule's after 400 iterations.  The cause was the
+compiled release sequence: the done count of an item was raised before the L2 write-back of its
+release fence had completed, so an item on another XCD could read stale weights.  An explicit
+wait after each fence of the batch kernel closes that window."""
 import numpy as np
 import pytest
 
