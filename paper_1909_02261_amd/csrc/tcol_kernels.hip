@@ -1506,36 +1506,44 @@ __device__ __forceinline__ void update_row(const GraphDev* __restrict__ gd, int 
     const float gam = d.momentum;
     float* __restrict__ vel = d.vel ? d.vel + (size_t)r * k : nullptr;
     int16_t* __restrict__ cnext = d.c[st->pS] + (size_t)m * d.cs;
-    // every load of the row first (indices clamped into the row instead of branches,
-    // so they are all in flight together), then the arithmetic
+    // every load of the row first (indices clamped into the row inside the last group of
+    // 16 instead of per-lane branches, so they are all in flight together), then the
+    // arithmetic.  Groups of 16 past the row's end are skipped whole: KPL is sized for the
+    // largest k of the launch, and a row of a graph with fewer colours would otherwise
+    // issue every group's loads.
     constexpr bool ADD = (VAR & 1) != 0, MOM = (VAR & 2) != 0;
     float wv[KPL], gv[KPL], vv[MOM ? KPL : 1];
     int32_t cv[ADD ? KPL : 1];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-        const int l = min(l16 + 16 * q, k - 1);
-        wv[q] = gview(w)[l];
-        gv[q] = gview(gs)[l];
+        if (16 * q < k) {
+            const int l = min(l16 + 16 * q, k - 1);
+            wv[q] = gview(w)[l];
+            gv[q] = gview(gs)[l];
+        }
     }
     if constexpr (ADD) {
         if (nut != 0.0f) {
 #pragma unroll
-            for (int q = 0; q < KPL; ++q) cv[q] = gview(V)[min(l16 + 16 * q, k - 1)];
+            for (int q = 0; q < KPL; ++q)
+                if (16 * q < k) cv[q] = gview(V)[min(l16 + 16 * q, k - 1)];
         }
     }
     if constexpr (MOM) {
         if (vel && mode != 1) {
 #pragma unroll
-            for (int q = 0; q < KPL; ++q) vv[q] = gview((const float*)vel)[min(l16 + 16 * q, k - 1)];
+            for (int q = 0; q < KPL; ++q)
+                if (16 * q < k) vv[q] = gview((const float*)vel)[min(l16 + 16 * q, k - 1)];
         }
     }
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         const int l = l16 + 16 * q;
-        if constexpr (ADD) {
-            if (nut != 0.0f) gv[q] += nut * added_grad(prob, cv[q], l, c1, c2);
-        }
-        if (l >= k) {
+        if (l < k) {
+            if constexpr (ADD) {
+                if (nut != 0.0f) gv[q] += nut * added_grad(prob, cv[q], l, c1, c2);
+            }
+        } else {
             wv[q] = -INFINITY;
             gv[q] = 0.0f;
         }
